@@ -1,0 +1,79 @@
+"""Pins of the oracle's density filter (Eqs. 4-5) and OC update (Eqs. 8-9)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import topopt as T
+
+
+def test_filter_brute_force():
+    """H from an O(Ne^2) loop over all element pairs and their centre distances."""
+    nx, ny, nz, r = 4, 3, 2, 1.5
+    H, Hs = T.filter_matrix(nx, ny, nz, r)
+    n = nx * ny * nz
+    Hb = np.zeros((n, n))
+    for e in range(n):
+        ce = (e % nx, (e // nx) % ny, e // (nx * ny))
+        for i in range(n):
+            ci = (i % nx, (i // nx) % ny, i // (nx * ny))
+            d = math.dist(ce, ci)
+            if d <= r:
+                Hb[e, i] = r - d
+    assert np.abs(H.toarray() - Hb).max() < 1e-15
+    assert np.allclose(Hs, Hb.sum(axis=1))
+
+
+def test_filter_weight_sums_closed_form():
+    """r = 1.5: self 1.5, 6 face neighbours 0.5, 12 edge neighbours 1.5 - sqrt 2,
+    corners (sqrt 3 > 1.5) excluded."""
+    H, Hs = T.filter_matrix(5, 5, 5, 1.5)
+    interior = 2 + 5 * (2 + 5 * 2)
+    assert Hs[interior] == pytest.approx(1.5 + 6 * 0.5 + 12 * (1.5 - math.sqrt(2)), rel=1e-15)
+    assert Hs[0] == pytest.approx(1.5 + 3 * 0.5 + 3 * (1.5 - math.sqrt(2)), rel=1e-15)
+    assert H[interior].nnz == 19  # self + 6 faces + 12 edges
+    assert np.abs(H - H.T).max() == 0
+
+
+def test_filter_constant_and_adjoint():
+    nx, ny, nz = 6, 4, 5
+    H, Hs = T.filter_matrix(nx, ny, nz, 1.5)
+    n = nx * ny * nz
+    assert np.allclose(T.density_filter(H, Hs, np.full(n, 0.12)), 0.12, rtol=1e-15)
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    lhs = float(y @ T.density_filter(H, Hs, x))
+    rhs = float(x @ T.density_filter_adjoint(H, Hs, y))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+def test_oc_uniform_closed_form():
+    """Uniform design and sensitivities: every element moves to the same value, so
+    the volume constraint gives x_new = volfrac when within the move limit."""
+    n = 50
+    x = np.full(n, 0.3)
+    dc, dv = np.full(n, -2.0), np.full(n, 1.0 / n)
+    xn, lam, steps = T.oc_update(x, dc, dv, lambda z: z.mean(), volfrac=0.25)
+    assert np.allclose(xn, 0.25, rtol=1e-10)
+    # x B^eta = volfrac  ->  lambda = -dc / dv (x/volfrac)^2
+    assert lam == pytest.approx(2.0 * n * (0.3 / 0.25) ** 2, rel=1e-10)
+    xn, _, _ = T.oc_update(x, dc, dv, lambda z: z.mean(), volfrac=0.01)
+    assert np.allclose(xn, 0.1)  # move limit 0.2
+
+
+def test_oc_volume_and_bounds():
+    nx, ny, nz = 6, 4, 4
+    H, Hs = T.filter_matrix(nx, ny, nz, 1.5)
+    n = nx * ny * nz
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.05, 0.6, n)
+    dc = -rng.uniform(0.1, 3.0, n)
+    dcx = T.density_filter_adjoint(H, Hs, dc)
+    dvx = T.density_filter_adjoint(H, Hs, np.full(n, 1.0 / n))
+    vol = lambda z: T.density_filter(H, Hs, z).mean()  # noqa: E731
+    xn, lam, steps = T.oc_update(x, dcx, dvx, vol, volfrac=0.3)
+    assert abs(vol(xn) - 0.3) < 1e-9
+    assert np.all(xn >= np.maximum(0, x - 0.2) - 1e-15)
+    assert np.all(xn <= np.minimum(1, x + 0.2) + 1e-15)
+    # the filtered volume is linear in x: mean(rho~(z)) = dv_x . z
+    assert vol(xn) == pytest.approx(float(dvx @ xn), rel=1e-13)
