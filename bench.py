@@ -1,0 +1,210 @@
+"""Benchmark of the hex8 SIMP state-solve hot path on one GPU.
+
+One step = one full pass of the hot path on the 128x64x64 random-field
+cantilever (524,288 elements, 1,635,075 DOFs): set the density (moduli on all
+levels, Jacobi diagonals, coarsest inverse), solve K u = f with mixed-precision
+MGPCG to a relative residual of 1e-6, and evaluate compliance and the adjoint
+sensitivity.  Inputs are resident on the GPU before the timed region.
+
+Prints one JSON line.  Besides the step throughput it reports K u throughput
+(binary32 and binary64), the mixed and plain-binary64 solve times, the roofline
+of the dominant kernel (timed with HIP events on its own stream inside the timed
+region) and, on rank 0, the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "K·u GDOF/s + MGPCG solve s to 1e-6 residual, FP32-mixed vs FP64, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def smooth_bytes_per_launch(g) -> float:
+    """Algorithmic HBM bytes of one level-0 Jacobi sweep in binary32:
+    read u, f, omega/D and write u (4 x 4 B per DOF), read E (4 B per element),
+    read the support bits (1 B per node)."""
+    return 16.0 * g.n_dof + 4.0 * g.n_elem + 1.0 * g.n_node
+
+
+def apply_bytes(g, word) -> float:
+    """Algorithmic bytes of y = K u: read u, write y, read E, read support bits."""
+    return 2.0 * word * g.n_dof + word * g.n_elem + 1.0 * g.n_node
+
+
+def time_events(fn, reps, stream):
+    import torch
+
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(name: str):
+    """The FP64 oracle (assembled operators, assembled V-cycle, PCG, sensitivity)
+    on a 64x32x32 sample of the same random-field cantilever recipe."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import fem, multigrid as mg
+
+    g = W.Grid(64, 32, 32)
+    rho = W.random_field_density(g, seed=1, lo=0.01)
+    f = W.cantilever_line_load(g)
+    mask = W.fixed_mask_face_x0(g)
+    t0 = time.perf_counter()
+    h = mg.Hierarchy(64, 32, 32, rho, mask, 4)
+    u, its, rel, _ = mg.mgpcg(h, f, rtol=1e-6)
+    fem.sensitivity(64, 32, 32, rho, u)
+    c = fem.compliance(f, u)
+    dt = time.perf_counter() - t0
+    return {
+        "value": g.n_dof / dt / 1e9,
+        "unit": "GDOF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"64x32x32 random-field cantilever ({g.n_dof} DOFs), 4 levels, rtol 1e-6: "
+                  f"assembly + MGPCG ({its} its) + sensitivity in {dt:.2f} s (scipy sparse, single thread)",
+        "compliance": c,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cantilever_128x64x64_rf")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ku-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2201_12931_amd import hexmg
+
+    g, rho, f, mask, spec = W.workload(args.workload)
+    levels, rtol = spec["levels"], spec["rtol"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rho_d = torch.from_numpy(rho).to(dev)
+    f_d = torch.from_numpy(np.ascontiguousarray(f)).to(dev)
+    u_d = torch.zeros_like(f_d)
+    dc_d = torch.empty(g.n_elem, dtype=torch.float64, device=dev)
+
+    mixed = hexmg.Grid(g.nx, g.ny, g.nz, levels, precision=hexmg.MIXED)
+    fp64 = hexmg.Grid(g.nx, g.ny, g.nz, levels, precision=hexmg.FP64)
+
+    def step(grid):
+        grid.set_density(rho_d)
+        code, info = grid.solve(f_d, u_d, rtol=rtol, maxit=500)
+        c = grid.compliance_sensitivity(f_d, u_d, dc_d)
+        return code, info[0], c[0]
+
+    for _ in range(args.warmup):
+        step(mixed)
+    torch.cuda.synchronize()
+    mixed.profile_enable(True)
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(step(mixed))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_smooth, ms_smooth = mixed.profile_query("smooth_f32")
+    n_res, ms_res = mixed.profile_query("residual_f32")
+    n_app, ms_app = mixed.profile_query("apply_f64")
+    mixed.profile_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    code, info_mixed, c_mixed = infos[-1]
+
+    # plain binary64 form of the same step
+    step(fp64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    code64, info64, c64 = step(fp64)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+
+    # K u throughput (level 0) in both precisions
+    u32 = torch.randn(g.n_dof, dtype=torch.float32, device=dev)
+    y32 = torch.empty_like(u32)
+    u64 = u32.double()
+    y64 = torch.empty_like(u64)
+    mixed.apply_K(u32, y32)
+    mixed.apply_K(u64, y64)
+    ms32 = time_events(lambda: mixed.apply_K(u32, y32), args.ku_reps, stream)
+    ms64 = time_events(lambda: mixed.apply_K(u64, y64), args.ku_reps, stream)
+
+    avg_smooth_ms = ms_smooth / max(n_smooth, 1)
+    sb = smooth_bytes_per_launch(g)
+    achieved = sb / (avg_smooth_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": g.n_dof / (ms_per_step * 1e-3) / 1e9,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-mixed(f64 CG)",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "grid": [g.nx, g.ny, g.nz],
+            "elements": g.n_elem,
+            "dofs": g.n_dof,
+            "levels": levels,
+            "rtol": rtol,
+            "step": "set_density + mixed MGPCG to rtol + compliance/sensitivity",
+        },
+        "ku_gdofs": {"f32": g.n_dof / (ms32 * 1e-3) / 1e9, "f64": g.n_dof / (ms64 * 1e-3) / 1e9},
+        "ku_ms": {"f32": ms32, "f64": ms64},
+        "ku_hbm_frac": {"f32": apply_bytes(g, 4) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "f64": apply_bytes(g, 8) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "solve_s": {"mixed": info_mixed["ms_solve"] * 1e-3, "fp64": info64["ms_solve"] * 1e-3},
+        "step_s": {"mixed": ms_per_step * 1e-3, "fp64": t3 - t2},
+        "iterations": {"mixed": info_mixed["iterations"], "fp64": info64["iterations"]},
+        "rel_res_true": {"mixed": info_mixed["rel_res_true"], "fp64": info64["rel_res_true"]},
+        "compliance": {"mixed": c_mixed, "fp64": c64, "rel_diff": abs(c_mixed - c64) / abs(c64)},
+        "kernel_ms": {"smooth_f32": [n_smooth, ms_smooth], "residual_f32": [n_res, ms_res],
+                      "apply_f64": [n_app, ms_app]},
+        "roofline": {
+            "kernel": "k_gather<float, smooth> (level-0 damped Jacobi sweep)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_smooth_ms,
+            "bytes_per_launch": sb,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

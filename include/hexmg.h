@@ -1,0 +1,167 @@
+/*
+ * hexmg -- matrix-free multigrid-preconditioned CG for the SIMP linear-elastic
+ * state equation K(rho) u = f on structured hex8 grids, for AMD gfx950.
+ *
+ * The library is the black-box state solver of the paper's framework (Sec. 4.2:
+ * a solver for K u = f on a Cartesian grid of 8-node bricks, given the grid, the
+ * load and the supports), plus the compliance and adjoint sensitivity that feed
+ * each optimality-criteria update (Sec. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: nx*ny*nz unit cubes.  Element e = i + nx*(j + ny*k); node
+ * n = i + (nx+1)*(j + (ny+1)*k); DOF 3*n + c (c = 0,1,2 for x,y,z).
+ * A vector of N = 3*(nx+1)*(ny+1)*(nz+1) entries is contiguous; nrhs vectors are
+ * stored back to back ([nrhs][N]).  Local element node a = ax + 2*ay + 4*az.
+ *
+ * Material: E(rho) = Emin + rho^p (E0 - Emin) (Eq. 2, reading K_min = Emin*K0);
+ * the element stiffness is E(rho_e) K0 with K0 the isotropic hex8 stiffness of
+ * unit modulus and Poisson ratio nu.
+ *
+ * Supports: per-node uint8 mask, bit c set = DOF 3n+c fixed (u = 0).  The
+ * operator applied everywhere is A = M K M + (I - M), M = diag(free).
+ *
+ * Memory: all array arguments are DEVICE pointers unless marked "host".  The
+ * caller owns every pointer, including the workspace given to
+ * hexmg_grid_create; the library never frees caller memory and allocates no
+ * device memory of its own.  Calls are asynchronous on the given stream (a
+ * hipStream_t passed as void*; NULL = the null stream) except where a host
+ * output is written, in which case the call synchronises that stream.
+ *
+ * Status codes: 0 = OK, 1 = not converged (outputs valid), negative = error;
+ * hexmg_last_error() returns a message for the last non-zero status of the
+ * calling thread.
+ */
+#ifndef HEXMG_H
+#define HEXMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HEXMG_OK 0
+#define HEXMG_NOT_CONVERGED 1
+#define HEXMG_ERR_INVALID (-1)
+#define HEXMG_ERR_WORKSPACE (-2)
+#define HEXMG_ERR_DEVICE (-3)
+#define HEXMG_ERR_NONFINITE (-4)
+#define HEXMG_ERR_BREAKDOWN (-5)
+
+/* precision of the solver (hexmg_grid_desc.precision) */
+#define HEXMG_FP64 0  /* every step in binary64 */
+#define HEXMG_MIXED 1 /* V-cycle in binary32; CG vectors, dots, outer K p and coarsest solve in binary64 */
+
+/* element type of vectors passed to hexmg_apply_K / hexmg_vcycle */
+#define HEXMG_F64 0
+#define HEXMG_F32 1
+
+/* coarse-level modulus (hexmg_grid_desc.coarse_avg) */
+#define HEXMG_AVG_DENSITY 0 /* coarse rho = mean of the 8 children, then E(rho) (Sec. 4.2.2) */
+#define HEXMG_AVG_MODULUS 1 /* coarse E = mean of the 8 children's E */
+
+typedef struct hexmg_grid *hexmg_grid_t;
+
+typedef struct {
+  int nx, ny, nz;       /* elements per axis; each divisible by 2^(levels-1) */
+  int levels;           /* multigrid levels, >= 1; level 0 is the given grid */
+  double E0, Emin, nu, penal; /* 1, 1e-9, 0.3, 3 in the paper's examples */
+  int precision;        /* HEXMG_FP64 | HEXMG_MIXED */
+  int smooth_sweeps;    /* damped-Jacobi sweeps before and after the coarse correction */
+  double omega;         /* Jacobi damping, 0 < omega <= 1 */
+  int coarse_avg;       /* HEXMG_AVG_DENSITY | HEXMG_AVG_MODULUS */
+  int max_nrhs;         /* most right-hand sides per call (sizes the workspace) */
+  const uint8_t *fixed_mask; /* device, (nx+1)(ny+1)(nz+1) bytes; NULL = face x = 0 fixed.
+                                Copied at hexmg_grid_create; coarse masks are injected
+                                (coarse node fixed iff the coincident fine node is). */
+} hexmg_grid_desc;
+
+/* Fill *desc with the defaults (E0 1, Emin 1e-9, nu 0.3, penal 3, FP64, 2 sweeps,
+ * omega 0.6, density averaging, max_nrhs 1, fixed face x = 0) for the given
+ * grid.  Host only. */
+int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc *desc);
+
+/* Bytes of device workspace hexmg_grid_create needs for *desc (host only). */
+int hexmg_workspace_size(const hexmg_grid_desc *desc, size_t *bytes);
+
+/* Build a grid object on caller workspace (device, >= hexmg_workspace_size
+ * bytes, 256-byte aligned).  The workspace must stay valid until
+ * hexmg_grid_destroy.  Errors: -1 bad descriptor, -2 workspace too small. */
+int hexmg_grid_create(const hexmg_grid_desc *desc, void *workspace, size_t bytes,
+                      void *stream, hexmg_grid_t *out);
+
+/* Release host-side state (the workspace stays the caller's). */
+int hexmg_grid_destroy(hexmg_grid_t grid);
+
+/* S1-S3 of the hot path for one density field rho (device, nx*ny*nz doubles,
+ * element order): SIMP moduli on every level (Eq. 2; coarse densities by
+ * homogenization, Sec. 4.2.2, coarse element of side 2^l has stiffness
+ * 2^l E K0), the Jacobi diagonal of every level (Eq. 20), and the exact
+ * inverse of the coarsest operator (Alg. 3 solves the coarsest grid directly).
+ * rho is copied.  Returns -4 if rho holds a non-finite value or lies outside
+ * [0,1] (checked on the device; this call then synchronises the stream). */
+int hexmg_set_density(hexmg_grid_t grid, const double *rho, void *stream);
+
+/* y = A_l u on level `level` (0 = finest) with the level's moduli: the
+ * matrix-free element-by-element product of Sec. 4.2.1.  dtype HEXMG_F64 or
+ * HEXMG_F32 selects the element type of u and y; nrhs vectors.  u and y must
+ * not overlap. */
+int hexmg_apply_K(hexmg_grid_t grid, int level, int dtype, const void *u, void *y,
+                  int nrhs, void *stream);
+
+/* z = V(r): one multigrid V-cycle (Alg. 3) on the finest level from a zero
+ * initial guess, damped-Jacobi smoothing (Eq. 21), trilinear prolongation P,
+ * restriction P^T, direct coarsest solve.  dtype HEXMG_F64 runs every level in
+ * binary64, HEXMG_F32 in binary32 (coarsest solve in binary64 either way). */
+int hexmg_vcycle(hexmg_grid_t grid, int dtype, const void *r, void *z, int nrhs,
+                 void *stream);
+
+typedef struct {
+  int iterations;           /* PCG iterations taken */
+  int status;               /* 0 converged, 1 not converged, -5 breakdown */
+  double rel_res_recursive; /* ||r_k|| / ||M f|| of the CG recurrence */
+  double rel_res_true;      /* ||M f - A u|| / ||M f|| recomputed in binary64 */
+  double compliance;        /* f^T u */
+  float ms_solve;           /* device time of the solve (stream events) */
+} hexmg_solve_info;
+
+/* S10: MGPCG (Alg. 1, preconditioned by hexmg_vcycle in the grid's precision)
+ * for A u = M f from u0 = 0, stopping when ||r_k||_2 <= rtol ||M f||_2 or after
+ * maxit iterations; rtol <= 0 runs exactly maxit iterations.  f, u: device,
+ * [nrhs][N] doubles.  info: host array of nrhs entries (may be NULL).
+ * Synchronises the stream.  Returns 1 if some right-hand side did not
+ * converge, -5 on breakdown (p^T A p <= 0). */
+int hexmg_solve(hexmg_grid_t grid, const double *f, double *u, int nrhs, double rtol,
+                int maxit, hexmg_solve_info *info, void *stream);
+
+/* S11-S12: compliance c_r = f_r^T u_r (Eq. 6) per right-hand side into
+ * c_host (host, nrhs doubles, may be NULL) and the adjoint sensitivity (Eq. 7,
+ * u* = u)  dc_e = -p rho_e^(p-1) (E0 - Emin) sum_r w_r u_{r,e}^T K0 u_{r,e}
+ * into dc (device, nx*ny*nz doubles, may be NULL), with weights w (host, nrhs
+ * doubles; NULL = all 1).  Uses the density of the last hexmg_set_density. */
+int hexmg_compliance_sensitivity(hexmg_grid_t grid, const double *f, const double *u,
+                                 int nrhs, const double *weights_host, double *c_host,
+                                 double *dc, void *stream);
+
+/* The library's unit element stiffness K0 (24x24, row-major, local DOF 3a+c)
+ * for Poisson ratio nu, written to Ke_host.  Host only; needs no GPU. */
+int hexmg_element_matrix(double nu, double *Ke_host);
+
+/* Per-kernel device timing with stream events (off by default).  While
+ * enabled, every finest-level launch of the named kernel family is bracketed
+ * by events on its stream; hexmg_profile_query returns the number of launches and their
+ * total milliseconds since the last reset (synchronises the grid's last
+ * stream).  Families: "apply_f64", "apply_f32", "smooth_f64", "smooth_f32",
+ * "residual_f64", "residual_f32". */
+int hexmg_profile_enable(hexmg_grid_t grid, int enable);
+int hexmg_profile_query(hexmg_grid_t grid, const char *family, int *launches, double *ms);
+
+/* Message for the calling thread's last non-zero status ("" if none). */
+const char *hexmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEXMG_H */

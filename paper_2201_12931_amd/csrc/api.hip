@@ -1,0 +1,591 @@
+// C ABI of the hexmg library: grid set-up, K u, V-cycle, MGPCG solve,
+// compliance and sensitivity.  Host orchestration only; all arithmetic of the
+// hot path runs in the kernels of kernels.hip.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "hexmg_impl.h"
+
+using namespace hexmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(x)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess) return fail(HEXMG_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+const char* kFamilies[] = {"apply_f64", "apply_f32", "smooth_f64", "smooth_f32", "residual_f64",
+                           "residual_f32"};
+constexpr int kNumFamilies = 6;
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+int validate(const hexmg_grid_desc* d) {
+  if (!d) return fail(HEXMG_ERR_INVALID, "null descriptor");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(HEXMG_ERR_INVALID, "grid dimensions must be >= 1");
+  if (d->levels < 1 || d->levels > 12) return fail(HEXMG_ERR_INVALID, "levels must be in [1, 12]");
+  const int q = 1 << (d->levels - 1);
+  if (d->nx % q || d->ny % q || d->nz % q)
+    return fail(HEXMG_ERR_INVALID, "grid dimensions must be divisible by 2^(levels-1)");
+  const long long nn = (long long)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+  if (3 * nn >= (1ll << 31)) return fail(HEXMG_ERR_INVALID, "grid too large (3*nodes must be < 2^31)");
+  const long long nnc = (long long)(d->nx / q + 1) * (d->ny / q + 1) * (d->nz / q + 1);
+  if (3 * nnc > 6144) return fail(HEXMG_ERR_INVALID, "coarsest level too large for the dense solve (> 6144 DOFs); add levels");
+  if (!(d->Emin > 0.0) || !(d->E0 > d->Emin) || !std::isfinite(d->E0))
+    return fail(HEXMG_ERR_INVALID, "need 0 < Emin < E0 < inf");
+  if (!(d->nu > -1.0 && d->nu < 0.5)) return fail(HEXMG_ERR_INVALID, "need -1 < nu < 0.5");
+  if (!(d->penal >= 1.0 && d->penal <= 16.0)) return fail(HEXMG_ERR_INVALID, "need 1 <= penal <= 16");
+  if (d->precision != HEXMG_FP64 && d->precision != HEXMG_MIXED) return fail(HEXMG_ERR_INVALID, "bad precision");
+  if (d->smooth_sweeps < 1 || d->smooth_sweeps > 64) return fail(HEXMG_ERR_INVALID, "smooth_sweeps in [1,64]");
+  if (!(d->omega > 0.0 && d->omega <= 1.0)) return fail(HEXMG_ERR_INVALID, "need 0 < omega <= 1");
+  if (d->coarse_avg != HEXMG_AVG_DENSITY && d->coarse_avg != HEXMG_AVG_MODULUS)
+    return fail(HEXMG_ERR_INVALID, "bad coarse_avg");
+  if (d->max_nrhs < 1) return fail(HEXMG_ERR_INVALID, "max_nrhs must be >= 1");
+  return 0;
+}
+
+void make_levels(const hexmg_grid_desc* d, std::vector<Level>& lv) {
+  lv.clear();
+  for (int l = 0; l < d->levels; ++l) {
+    Level L;
+    L.nx = d->nx >> l;
+    L.ny = d->ny >> l;
+    L.nz = d->nz >> l;
+    L.nxn = L.nx + 1;
+    L.nyn = L.ny + 1;
+    L.nzn = L.nz + 1;
+    L.nn = L.nxn * L.nyn * L.nzn;
+    L.ne = L.nx * L.ny * L.nz;
+    L.mask = nullptr;
+    lv.push_back(L);
+  }
+}
+
+// One layout function serves hexmg_workspace_size (base = nullptr) and
+// hexmg_grid_create.
+size_t carve(hexmg_grid* g, char* base) {
+  Carver c{base};
+  const int L = g->L;
+  g->rho.assign(L, nullptr);
+  g->E64.assign(L, nullptr);
+  g->E32.assign(L, nullptr);
+  g->wd64.assign(L, nullptr);
+  g->wd32.assign(L, nullptr);
+  g->mask.assign(L, nullptr);
+  g->vf64.assign(L, nullptr);
+  g->vu64.assign(L, nullptr);
+  g->vt64.assign(L, nullptr);
+  g->vr64.assign(L, nullptr);
+  g->vf32.assign(L, nullptr);
+  g->vu32.assign(L, nullptr);
+  g->vt32.assign(L, nullptr);
+  g->vr32.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) {
+    const Level& lv = g->lv[l];
+    const size_t N = 3ull * lv.nn;
+    g->rho[l] = c.take<double>(lv.ne);
+    g->E64[l] = c.take<double>(lv.ne);
+    g->E32[l] = c.take<float>(lv.ne);
+    g->wd64[l] = c.take<double>(N);
+    g->wd32[l] = c.take<float>(N);
+    g->mask[l] = c.take<uint8_t>(lv.nn);
+    g->vf64[l] = c.take<double>(N);
+    g->vu64[l] = c.take<double>(N);
+    g->vt64[l] = c.take<double>(N);
+    g->vr64[l] = c.take<double>(N);
+    g->vf32[l] = c.take<float>(N);
+    g->vu32[l] = c.take<float>(N);
+    g->vt32[l] = c.take<float>(N);
+    g->vr32[l] = c.take<float>(N);
+  }
+  const size_t nc = 3ull * g->lv[L - 1].nn;
+  g->nc = (int)nc;
+  g->Abuf[0] = c.take<double>(nc * nc);
+  g->Abuf[1] = c.take<double>(nc * nc);
+  g->Ke64 = c.take<double>(576);
+  g->Ke32 = c.take<float>(576);
+  const size_t N0 = 3ull * g->lv[0].nn;
+  g->r = c.take<double>(N0);
+  g->z = c.take<double>(N0);
+  g->p = c.take<double>(N0);
+  g->q = c.take<double>(N0);
+  g->partials = c.take<double>(kReduceBlocks);
+  g->scalars = c.take<double>(kScalars);
+  g->flags = c.take<int>(kReduceBlocks + 1);
+  return c.off + 256;
+}
+
+// ---- profiling ------------------------------------------------------------
+int family_of(int mode, bool f32) {
+  return 2 * mode + (f32 ? 1 : 0);  // apply 0/1, smooth 2/3, residual 4/5
+}
+
+hipEvent_t take_event(hexmg_grid* g) {
+  if (!g->event_pool.empty()) {
+    hipEvent_t e = g->event_pool.back();
+    g->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <typename T>
+void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
+  const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
+  hipEvent_t a = nullptr, b = nullptr;
+  const bool prof = g->profile && level == 0;
+  if (prof) {
+    a = take_event(g);
+    b = take_event(g);
+    if (a && b) hipEventRecord(a, s);
+  }
+  launch_gather<T>(mode, g->lv[level], Ke, E, u, f, wd, y, s);
+  if (prof && a && b) {
+    hipEventRecord(b, s);
+    g->recs.push_back({family_of(mode, f32), a, b});
+  }
+}
+
+void drain_profile(hexmg_grid* g) {
+  for (auto& r : g->recs) {
+    float ms = 0.f;
+    hipEventSynchronize(r.b);
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g->prof_ms[r.family] += ms;
+      g->prof_count[r.family] += 1;
+    }
+    g->event_pool.push_back(r.a);
+    g->event_pool.push_back(r.b);
+  }
+  g->recs.clear();
+}
+
+// ---- V-cycle (Alg. 3) -----------------------------------------------------
+template <typename T>
+struct VView {
+  std::vector<T*> f, u, t, r;
+  std::vector<const T*> wd;
+};
+
+VView<double> view64(hexmg_grid* g) {
+  VView<double> v{g->vf64, g->vu64, g->vt64, g->vr64, {}};
+  for (auto p : g->wd64) v.wd.push_back(p);
+  return v;
+}
+VView<float> view32(hexmg_grid* g) {
+  VView<float> v{g->vf32, g->vu32, g->vt32, g->vr32, {}};
+  for (auto p : g->wd32) v.wd.push_back(p);
+  return v;
+}
+
+// out = V_l(f) from a zero initial guess.  The first sweep writes the level's
+// scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
+// in `out` without a copy.  f and out must not overlap.
+template <typename T>
+void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, hipStream_t s) {
+  const Level& L = g->lv[l];
+  if (l == g->L - 1) {
+    launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, s);
+    return;
+  }
+  const long long N = 3ll * L.nn;
+  const int nu = g->desc.smooth_sweeps;
+  T* buf[2] = {v.t[l], out};
+  int cur = 0;
+  launch_jacobi_first<T>(N, v.wd[l], f, buf[0], s);
+  for (int it = 1; it < nu; ++it) {
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], s);
+    cur = 1 - cur;
+  }
+  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], s);
+  launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], s);
+  vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], s);
+  launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], s);
+  for (int it = 0; it < nu; ++it) {
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], s);
+    cur = 1 - cur;
+  }
+}
+
+// z = V(r) in the grid's precision for one binary64 right-hand side.
+void precondition(hexmg_grid* g, const double* r, double* z, hipStream_t s) {
+  const long long N = 3ll * g->lv[0].nn;
+  if (g->desc.precision == HEXMG_FP64) {
+    VView<double> v = view64(g);
+    vcycle_level<double>(g, v, 0, r, z, s);
+  } else {
+    VView<float> v = view32(g);
+    launch_f64_to_f32(N, r, g->vf32[0], s);
+    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], s);
+    launch_f32_to_f64(N, g->vu32[0], z, s);
+  }
+}
+
+void dot(hexmg_grid* g, long long n, const double* x, const double* y, double* out, hipStream_t s) {
+  launch_dot_partial(n, x, y, g->partials, s);
+  launch_reduce_final(g->partials, out, s);
+}
+
+int read_scalars(hexmg_grid* g, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(g->host_scalars, g->scalars, kScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc* d) {
+  if (!d) return fail(HEXMG_ERR_INVALID, "null descriptor");
+  std::memset(d, 0, sizeof(*d));
+  d->nx = nx;
+  d->ny = ny;
+  d->nz = nz;
+  d->levels = levels;
+  d->E0 = 1.0;
+  d->Emin = 1e-9;
+  d->nu = 0.3;
+  d->penal = 3.0;
+  d->precision = HEXMG_FP64;
+  d->smooth_sweeps = 2;
+  d->omega = 0.6;
+  d->coarse_avg = HEXMG_AVG_DENSITY;
+  d->max_nrhs = 1;
+  d->fixed_mask = nullptr;
+  return 0;
+}
+
+int hexmg_workspace_size(const hexmg_grid_desc* d, size_t* bytes) {
+  if (int e = validate(d)) return e;
+  if (!bytes) return fail(HEXMG_ERR_INVALID, "null bytes");
+  hexmg_grid g;
+  g.desc = *d;
+  g.L = d->levels;
+  make_levels(d, g.lv);
+  *bytes = carve(&g, nullptr);
+  return 0;
+}
+
+int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, void* stream,
+                      hexmg_grid_t* out) {
+  if (int e = validate(d)) return e;
+  if (!workspace || !out) return fail(HEXMG_ERR_INVALID, "null workspace or output");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(HEXMG_ERR_INVALID, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  hexmg_workspace_size(d, &need);
+  if (bytes < need) return fail(HEXMG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  hexmg_grid* g = new hexmg_grid();
+  g->desc = *d;
+  g->L = d->levels;
+  make_levels(d, g->lv);
+  carve(g, static_cast<char*>(workspace));
+  for (int l = 0; l < g->L; ++l) g->lv[l].mask = g->mask[l];
+  g->density_set = false;
+  g->profile = false;
+  g->Ainv = g->Abuf[0];
+  g->last_stream = s;
+  for (int i = 0; i < 8; ++i) {
+    g->prof_ms[i] = 0.0;
+    g->prof_count[i] = 0;
+  }
+  g->host_scalars = nullptr;
+  auto cleanup = [&](int code) {
+    if (g->host_scalars) (void)hipHostFree(g->host_scalars);
+    delete g;
+    return code;
+  };
+  if (hipHostMalloc((void**)&g->host_scalars, 2 * kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(HEXMG_ERR_DEVICE, "pinned host allocation failed"));
+  double Ke[576];
+  float Kf[576];
+  element_matrix(d->nu, Ke);
+  for (int i = 0; i < 576; ++i) Kf[i] = (float)Ke[i];
+  if (hipMemcpyAsync(g->Ke64, Ke, sizeof(Ke), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(g->Ke32, Kf, sizeof(Kf), hipMemcpyHostToDevice, s) != hipSuccess)
+    return cleanup(fail(HEXMG_ERR_DEVICE, "copy of the element matrix failed"));
+  if (d->fixed_mask) {
+    if (hipMemcpyAsync(g->mask[0], d->fixed_mask, g->lv[0].nn, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return cleanup(fail(HEXMG_ERR_DEVICE, "copy of the support mask failed"));
+  } else {
+    launch_mask_default(g->lv[0], g->mask[0], s);
+  }
+  for (int l = 1; l < g->L; ++l) launch_mask_inject(g->lv[l - 1], g->lv[l], g->mask[l - 1], g->mask[l], s);
+  g->desc.fixed_mask = nullptr;  // copied; do not keep the caller's pointer
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
+    return cleanup(fail(HEXMG_ERR_DEVICE, "grid set-up kernels failed"));
+  *out = g;
+  return 0;
+}
+
+int hexmg_grid_destroy(hexmg_grid_t g) {
+  if (!g) return 0;
+  for (auto& r : g->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : g->event_pool) hipEventDestroy(e);
+  if (g->host_scalars) (void)hipHostFree(g->host_scalars);
+  delete g;
+  return 0;
+}
+
+int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
+  if (!g || !rho) return fail(HEXMG_ERR_INVALID, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  g->last_stream = s;
+  const hexmg_grid_desc& d = g->desc;
+  launch_simp(g->lv[0].ne, rho, d.E0, d.Emin, d.penal, 1.0, g->E64[0], g->E32[0], g->rho[0], g->flags, s);
+  launch_or_flags(kReduceBlocks, g->flags, g->flags + kReduceBlocks, s);
+  for (int l = 1; l < g->L; ++l) {
+    launch_homogenize(g->lv[l - 1], g->lv[l], g->rho[l - 1], g->rho[l], s);
+    if (d.coarse_avg == HEXMG_AVG_DENSITY)
+      launch_modulus_from_density(g->lv[l].ne, g->rho[l], d.E0, d.Emin, d.penal, double(1 << l), g->E64[l],
+                                  g->E32[l], s);
+    else
+      launch_modulus_from_mean(g->lv[l - 1], g->lv[l], g->E64[l - 1], 2.0, g->E64[l], g->E32[l], s);
+  }
+  for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], d.omega, g->wd64[l], g->wd32[l], s);
+  // Coarsest level: assemble, invert by Gauss-Jordan, symmetrize.
+  const int nc = g->nc;
+  launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], s);
+  int cur = 0;
+  for (int k = 0; k < nc; ++k) {
+    launch_gj_step(nc, k, g->Abuf[cur], g->Abuf[1 - cur], s);
+    cur = 1 - cur;
+  }
+  launch_symmetrize(nc, g->Abuf[cur], g->Abuf[1 - cur], s);
+  g->Ainv = g->Abuf[1 - cur];
+  HIP_TRY(hipGetLastError());
+  int bad = 0;
+  HIP_TRY(hipMemcpyAsync(g->host_scalars, g->flags + kReduceBlocks, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(&bad, g->host_scalars, sizeof(int));
+  if (bad) {
+    g->density_set = false;
+    return fail(HEXMG_ERR_NONFINITE, "density outside [0,1] or not finite");
+  }
+  g->density_set = true;
+  return 0;
+}
+
+int hexmg_apply_K(hexmg_grid_t g, int level, int dtype, const void* u, void* y, int nrhs, void* stream) {
+  if (!g || !u || !y) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (level < 0 || level >= g->L) return fail(HEXMG_ERR_INVALID, "bad level");
+  if (nrhs < 1) return fail(HEXMG_ERR_INVALID, "nrhs must be >= 1");
+  if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
+  hipStream_t s = (hipStream_t)stream;
+  g->last_stream = s;
+  const long long N = 3ll * g->lv[level].nn;
+  for (int r = 0; r < nrhs; ++r) {
+    if (dtype == HEXMG_F64)
+      gather<double>(g, kApply, level, (const double*)u + r * N, nullptr, nullptr, (double*)y + r * N, s);
+    else if (dtype == HEXMG_F32)
+      gather<float>(g, kApply, level, (const float*)u + r * N, nullptr, nullptr, (float*)y + r * N, s);
+    else
+      return fail(HEXMG_ERR_INVALID, "bad dtype");
+  }
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_vcycle(hexmg_grid_t g, int dtype, const void* r, void* z, int nrhs, void* stream) {
+  if (!g || !r || !z) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (nrhs < 1) return fail(HEXMG_ERR_INVALID, "nrhs must be >= 1");
+  if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
+  if (r == z) return fail(HEXMG_ERR_INVALID, "r and z must not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  g->last_stream = s;
+  const long long N = 3ll * g->lv[0].nn;
+  for (int k = 0; k < nrhs; ++k) {
+    if (dtype == HEXMG_F64) {
+      VView<double> v = view64(g);
+      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, s);
+    } else if (dtype == HEXMG_F32) {
+      VView<float> v = view32(g);
+      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, s);
+    } else {
+      return fail(HEXMG_ERR_INVALID, "bad dtype");
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_solve(hexmg_grid_t g, const double* f, double* u, int nrhs, double rtol, int maxit,
+                hexmg_solve_info* info, void* stream) {
+  if (!g || !f || !u) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (nrhs < 1 || maxit < 0) return fail(HEXMG_ERR_INVALID, "bad nrhs or maxit");
+  if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
+  hipStream_t s = (hipStream_t)stream;
+  g->last_stream = s;
+  const Level& L0 = g->lv[0];
+  const long long N = 3ll * L0.nn;
+  double* sc = g->scalars;
+  double* hs = g->host_scalars;
+  int worst = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  HIP_TRY(hipEventCreate(&ev0));
+  HIP_TRY(hipEventCreate(&ev1));
+  for (int k = 0; k < nrhs; ++k) {
+    const double* fk = f + k * N;
+    double* uk = u + k * N;
+    HIP_TRY(hipEventRecord(ev0, s));
+    launch_mask_copy(L0, fk, g->r, s);        // r0 = M f
+    launch_fill(N, 0.0, uk, s);               // x0 = 0
+    dot(g, N, g->r, g->r, sc + kFf, s);
+    int st = 0, its = 0;
+    double ff = 0.0, rr = 0.0;
+    if (int e = read_scalars(g, s)) return e;
+    ff = hs[kFf];
+    rr = ff;
+    if (!std::isfinite(ff)) return fail(HEXMG_ERR_NONFINITE, "load vector is not finite");
+    if (ff > 0.0) {
+      precondition(g, g->r, g->z, s);         // z0 = M^{-1} r0
+      dot(g, N, g->r, g->z, sc + kRz, s);
+      HIP_TRY(hipMemcpyAsync(g->p, g->z, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // p0 = z0
+      st = HEXMG_NOT_CONVERGED;
+      const double stop = (rtol > 0.0) ? rtol * rtol * ff : -1.0;
+      while (its < maxit) {
+        gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, s);  // q = A p
+        dot(g, N, g->p, g->q, sc + kPq, s);
+        launch_scalar_op(kOpAlpha, sc, s);                                 // alpha = r^T z / p^T q
+        launch_update_xr(N, sc, g->p, g->q, uk, g->r, g->partials, s);     // x += alpha p, r -= alpha q
+        launch_reduce_final(g->partials, sc + kRr, s);
+        ++its;
+        if (int e = read_scalars(g, s)) return e;
+        rr = hs[kRr];
+        if (!(hs[kPq] > 0.0) || !std::isfinite(rr)) {
+          st = HEXMG_ERR_BREAKDOWN;
+          break;
+        }
+        if (rr <= stop) {
+          st = HEXMG_OK;
+          break;
+        }
+        if (its == maxit) break;
+        precondition(g, g->r, g->z, s);       // z = M^{-1} r
+        dot(g, N, g->r, g->z, sc + kRzNew, s);
+        launch_scalar_op(kOpBeta, sc, s);     // beta = r^T z / r_old^T z_old
+        launch_update_p(N, sc, g->z, g->p, s);  // p = z + beta p
+      }
+    }
+    HIP_TRY(hipEventRecord(ev1, s));
+    // true residual and compliance in binary64
+    gather<double>(g, kApply, 0, uk, nullptr, nullptr, g->q, s);
+    launch_mask_copy(L0, fk, g->z, s);
+    launch_sub(N, g->z, g->q, g->z, s);
+    dot(g, N, g->z, g->z, sc + kTmp, s);
+    dot(g, N, fk, uk, sc + kRzNew, s);
+    if (int e = read_scalars(g, s)) return e;
+    HIP_TRY(hipGetLastError());
+    if (info) {
+      hexmg_solve_info& in = info[k];
+      in.iterations = its;
+      in.status = st;
+      in.rel_res_recursive = ff > 0 ? std::sqrt(rr / ff) : 0.0;
+      in.rel_res_true = ff > 0 ? std::sqrt(hs[kTmp] / ff) : 0.0;
+      in.compliance = hs[kRzNew];
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev0, ev1);
+      in.ms_solve = ms;
+    }
+    if (st < 0)
+      worst = st;
+    else if (st > worst && worst >= 0)
+      worst = st;
+  }
+  hipEventDestroy(ev0);
+  hipEventDestroy(ev1);
+  if (worst == HEXMG_ERR_BREAKDOWN) return fail(worst, "PCG breakdown (p^T A p <= 0 or non-finite residual)");
+  if (worst == HEXMG_NOT_CONVERGED) g_err = "not converged within maxit";
+  return worst;
+}
+
+int hexmg_compliance_sensitivity(hexmg_grid_t g, const double* f, const double* u, int nrhs,
+                                 const double* weights, double* c_host, double* dc, void* stream) {
+  if (!g || !f || !u) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (nrhs < 1) return fail(HEXMG_ERR_INVALID, "nrhs must be >= 1");
+  if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
+  hipStream_t s = (hipStream_t)stream;
+  g->last_stream = s;
+  const Level& L0 = g->lv[0];
+  const long long N = 3ll * L0.nn;
+  const hexmg_grid_desc& d = g->desc;
+  for (int k = 0; k < nrhs; ++k) {
+    if (dc) {
+      const double w = weights ? weights[k] : 1.0;
+      launch_sensitivity(L0, g->Ke64, g->rho[0], u + k * N, -d.penal * (d.E0 - d.Emin) * w, d.penal - 1.0,
+                         k > 0, dc, s);
+    }
+    if (c_host) {
+      dot(g, N, f + k * N, u + k * N, g->scalars + kTmp, s);
+      if (int e = read_scalars(g, s)) return e;
+      c_host[k] = g->host_scalars[kTmp];
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_element_matrix(double nu, double* Ke) {
+  if (!Ke) return fail(HEXMG_ERR_INVALID, "null output");
+  if (!(nu > -1.0 && nu < 0.5)) return fail(HEXMG_ERR_INVALID, "need -1 < nu < 0.5");
+  element_matrix(nu, Ke);
+  return 0;
+}
+
+int hexmg_profile_enable(hexmg_grid_t g, int enable) {
+  if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
+  if (!enable) drain_profile(g);
+  g->profile = enable != 0;
+  if (enable) {
+    drain_profile(g);
+    for (int i = 0; i < 8; ++i) {
+      g->prof_ms[i] = 0.0;
+      g->prof_count[i] = 0;
+    }
+  }
+  return 0;
+}
+
+int hexmg_profile_query(hexmg_grid_t g, const char* family, int* launches, double* ms) {
+  if (!g || !family) return fail(HEXMG_ERR_INVALID, "null argument");
+  drain_profile(g);
+  for (int i = 0; i < kNumFamilies; ++i)
+    if (std::strcmp(family, kFamilies[i]) == 0) {
+      if (launches) *launches = g->prof_count[i];
+      if (ms) *ms = g->prof_ms[i];
+      return 0;
+    }
+  return fail(HEXMG_ERR_INVALID, std::string("unknown kernel family ") + family);
+}
+
+const char* hexmg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations of the hexmg library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hexmg.h"
+
+namespace hexmg {
+
+// Host-side element stiffness (element.hip).
+void modal_quadratic_form(double nu, double Q[24][24]);
+void element_matrix(double nu, double Ke[576]);
+
+// Geometry of one multigrid level as seen by the kernels.
+struct Level {
+  int nx, ny, nz;     // elements
+  int nxn, nyn, nzn;  // nodes
+  int nn;             // node count
+  int ne;             // element count
+  const uint8_t* mask;  // per-node support bits (device)
+};
+
+constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
+constexpr int kBlock = 256;
+
+// ---- kernel launchers (kernels.hip) --------------------------------------
+template <typename T>
+void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
+                   const T* wdinv, T* y, hipStream_t s);
+// mode: 0 y = A u; 1 y = u + wdinv (f - A u); 2 y = f - A u
+enum { kApply = 0, kSmooth = 1, kResidual = 2 };
+
+template <typename T>
+void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, hipStream_t s);
+template <typename T>
+void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, hipStream_t s);
+
+void launch_simp(int ne, const double* rho, double E0, double Emin, double p, double scale,
+                 double* E64, float* E32, double* rho_copy, int* bad_flags, hipStream_t s);
+void launch_homogenize(const Level& F, const Level& C, const double* vf, double* vc, hipStream_t s);
+void launch_modulus_from_density(int ne, const double* rho, double E0, double Emin, double p,
+                                 double scale, double* E64, float* E32, hipStream_t s);
+void launch_modulus_from_mean(const Level& F, const Level& C, const double* Ef, double scale,
+                              double* E64, float* E32, hipStream_t s);
+void launch_diag(const Level& L, const double* Ke, const double* E, double omega, double* wdinv64,
+                 float* wdinv32, hipStream_t s);
+void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s);
+void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8_t* mc, hipStream_t s);
+void launch_or_flags(int n, const int* flags, int* out, hipStream_t s);
+
+void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, double* A, hipStream_t s);
+void launch_gj_step(int n, int k, const double* A, double* B, hipStream_t s);
+template <typename T>
+void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, hipStream_t s);
+
+// BLAS-1 in binary64 with deterministic two-stage reductions.
+void launch_dot_partial(long long n, const double* x, const double* y, double* partials, hipStream_t s);
+// out[0] = sum of partials[0..kReduceBlocks)
+void launch_reduce_final(const double* partials, double* out, hipStream_t s);
+// scalars: see ScalarSlot
+void launch_scalar_op(int op, double* sc, hipStream_t s);
+void launch_update_xr(long long n, const double* sc, const double* p, const double* q, double* x,
+                      double* r, double* partials, hipStream_t s);
+void launch_update_p(long long n, const double* sc, const double* z, double* p, hipStream_t s);
+void launch_mask_copy(const Level& L, const double* f, double* r, hipStream_t s);
+void launch_f64_to_f32(long long n, const double* a, float* b, hipStream_t s);
+void launch_f32_to_f64(long long n, const float* a, double* b, hipStream_t s);
+void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);
+void launch_fill(long long n, double v, double* x, hipStream_t s);
+
+void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
+                        double coef, double pm1, int accumulate, double* dc, hipStream_t s);
+void launch_symmetrize(int n, const double* A, double* B, hipStream_t s);
+
+// Device scalar slots used by the PCG (one block of kScalars doubles).
+enum ScalarSlot {
+  kRz = 0,      // r^T z (current)
+  kPq = 1,      // p^T A p
+  kRr = 2,      // r^T r
+  kAlpha = 3,
+  kBeta = 4,
+  kRzNew = 5,
+  kFf = 6,      // ||M f||^2
+  kTmp = 7,
+  kScalars = 8
+};
+enum ScalarOp { kOpAlpha = 0, kOpBeta = 1 };
+
+}  // namespace hexmg
+
+// The opaque grid object behind hexmg_grid_t.
+struct hexmg_grid {
+  hexmg_grid_desc desc;
+  int L;
+  std::vector<hexmg::Level> lv;
+  // per-level device arrays (carved from the caller's workspace)
+  std::vector<double*> rho;      // homogenized densities (level 0: copy of the input)
+  std::vector<double*> E64;      // element moduli incl. the 2^l size factor
+  std::vector<float*> E32;
+  std::vector<double*> wd64;     // omega / diag(A_l)
+  std::vector<float*> wd32;
+  std::vector<uint8_t*> mask;
+  // V-cycle vectors per level: f (rhs), u (solution), t (ping-pong), r (residual)
+  std::vector<double*> vf64, vu64, vt64, vr64;
+  std::vector<float*> vf32, vu32, vt32, vr32;
+  double* Abuf[2];  // coarsest operator / Gauss-Jordan ping-pong
+  double* Ainv;     // points at the buffer holding the symmetrized inverse
+  int nc;         // coarsest DOFs
+  double* Ke64;   // 576
+  float* Ke32;
+  // PCG
+  double *r, *z, *p, *q;
+  double* partials;
+  double* scalars;
+  int* flags;     // per-block status flags (kReduceBlocks) + 1 result
+  double* host_scalars;  // pinned host mirror
+  bool density_set;
+  hipStream_t last_stream;
+  // profiling
+  bool profile;
+  struct Rec { int family; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[8];
+  int prof_count[8];
+};

@@ -1,0 +1,587 @@
+// HIP kernels of the hexmg hot path for gfx950 (wave64).
+//
+// Layout: node-major vectors (DOF 3n + c); element moduli per element; support
+// bits per node.  Every reduction is a fixed-shape two-stage tree (kReduceBlocks
+// partial sums, then one block in a fixed order) so results are reproducible
+// run to run; no floating-point atomics are used anywhere.
+#include "hexmg_impl.h"
+
+namespace hexmg {
+
+namespace {
+
+__device__ inline void node_coords(const Level& L, int n, int& i, int& j, int& k) {
+  i = n % L.nxn;
+  const int t = n / L.nxn;
+  j = t % L.nyn;
+  k = t / L.nyn;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over a block of kBlock threads; the result is valid in thread 0.
+__device__ inline double block_sum(double v) {
+  __shared__ double part[kBlock / 64];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s += part[i];
+  }
+  return s;
+}
+
+inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------------------
+// Matrix-free K u (Sec. 4.2.1): every node gathers the rows of its <= 8
+// adjacent elements, y_n = sum_e E_e K0[a_e(n), :] u_e, so no global matrix and
+// no scatter conflicts.  Supports: u is read as M u; fixed DOFs return u.
+// MODE 0: y = A u;  1: y = u + wdinv (f - A u) (damped Jacobi, Eq. 21);
+// 2: y = f - A u (residual, Eq. 19).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather(Level L, const T* __restrict__ Ke,
+                                                   const T* __restrict__ E, const T* __restrict__ u,
+                                                   const T* __restrict__ f,
+                                                   const T* __restrict__ wdinv, T* __restrict__ y) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= L.nn) return;
+  int i, j, k;
+  node_coords(L, n, i, j, k);
+  T un[27][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int o = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        T v0 = 0, v1 = 0, v2 = 0;
+        if (ii >= 0 && ii < L.nxn && jj >= 0 && jj < L.nyn && kk >= 0 && kk < L.nzn) {
+          const int m = n + dx + L.nxn * (dy + L.nyn * dz);
+          const int mk = L.mask[m];
+          const T* um = u + 3ll * m;
+          v0 = (mk & 1) ? T(0) : um[0];
+          v1 = (mk & 2) ? T(0) : um[1];
+          v2 = (mk & 4) ? T(0) : um[2];
+        }
+        un[o][0] = v0;
+        un[o][1] = v1;
+        un[o][2] = v2;
+      }
+  T acc0 = 0, acc1 = 0, acc2 = 0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const int ei = i - ax, ej = j - ay, ek = k - az;
+    if (ei < 0 || ei >= L.nx || ej < 0 || ej >= L.ny || ek < 0 || ek >= L.nz) continue;
+    const T Ee = E[ei + L.nx * (ej + L.ny * ek)];
+    T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+      const int o = (bz - az + 1) * 9 + (by - ay + 1) * 3 + (bx - ax + 1);
+      const T* kr = Ke + (3 * a) * 24 + 3 * b;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        s0 += kr[d] * un[o][d];
+        s1 += kr[24 + d] * un[o][d];
+        s2 += kr[48 + d] * un[o][d];
+      }
+    }
+    acc0 += Ee * s0;
+    acc1 += Ee * s1;
+    acc2 += Ee * s2;
+  }
+  const int mk = L.mask[n];
+  const long long b = 3ll * n;
+  const T Au0 = (mk & 1) ? u[b] : acc0;
+  const T Au1 = (mk & 2) ? u[b + 1] : acc1;
+  const T Au2 = (mk & 4) ? u[b + 2] : acc2;
+  if (MODE == kApply) {
+    y[b] = Au0;
+    y[b + 1] = Au1;
+    y[b + 2] = Au2;
+  } else if (MODE == kSmooth) {
+    y[b] = u[b] + wdinv[b] * (f[b] - Au0);
+    y[b + 1] = u[b + 1] + wdinv[b + 1] * (f[b + 1] - Au1);
+    y[b + 2] = u[b + 2] + wdinv[b + 2] * (f[b + 2] - Au2);
+  } else {
+    y[b] = f[b] - Au0;
+    y[b + 1] = f[b + 1] - Au1;
+    y[b + 2] = f[b + 2] - Au2;
+  }
+}
+
+// First sweep from a zero guess: u = omega D^{-1} f.
+template <typename T>
+__global__ void k_jacobi_first(long long n, const T* __restrict__ wdinv, const T* __restrict__ f,
+                               T* __restrict__ u) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) u[i] = wdinv[i] * f[i];
+}
+
+// Coarse right-hand side f_c = M_c P^T r: trilinear weights 1, 1/2 per axis.
+template <typename T>
+__global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restrict__ fc) {
+  const int m = blockIdx.x * kBlock + threadIdx.x;
+  if (m >= C.nn) return;
+  int I, J, K;
+  node_coords(C, m, I, J, K);
+  T s0 = 0, s1 = 0, s2 = 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int kk = 2 * K + dz;
+    if (kk < 0 || kk >= F.nzn) continue;
+    const T wz = dz ? T(0.5) : T(1);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jj = 2 * J + dy;
+      if (jj < 0 || jj >= F.nyn) continue;
+      const T wy = dy ? T(0.5) : T(1);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = 2 * I + dx;
+        if (ii < 0 || ii >= F.nxn) continue;
+        const T w = (dx ? T(0.5) : T(1)) * wy * wz;
+        const T* rn = r + 3ll * (ii + F.nxn * (jj + F.nyn * kk));
+        s0 += w * rn[0];
+        s1 += w * rn[1];
+        s2 += w * rn[2];
+      }
+    }
+  }
+  const int mk = C.mask[m];
+  fc[3ll * m] = (mk & 1) ? T(0) : s0;
+  fc[3ll * m + 1] = (mk & 2) ? T(0) : s1;
+  fc[3ll * m + 2] = (mk & 4) ? T(0) : s2;
+}
+
+// Fine correction u += M P e_c (trilinear interpolation).
+template <typename T>
+__global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= F.nn) return;
+  int i, j, k;
+  node_coords(F, n, i, j, k);
+  T s0 = 0, s1 = 0, s2 = 0;
+  const int oz = k & 1, oy = j & 1, ox = i & 1;
+  const T wz = oz ? T(0.5) : T(1), wy = oy ? T(0.5) : T(1), wx = ox ? T(0.5) : T(1);
+  for (int cz = 0; cz <= oz; ++cz)
+    for (int cy = 0; cy <= oy; ++cy)
+      for (int cx = 0; cx <= ox; ++cx) {
+        const int m = ((i >> 1) + cx) + C.nxn * (((j >> 1) + cy) + C.nyn * ((k >> 1) + cz));
+        const T w = wx * wy * wz;
+        s0 += w * ec[3ll * m];
+        s1 += w * ec[3ll * m + 1];
+        s2 += w * ec[3ll * m + 2];
+      }
+  const int mk = F.mask[n];
+  if (!(mk & 1)) u[3ll * n] += s0;
+  if (!(mk & 2)) u[3ll * n + 1] += s1;
+  if (!(mk & 4)) u[3ll * n + 2] += s2;
+}
+
+// ---------------------------------------------------------------------------
+// Set-up: SIMP moduli (Eq. 2), homogenized coarse densities (Sec. 4.2.2),
+// Jacobi diagonal, supports.
+__global__ void k_simp(int ne, const double* __restrict__ rho, double E0, double Emin, double p,
+                       double scale, double* __restrict__ E64, float* __restrict__ E32,
+                       double* __restrict__ rho_copy, int* __restrict__ flags) {
+  int bad = 0;
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < ne; e += gridDim.x * kBlock) {
+    const double r = rho[e];
+    if (!(r >= 0.0 && r <= 1.0)) bad = 1;  // also catches NaN
+    rho_copy[e] = r;
+    const double E = scale * (Emin + pow(r, p) * (E0 - Emin));
+    E64[e] = E;
+    E32[e] = (float)E;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) flags[blockIdx.x] = bad;
+}
+
+__global__ void k_or_flags(int n, const int* __restrict__ flags, int* __restrict__ out) {
+  int v = 0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v |= flags[i];
+  v = __syncthreads_or(v);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+__global__ void k_homogenize(Level F, Level C, const double* __restrict__ vf, double* __restrict__ vc) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= C.ne) return;
+  const int I = e % C.nx, t = e / C.nx, J = t % C.ny, K = t / C.ny;
+  double s = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) s += vf[(2 * I + dx) + F.nx * ((2 * J + dy) + F.ny * (2 * K + dz))];
+  vc[e] = 0.125 * s;
+}
+
+__global__ void k_modulus_from_density(int ne, const double* __restrict__ rho, double E0, double Emin,
+                                       double p, double scale, double* __restrict__ E64,
+                                       float* __restrict__ E32) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= ne) return;
+  const double E = scale * (Emin + pow(rho[e], p) * (E0 - Emin));
+  E64[e] = E;
+  E32[e] = (float)E;
+}
+
+__global__ void k_modulus_from_mean(Level F, Level C, const double* __restrict__ Ef, double scale,
+                                    double* __restrict__ E64, float* __restrict__ E32) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= C.ne) return;
+  const int I = e % C.nx, t = e / C.nx, J = t % C.ny, K = t / C.ny;
+  double s = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) s += Ef[(2 * I + dx) + F.nx * ((2 * J + dy) + F.ny * (2 * K + dz))];
+  const double E = scale * 0.125 * s;
+  E64[e] = E;
+  E32[e] = (float)E;
+}
+
+__global__ void k_diag(Level L, const double* __restrict__ Ke, const double* __restrict__ E,
+                       double omega, double* __restrict__ wd64, float* __restrict__ wd32) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= L.nn) return;
+  int i, j, k;
+  node_coords(L, n, i, j, k);
+  double d0 = 0, d1 = 0, d2 = 0;
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const int ei = i - ax, ej = j - ay, ek = k - az;
+    if (ei < 0 || ei >= L.nx || ej < 0 || ej >= L.ny || ek < 0 || ek >= L.nz) continue;
+    const double Ee = E[ei + L.nx * (ej + L.ny * ek)];
+    d0 += Ee * Ke[(3 * a + 0) * 25];
+    d1 += Ee * Ke[(3 * a + 1) * 25];
+    d2 += Ee * Ke[(3 * a + 2) * 25];
+  }
+  const int mk = L.mask[n];
+  const double w0 = omega / ((mk & 1) ? 1.0 : d0);
+  const double w1 = omega / ((mk & 2) ? 1.0 : d1);
+  const double w2 = omega / ((mk & 4) ? 1.0 : d2);
+  wd64[3ll * n] = w0;
+  wd64[3ll * n + 1] = w1;
+  wd64[3ll * n + 2] = w2;
+  wd32[3ll * n] = (float)w0;
+  wd32[3ll * n + 1] = (float)w1;
+  wd32[3ll * n + 2] = (float)w2;
+}
+
+__global__ void k_mask_default(Level L, uint8_t* __restrict__ mask) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= L.nn) return;
+  mask[n] = (n % L.nxn == 0) ? 7 : 0;
+}
+
+__global__ void k_mask_inject(Level F, Level C, const uint8_t* __restrict__ mf, uint8_t* __restrict__ mc) {
+  const int m = blockIdx.x * kBlock + threadIdx.x;
+  if (m >= C.nn) return;
+  int I, J, K;
+  node_coords(C, m, I, J, K);
+  mc[m] = mf[2 * I + F.nxn * (2 * J + F.nyn * 2 * K)];
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: dense A_c, in-place Gauss-Jordan inverse (SPD, so no pivoting),
+// and the direct solve e = A_c^{-1} f as a GEMV (Alg. 3, coarsest grid).
+__global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const double* __restrict__ E,
+                                  double* __restrict__ A) {
+  const long long N = 3ll * C.nn;
+  const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N * N) return;
+  const int r = (int)(idx / N), c = (int)(idx % N);
+  const int m1 = r / 3, c1 = r % 3, m2 = c / 3, c2 = c % 3;
+  const bool fixed = ((C.mask[m1] >> c1) & 1) || ((C.mask[m2] >> c2) & 1);
+  if (fixed) {
+    A[idx] = (r == c) ? 1.0 : 0.0;
+    return;
+  }
+  int i1, j1, k1, i2, j2, k2;
+  node_coords(C, m1, i1, j1, k1);
+  node_coords(C, m2, i2, j2, k2);
+  double s = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const int ei = i1 - ax, ej = j1 - ay, ek = k1 - az;
+    if (ei < 0 || ei >= C.nx || ej < 0 || ej >= C.ny || ek < 0 || ek >= C.nz) continue;
+    const int bx = i2 - ei, by = j2 - ej, bz = k2 - ek;
+    if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+    const int b = bx + 2 * by + 4 * bz;
+    s += E[ei + C.nx * (ej + C.ny * ek)] * Ke[(3 * a + c1) * 24 + 3 * b + c2];
+  }
+  A[idx] = s;
+}
+
+__global__ void k_gj_step(int n, int k, const double* __restrict__ A, double* __restrict__ B) {
+  const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const double p = 1.0 / A[(long long)k * n + k];
+  double v;
+  if (i == k && j == k)
+    v = p;
+  else if (i == k)
+    v = A[(long long)k * n + j] * p;
+  else if (j == k)
+    v = -A[(long long)i * n + k] * p;
+  else
+    v = A[idx] - A[(long long)i * n + k] * A[(long long)k * n + j] * p;
+  B[idx] = v;
+}
+
+__global__ void k_symmetrize(int n, const double* __restrict__ A, double* __restrict__ B) {
+  const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  B[idx] = 0.5 * (A[idx] + A[(long long)j * n + i]);
+}
+
+template <typename T>
+__global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const T* __restrict__ x,
+                              T* __restrict__ y) {
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;  // uniform per wave
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s += Ainv[(long long)row * n + c] * (double)x[c];
+  s = wave_sum(s);
+  if (lane == 0) y[row] = (T)s;
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector kernels (binary64).
+__global__ void k_dot_partial(long long n, const double* __restrict__ x, const double* __restrict__ y,
+                              double* __restrict__ partials) {
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    s += x[i] * y[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_reduce_final(const double* __restrict__ partials, double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kReduceBlocks; i += kBlock) s += partials[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void k_scalar_op(int op, double* __restrict__ sc) {
+  if (threadIdx.x != 0) return;
+  if (op == kOpAlpha) {
+    sc[kAlpha] = sc[kRz] / sc[kPq];
+  } else {
+    sc[kBeta] = sc[kRzNew] / sc[kRz];
+    sc[kRz] = sc[kRzNew];
+  }
+}
+
+__global__ void k_update_xr(long long n, const double* __restrict__ sc, const double* __restrict__ p,
+                            const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
+                            double* __restrict__ partials) {
+  const double alpha = sc[kAlpha];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_update_p(long long n, const double* __restrict__ sc, const double* __restrict__ z,
+                           double* __restrict__ p) {
+  const double beta = sc[kBeta];
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_mask_copy(Level L, const double* __restrict__ f, double* __restrict__ r) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= 3ll * L.nn) return;
+  const int n = (int)(i / 3), c = (int)(i % 3);
+  r[i] = ((L.mask[n] >> c) & 1) ? 0.0 : f[i];
+}
+
+__global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_f32_to_f64(long long n, const float* __restrict__ a, double* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+__global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ c) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) c[i] = a[i] - b[i];
+}
+
+__global__ void k_fill(long long n, double v, double* __restrict__ x) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// Adjoint sensitivity (Eq. 7 with u* = u): dc_e = coef rho_e^(p-1) u_e^T K0 u_e,
+// coef = -p (E0 - Emin) times the load-case weight.
+__global__ void k_sensitivity(Level L, const double* __restrict__ Ke, const double* __restrict__ rho,
+                              const double* __restrict__ u, double coef, double pm1, int accumulate,
+                              double* __restrict__ dc) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= L.ne) return;
+  const int i = e % L.nx, t = e / L.nx, j = t % L.ny, k = t / L.ny;
+  double ue[24];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int m = (i + (b & 1)) + L.nxn * ((j + ((b >> 1) & 1)) + L.nyn * (k + (b >> 2)));
+    ue[3 * b] = u[3ll * m];
+    ue[3 * b + 1] = u[3ll * m + 1];
+    ue[3 * b + 2] = u[3ll * m + 2];
+  }
+  double q = 0.0;
+#pragma unroll
+  for (int r = 0; r < 24; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 24; ++c) s += Ke[r * 24 + c] * ue[c];
+    q += ue[r] * s;
+  }
+  const double v = coef * pow(rho[e], pm1) * q;
+  dc[e] = accumulate ? dc[e] + v : v;
+}
+
+}  // namespace
+
+// ---- launchers ------------------------------------------------------------
+template <typename T>
+void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
+                   const T* wdinv, T* y, hipStream_t s) {
+  const int g = blocks_for(L.nn);
+  if (mode == kApply)
+    k_gather<T, kApply><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
+  else if (mode == kSmooth)
+    k_gather<T, kSmooth><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
+  else
+    k_gather<T, kResidual><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
+}
+template void launch_gather<double>(int, const Level&, const double*, const double*, const double*,
+                                    const double*, const double*, double*, hipStream_t);
+template void launch_gather<float>(int, const Level&, const float*, const float*, const float*,
+                                   const float*, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, hipStream_t s) {
+  k_jacobi_first<T><<<blocks_for(n), kBlock, 0, s>>>(n, wdinv, f, u);
+}
+template void launch_jacobi_first<double>(long long, const double*, const double*, double*, hipStream_t);
+template void launch_jacobi_first<float>(long long, const float*, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, hipStream_t s) {
+  k_restrict<T><<<blocks_for(C.nn), kBlock, 0, s>>>(F, C, r, fc);
+}
+template void launch_restrict<double>(const Level&, const Level&, const double*, double*, hipStream_t);
+template void launch_restrict<float>(const Level&, const Level&, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, hipStream_t s) {
+  k_prolong_add<T><<<blocks_for(F.nn), kBlock, 0, s>>>(F, C, ec, u);
+}
+template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, hipStream_t);
+template void launch_prolong_add<float>(const Level&, const Level&, const float*, float*, hipStream_t);
+
+void launch_simp(int ne, const double* rho, double E0, double Emin, double p, double scale,
+                 double* E64, float* E32, double* rho_copy, int* bad_flags, hipStream_t s) {
+  k_simp<<<kReduceBlocks, kBlock, 0, s>>>(ne, rho, E0, Emin, p, scale, E64, E32, rho_copy, bad_flags);
+}
+void launch_or_flags(int n, const int* flags, int* out, hipStream_t s) {
+  k_or_flags<<<1, kBlock, 0, s>>>(n, flags, out);
+}
+void launch_homogenize(const Level& F, const Level& C, const double* vf, double* vc, hipStream_t s) {
+  k_homogenize<<<blocks_for(C.ne), kBlock, 0, s>>>(F, C, vf, vc);
+}
+void launch_modulus_from_density(int ne, const double* rho, double E0, double Emin, double p,
+                                 double scale, double* E64, float* E32, hipStream_t s) {
+  k_modulus_from_density<<<blocks_for(ne), kBlock, 0, s>>>(ne, rho, E0, Emin, p, scale, E64, E32);
+}
+void launch_modulus_from_mean(const Level& F, const Level& C, const double* Ef, double scale,
+                              double* E64, float* E32, hipStream_t s) {
+  k_modulus_from_mean<<<blocks_for(C.ne), kBlock, 0, s>>>(F, C, Ef, scale, E64, E32);
+}
+void launch_diag(const Level& L, const double* Ke, const double* E, double omega, double* wdinv64,
+                 float* wdinv32, hipStream_t s) {
+  k_diag<<<blocks_for(L.nn), kBlock, 0, s>>>(L, Ke, E, omega, wdinv64, wdinv32);
+}
+void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s) {
+  k_mask_default<<<blocks_for(L.nn), kBlock, 0, s>>>(L, mask);
+}
+void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8_t* mc, hipStream_t s) {
+  k_mask_inject<<<blocks_for(C.nn), kBlock, 0, s>>>(F, C, mf, mc);
+}
+
+void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, double* A, hipStream_t s) {
+  const long long N = 3ll * C.nn;
+  k_coarse_assemble<<<blocks_for(N * N), kBlock, 0, s>>>(C, Ke, E, A);
+}
+void launch_gj_step(int n, int k, const double* A, double* B, hipStream_t s) {
+  k_gj_step<<<blocks_for((long long)n * n), kBlock, 0, s>>>(n, k, A, B);
+}
+void launch_symmetrize(int n, const double* A, double* B, hipStream_t s) {
+  k_symmetrize<<<blocks_for((long long)n * n), kBlock, 0, s>>>(n, A, B);
+}
+template <typename T>
+void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, hipStream_t s) {
+  const int rows_per_block = kBlock / 64;
+  k_coarse_gemv<T><<<(n + rows_per_block - 1) / rows_per_block, kBlock, 0, s>>>(n, Ainv, x, y);
+}
+template void launch_coarse_gemv<double>(int, const double*, const double*, double*, hipStream_t);
+template void launch_coarse_gemv<float>(int, const double*, const float*, float*, hipStream_t);
+
+void launch_dot_partial(long long n, const double* x, const double* y, double* partials, hipStream_t s) {
+  k_dot_partial<<<kReduceBlocks, kBlock, 0, s>>>(n, x, y, partials);
+}
+void launch_reduce_final(const double* partials, double* out, hipStream_t s) {
+  k_reduce_final<<<1, kBlock, 0, s>>>(partials, out);
+}
+void launch_scalar_op(int op, double* sc, hipStream_t s) { k_scalar_op<<<1, 64, 0, s>>>(op, sc); }
+void launch_update_xr(long long n, const double* sc, const double* p, const double* q, double* x,
+                      double* r, double* partials, hipStream_t s) {
+  k_update_xr<<<kReduceBlocks, kBlock, 0, s>>>(n, sc, p, q, x, r, partials);
+}
+void launch_update_p(long long n, const double* sc, const double* z, double* p, hipStream_t s) {
+  k_update_p<<<blocks_for(n), kBlock, 0, s>>>(n, sc, z, p);
+}
+void launch_mask_copy(const Level& L, const double* f, double* r, hipStream_t s) {
+  k_mask_copy<<<blocks_for(3ll * L.nn), kBlock, 0, s>>>(L, f, r);
+}
+void launch_f64_to_f32(long long n, const double* a, float* b, hipStream_t s) {
+  k_f64_to_f32<<<blocks_for(n), kBlock, 0, s>>>(n, a, b);
+}
+void launch_f32_to_f64(long long n, const float* a, double* b, hipStream_t s) {
+  k_f32_to_f64<<<blocks_for(n), kBlock, 0, s>>>(n, a, b);
+}
+void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s) {
+  k_sub<<<blocks_for(n), kBlock, 0, s>>>(n, a, b, c);
+}
+void launch_fill(long long n, double v, double* x, hipStream_t s) {
+  k_fill<<<blocks_for(n), kBlock, 0, s>>>(n, v, x);
+}
+void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
+                        double coef, double pm1, int accumulate, double* dc, hipStream_t s) {
+  k_sensitivity<<<blocks_for(L.ne), kBlock, 0, s>>>(L, Ke, rho, u, coef, pm1, accumulate, dc);
+}
+
+}  // namespace hexmg

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of the hexmg C ABI (include/hexmg.h).
+
+Argument marshalling only: torch tensors supply device pointers and the current
+HIP stream; every step of the computation runs in the HIP library.  The library
+must be built (``python -m paper_2201_12931_amd._build`` or
+``__graft_entry__.build()``); importing this module on a machine without it
+raises immediately -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libhexmg.so")
+HEADER = os.path.join(ROOT, "include", "hexmg.h")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID, ERR_WORKSPACE, ERR_DEVICE, ERR_NONFINITE, ERR_BREAKDOWN = -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+F64, F32 = 0, 1
+AVG_DENSITY, AVG_MODULUS = 0, 1
+
+
+class HexmgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hexmg error {code}: {msg}")
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("levels", ctypes.c_int),
+        ("E0", ctypes.c_double), ("Emin", ctypes.c_double), ("nu", ctypes.c_double),
+        ("penal", ctypes.c_double),
+        ("precision", ctypes.c_int), ("smooth_sweeps", ctypes.c_int),
+        ("omega", ctypes.c_double), ("coarse_avg", ctypes.c_int), ("max_nrhs", ctypes.c_int),
+        ("fixed_mask", ctypes.c_void_p),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int), ("status", ctypes.c_int),
+        ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+        ("compliance", ctypes.c_double), ("ms_solve", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhexmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2201_12931_amd._build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        sig = {
+            "hexmg_default_desc": (i, [i, i, i, i, ctypes.POINTER(GridDesc)]),
+            "hexmg_workspace_size": (i, [ctypes.POINTER(GridDesc), ctypes.POINTER(sz)]),
+            "hexmg_grid_create": (i, [ctypes.POINTER(GridDesc), vp, sz, vp, ctypes.POINTER(vp)]),
+            "hexmg_grid_destroy": (i, [vp]),
+            "hexmg_set_density": (i, [vp, vp, vp]),
+            "hexmg_apply_K": (i, [vp, i, i, vp, vp, i, vp]),
+            "hexmg_vcycle": (i, [vp, i, vp, vp, i, vp]),
+            "hexmg_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(SolveInfo), vp]),
+            "hexmg_compliance_sensitivity": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
+            "hexmg_element_matrix": (i, [d, vp]),
+            "hexmg_profile_enable": (i, [vp, i]),
+            "hexmg_profile_query": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(d)]),
+            "hexmg_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/hexmg.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hexmg_\w+)\s*\(", txt, re.M)))
+
+
+def last_error() -> str:
+    return lib().hexmg_last_error().decode()
+
+
+def _check(code: int, ok=(OK,)) -> int:
+    if code not in ok:
+        raise HexmgError(code, last_error())
+    return code
+
+
+# ---- host-only entry points ------------------------------------------------
+def default_desc(nx, ny, nz, levels, **kw) -> GridDesc:
+    d = GridDesc()
+    _check(lib().hexmg_default_desc(nx, ny, nz, levels, ctypes.byref(d)))
+    for k, v in kw.items():
+        if k == "fixed_mask":
+            v = None if v is None else v.data_ptr()
+        setattr(d, k, v)
+    return d
+
+
+def workspace_size(desc: GridDesc) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().hexmg_workspace_size(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def element_matrix(nu: float = 0.3):
+    import numpy as np
+
+    Ke = np.zeros((24, 24), dtype=np.float64)
+    _check(lib().hexmg_element_matrix(nu, Ke.ctypes.data_as(ctypes.c_void_p)))
+    return Ke
+
+
+# ---- device entry points (torch tensors) -----------------------------------
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype=None, numel=None, name="tensor"):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """Owns the workspace tensor and the opaque grid handle of one hexmg grid."""
+
+    def __init__(self, nx, ny, nz, levels, device="cuda", stream=None, **kw):
+        import torch
+
+        self.desc = default_desc(nx, ny, nz, levels, **kw)
+        self.nx, self.ny, self.nz, self.levels = nx, ny, nz, levels
+        self.n_elem = nx * ny * nz
+        self.n_dof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+        self.workspace = torch.empty(workspace_size(self.desc), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().hexmg_grid_create(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().hexmg_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_dofs(self, level):
+        q = 1 << level
+        return 3 * (self.nx // q + 1) * (self.ny // q + 1) * (self.nz // q + 1)
+
+    def set_density(self, rho, stream=None):
+        import torch
+
+        _check(lib().hexmg_set_density(self.handle, _dev(rho, torch.float64, self.n_elem, "rho"), _stream(stream)))
+
+    def apply_K(self, u, y, level=0, stream=None):
+        import torch
+
+        dt = F64 if u.dtype == torch.float64 else F32
+        n = self.level_dofs(level)
+        if u.numel() % n or y.shape != u.shape or y.dtype != u.dtype:
+            raise ValueError("u, y must be [nrhs, N_level] of one dtype")
+        _check(lib().hexmg_apply_K(self.handle, level, dt, _dev(u, name="u"), _dev(y, name="y"),
+                                   u.numel() // n, _stream(stream)))
+        return y
+
+    def vcycle(self, r, z, stream=None):
+        import torch
+
+        dt = F64 if r.dtype == torch.float64 else F32
+        if r.numel() % self.n_dof or z.shape != r.shape or z.dtype != r.dtype:
+            raise ValueError("r, z must be [nrhs, N] of one dtype")
+        _check(lib().hexmg_vcycle(self.handle, dt, _dev(r, name="r"), _dev(z, name="z"),
+                                  r.numel() // self.n_dof, _stream(stream)))
+        return z
+
+    def solve(self, f, u, rtol=1e-6, maxit=500, stream=None, check=True):
+        import torch
+
+        if f.numel() % self.n_dof or u.shape != f.shape:
+            raise ValueError("f, u must be [nrhs, N]")
+        nrhs = f.numel() // self.n_dof
+        infos = (SolveInfo * nrhs)()
+        code = lib().hexmg_solve(self.handle, _dev(f, torch.float64, name="f"), _dev(u, torch.float64, name="u"),
+                                 nrhs, float(rtol), int(maxit), infos, _stream(stream))
+        if check:
+            _check(code, ok=(OK, NOT_CONVERGED))
+        return code, [x.as_dict() for x in infos]
+
+    def compliance_sensitivity(self, f, u, dc=None, weights=None, stream=None):
+        import numpy as np
+        import torch
+
+        nrhs = f.numel() // self.n_dof
+        c = np.zeros(nrhs, dtype=np.float64)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        _check(lib().hexmg_compliance_sensitivity(
+            self.handle, _dev(f, torch.float64, name="f"), _dev(u, torch.float64, name="u"), nrhs,
+            None if w is None else w.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
+            None if dc is None else _dev(dc, torch.float64, self.n_elem, "dc"), _stream(stream)))
+        return c
+
+    def profile_enable(self, on=True):
+        _check(lib().hexmg_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_query(self, family):
+        n, ms = ctypes.c_int(), ctypes.c_double()
+        _check(lib().hexmg_profile_query(self.handle, family.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
