@@ -156,6 +156,8 @@ def main():
     avg_smooth_ms = ms_smooth / max(n_smooth, 1)
     sb = smooth_bytes_per_launch(g)
     achieved = sb / (avg_smooth_ms * 1e-3) / 1e9
+    choices = {f"L{l}": {"f32": mixed.kernel_choice(l, hexmg.F32), "f64": mixed.kernel_choice(l, hexmg.F64)}
+               for l in range(levels)}
     out = {
         "metric": METRIC,
         "value": g.n_dof / (ms_per_step * 1e-3) / 1e9,
@@ -189,8 +191,9 @@ def main():
         "compliance": {"mixed": c_mixed, "fp64": c64, "rel_diff": abs(c_mixed - c64) / abs(c64)},
         "kernel_ms": {"smooth_f32": [n_smooth, ms_smooth], "residual_f32": [n_res, ms_res],
                       "apply_f64": [n_app, ms_app]},
+        "kernel_choice": choices,
         "roofline": {
-            "kernel": "k_gather<float, smooth> (level-0 damped Jacobi sweep)",
+            "kernel": "level-0 binary32 damped Jacobi sweep (%s, z-chunk %d)" % choices["L0"]["f32"],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -58,6 +58,11 @@ extern "C" {
 #define HEXMG_F64 0
 #define HEXMG_F32 1
 
+/* element-product kernel (hexmg_grid_desc.kernel) */
+#define HEXMG_KERNEL_STREAM 0 /* z-streaming Haar-basis kernel */
+#define HEXMG_KERNEL_GATHER 1 /* node-gather of dense 24x24 element rows */
+#define HEXMG_KERNEL_AUTO 2   /* per level and precision, the faster of the two (timed once, default) */
+
 /* coarse-level modulus (hexmg_grid_desc.coarse_avg) */
 #define HEXMG_AVG_DENSITY 0 /* coarse rho = mean of the 8 children, then E(rho) (Sec. 4.2.2) */
 #define HEXMG_AVG_MODULUS 1 /* coarse E = mean of the 8 children's E */
@@ -73,14 +78,15 @@ typedef struct {
   double omega;         /* Jacobi damping, 0 < omega <= 1 */
   int coarse_avg;       /* HEXMG_AVG_DENSITY | HEXMG_AVG_MODULUS */
   int max_nrhs;         /* most right-hand sides per call (sizes the workspace) */
+  int kernel;           /* HEXMG_KERNEL_AUTO | HEXMG_KERNEL_STREAM | HEXMG_KERNEL_GATHER */
   const uint8_t *fixed_mask; /* device, (nx+1)(ny+1)(nz+1) bytes; NULL = face x = 0 fixed.
                                 Copied at hexmg_grid_create; coarse masks are injected
                                 (coarse node fixed iff the coincident fine node is). */
 } hexmg_grid_desc;
 
 /* Fill *desc with the defaults (E0 1, Emin 1e-9, nu 0.3, penal 3, FP64, 2 sweeps,
- * omega 0.6, density averaging, max_nrhs 1, fixed face x = 0) for the given
- * grid.  Host only. */
+ * omega 0.6, density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0)
+ * for the given grid.  Host only. */
 int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc *desc);
 
 /* Bytes of device workspace hexmg_grid_create needs for *desc (host only). */
@@ -148,6 +154,13 @@ int hexmg_compliance_sensitivity(hexmg_grid_t grid, const double *f, const doubl
 /* The library's unit element stiffness K0 (24x24, row-major, local DOF 3a+c)
  * for Poisson ratio nu, written to Ke_host.  Host only; needs no GPU. */
 int hexmg_element_matrix(double nu, double *Ke_host);
+
+/* The element-product kernel used on `level` for dtype (HEXMG_F64/F32):
+ * *kernel = HEXMG_KERNEL_STREAM or HEXMG_KERNEL_GATHER and, for the streaming
+ * kernel, the planes per z-chunk.  With HEXMG_KERNEL_AUTO the choice is made by
+ * timing the candidates (node-gather; streaming with 2..64 planes per chunk) on
+ * the grid's stream during the first successful hexmg_set_density. */
+int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int *kernel, int *zchunk);
 
 /* Per-kernel device timing with stream events (off by default).  While
  * enabled, every finest-level launch of the named kernel family is bracketed

@@ -61,6 +61,8 @@ int validate(const hexmg_grid_desc* d) {
   if (d->coarse_avg != HEXMG_AVG_DENSITY && d->coarse_avg != HEXMG_AVG_MODULUS)
     return fail(HEXMG_ERR_INVALID, "bad coarse_avg");
   if (d->max_nrhs < 1) return fail(HEXMG_ERR_INVALID, "max_nrhs must be >= 1");
+  if (d->kernel != HEXMG_KERNEL_STREAM && d->kernel != HEXMG_KERNEL_GATHER && d->kernel != HEXMG_KERNEL_AUTO)
+    return fail(HEXMG_ERR_INVALID, "bad kernel");
   return 0;
 }
 
@@ -122,6 +124,8 @@ size_t carve(hexmg_grid* g, char* base) {
   g->nc = (int)nc;
   g->Abuf[0] = c.take<double>(nc * nc);
   g->Abuf[1] = c.take<double>(nc * nc);
+  g->gjD = c.take<double>(kGJBlock * kGJBlock);
+  g->gjX = c.take<double>(kGJBlock * nc);
   g->Ke64 = c.take<double>(576);
   g->Ke32 = c.take<float>(576);
   const size_t N0 = 3ull * g->lv[0].nn;
@@ -151,21 +155,94 @@ hipEvent_t take_event(hexmg_grid* g) {
   return e;
 }
 
+// z-chunk of the streaming kernel: enough workgroups to fill the chip
+// (about 1024), at least 4 and at most 64 planes per chunk.
+int stream_zchunk(const Level& L, bool f32) {
+  const int rows = f32 ? kStreamWaves32 * kStreamRows32 - 2 : kStreamWaves64 * kStreamRows64 - 2;
+  const long long tiles = (long long)((L.nxn + 61) / 62) * ((L.nyn + rows - 1) / rows);
+  long long zc = (L.nzn * tiles + 1023) / 1024;
+  if (zc < 4) zc = 4;
+  if (zc > 64) zc = 64;
+  return (int)zc;
+}
+
 template <typename T>
-void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, hipStream_t s) {
+void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
+                   const T* wd, T* y, hipStream_t s) {
   const bool f32 = sizeof(T) == 4;
   const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
   const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
+  const Level& L = g->lv[level];
+  if (ch.kernel == HEXMG_KERNEL_GATHER) {
+    launch_gather<T>(mode, L, Ke, E, u, f, wd, y, s);
+  } else {
+    const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
+    launch_stream<T>(mode, L, q, E, u, f, wd, y, ch.zchunk, s);
+  }
+}
+
+// Times the candidate kernels of one level in one precision (a damped-Jacobi
+// sweep on zero vectors, the level's own scratch buffers) and returns the
+// fastest.  The streaming kernel is kept unless the node-gather is more than
+// 5% faster.
+template <typename T>
+int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_grid::Choice* out, hipStream_t s) {
+  const Level& L = g->lv[level];
+  const size_t bytes = 3ull * L.nn * sizeof(T);
+  HIP_TRY(hipMemsetAsync(u, 0, bytes, s));
+  HIP_TRY(hipMemsetAsync(f, 0, bytes, s));
+  std::vector<hexmg_grid::Choice> cand;
+  for (int zc : {2, 4, 8, 16, 32, 64})
+    if (zc <= L.nzn || zc == 2) cand.push_back({HEXMG_KERNEL_STREAM, zc});
+  cand.push_back({HEXMG_KERNEL_GATHER, 0});
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_stream = 1e30f, best_gather = 1e30f;
+  hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4};
+  for (const auto& c : cand) {
+    launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, s);
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 3; ++rep) launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, s);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (c.kernel == HEXMG_KERNEL_GATHER) {
+      best_gather = ms;
+    } else if (ms < best_stream) {
+      best_stream = ms;
+      bs = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *out = (best_gather < 0.95f * best_stream) ? hexmg_grid::Choice{HEXMG_KERNEL_GATHER, 0} : bs;
+  return 0;
+}
+
+int tune_kernels(hexmg_grid* g, hipStream_t s) {
+  for (int l = 0; l < g->L; ++l) {
+    if (int e = tune_level<double>(g, l, g->vu64[l], g->vf64[l], g->vt64[l], g->wd64[l], &g->choice64[l], s)) return e;
+    if (int e = tune_level<float>(g, l, g->vu32[l], g->vf32[l], g->vt32[l], g->wd32[l], &g->choice32[l], s)) return e;
+  }
+  g->tuned = true;
+  return 0;
+}
+
+template <typename T>
+void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
   hipEvent_t a = nullptr, b = nullptr;
   const bool prof = g->profile && level == 0;
   if (prof) {
     a = take_event(g);
     b = take_event(g);
-    if (a && b) hipEventRecord(a, s);
+    if (a && b) (void)hipEventRecord(a, s);
   }
-  launch_gather<T>(mode, g->lv[level], Ke, E, u, f, wd, y, s);
+  launch_choice<T>(g, f32 ? g->choice32[level] : g->choice64[level], mode, level, u, f, wd, y, s);
   if (prof && a && b) {
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     g->recs.push_back({family_of(mode, f32), a, b});
   }
 }
@@ -173,7 +250,7 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
 void drain_profile(hexmg_grid* g) {
   for (auto& r : g->recs) {
     float ms = 0.f;
-    hipEventSynchronize(r.b);
+    (void)hipEventSynchronize(r.b);
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       g->prof_ms[r.family] += ms;
       g->prof_count[r.family] += 1;
@@ -276,6 +353,7 @@ int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc* d) {
   d->omega = 0.6;
   d->coarse_avg = HEXMG_AVG_DENSITY;
   d->max_nrhs = 1;
+  d->kernel = HEXMG_KERNEL_AUTO;
   d->fixed_mask = nullptr;
   return 0;
 }
@@ -306,6 +384,18 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   make_levels(d, g->lv);
   carve(g, static_cast<char*>(workspace));
   for (int l = 0; l < g->L; ++l) g->lv[l].mask = g->mask[l];
+  g->tuned = d->kernel != HEXMG_KERNEL_AUTO;
+  g->choice64.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4});
+  g->choice32.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4});
+  for (int l = 0; l < g->L; ++l) {
+    if (d->kernel == HEXMG_KERNEL_GATHER) {
+      g->choice64[l] = {HEXMG_KERNEL_GATHER, 0};
+      g->choice32[l] = {HEXMG_KERNEL_GATHER, 0};
+    } else {
+      g->choice64[l].zchunk = stream_zchunk(g->lv[l], false);
+      g->choice32[l].zchunk = stream_zchunk(g->lv[l], true);
+    }
+  }
   g->density_set = false;
   g->profile = false;
   g->Ainv = g->Abuf[0];
@@ -322,6 +412,13 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   };
   if (hipHostMalloc((void**)&g->host_scalars, 2 * kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(HEXMG_ERR_DEVICE, "pinned host allocation failed"));
+  if (!haar_coefficients(d->nu, &g->hq64))
+    return cleanup(fail(HEXMG_ERR_INVALID, "element stiffness does not have the expected Haar block pattern"));
+  {
+    const HaarCoef<double>& q = g->hq64;
+    g->hq32 = HaarCoef<float>{(float)q.d1, (float)q.b1, (float)q.g, (float)q.a2,
+                              (float)q.b2, (float)q.d3, (float)q.b3, (float)q.a4};
+  }
   double Ke[576];
   float Kf[576];
   element_matrix(d->nu, Ke);
@@ -346,8 +443,8 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
 int hexmg_grid_destroy(hexmg_grid_t g) {
   if (!g) return 0;
   for (auto& r : g->recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   for (auto e : g->event_pool) hipEventDestroy(e);
   if (g->host_scalars) (void)hipHostFree(g->host_scalars);
@@ -374,13 +471,11 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
   // Coarsest level: assemble, invert by Gauss-Jordan, symmetrize.
   const int nc = g->nc;
   launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], s);
-  int cur = 0;
-  for (int k = 0; k < nc; ++k) {
-    launch_gj_step(nc, k, g->Abuf[cur], g->Abuf[1 - cur], s);
-    cur = 1 - cur;
-  }
-  launch_symmetrize(nc, g->Abuf[cur], g->Abuf[1 - cur], s);
-  g->Ainv = g->Abuf[1 - cur];
+  double* inv = nullptr;
+  launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, g->gjX, &inv, s);
+  double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
+  launch_symmetrize(nc, inv, other, s);
+  g->Ainv = other;
   HIP_TRY(hipGetLastError());
   int bad = 0;
   HIP_TRY(hipMemcpyAsync(g->host_scalars, g->flags + kReduceBlocks, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -391,6 +486,9 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     return fail(HEXMG_ERR_NONFINITE, "density outside [0,1] or not finite");
   }
   g->density_set = true;
+  if (!g->tuned) {
+    if (int e = tune_kernels(g, s)) return e;
+  }
   return 0;
 }
 
@@ -512,7 +610,7 @@ int hexmg_solve(hexmg_grid_t g, const double* f, double* u, int nrhs, double rto
       in.rel_res_true = ff > 0 ? std::sqrt(hs[kTmp] / ff) : 0.0;
       in.compliance = hs[kRzNew];
       float ms = 0.f;
-      hipEventElapsedTime(&ms, ev0, ev1);
+      (void)hipEventElapsedTime(&ms, ev0, ev1);
       in.ms_solve = ms;
     }
     if (st < 0)
@@ -520,8 +618,8 @@ int hexmg_solve(hexmg_grid_t g, const double* f, double* u, int nrhs, double rto
     else if (st > worst && worst >= 0)
       worst = st;
   }
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
   if (worst == HEXMG_ERR_BREAKDOWN) return fail(worst, "PCG breakdown (p^T A p <= 0 or non-finite residual)");
   if (worst == HEXMG_NOT_CONVERGED) g_err = "not converged within maxit";
   return worst;
@@ -557,6 +655,16 @@ int hexmg_element_matrix(double nu, double* Ke) {
   if (!Ke) return fail(HEXMG_ERR_INVALID, "null output");
   if (!(nu > -1.0 && nu < 0.5)) return fail(HEXMG_ERR_INVALID, "need -1 < nu < 0.5");
   element_matrix(nu, Ke);
+  return 0;
+}
+
+int hexmg_kernel_choice(hexmg_grid_t g, int level, int dtype, int* kernel, int* zchunk) {
+  if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
+  if (level < 0 || level >= g->L) return fail(HEXMG_ERR_INVALID, "bad level");
+  if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
+  const hexmg_grid::Choice& c = dtype == HEXMG_F64 ? g->choice64[level] : g->choice32[level];
+  if (kernel) *kernel = c.kernel;
+  if (zchunk) *zchunk = c.zchunk;
   return 0;
 }
 

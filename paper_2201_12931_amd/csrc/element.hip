@@ -14,6 +14,8 @@
 //              = int lambda (sum_c d_c u_c)^2 + mu sum_{c,j} (d_j u_c)^2 + d_j u_c d_c u_j
 // an exact, sparse quadratic form Q in the modal coefficients.  Then
 // K0 = H^T Q H / 64 (node-major local DOF 3a + c).
+#include <cmath>
+
 #include "hexmg_impl.h"
 
 namespace hexmg {
@@ -74,6 +76,58 @@ void element_matrix(double nu, double Ke[576]) {
               s += haar_sign(m, a) * Q[3 * m + c][3 * m2 + d] * haar_sign(m2, b);
           Ke[(3 * a + c) * 24 + 3 * b + d] = s / 64.0;
         }
+}
+
+bool haar_coefficients(double nu, HaarCoef<double>* q) {
+  double Q[24][24];
+  modal_quadratic_form(nu, Q);
+  auto at = [&](int m, int c, int m2, int c2) { return Q[3 * m + c][3 * m2 + c2]; };
+  const double a1 = at(1, 0, 1, 0), b1 = at(1, 0, 2, 1), g = at(1, 1, 1, 1);
+  const double a2 = at(3, 0, 3, 0), b2 = at(3, 0, 6, 2), a3 = at(3, 2, 3, 2), b3 = at(3, 2, 5, 1);
+  const double a4 = at(7, 0, 7, 0);
+  // Rebuild Q from the 14-block pattern and compare.
+  double P[24][24];
+  for (int r = 0; r < 24; ++r)
+    for (int s = 0; s < 24; ++s) P[r][s] = 0.0;
+  auto set = [&](int m, int c, int m2, int c2, double v) {
+    P[3 * m + c][3 * m2 + c2] = v;
+    P[3 * m2 + c2][3 * m + c] = v;
+  };
+  const int normal[3][2] = {{1, 0}, {2, 1}, {4, 2}};
+  for (int x = 0; x < 3; ++x)
+    for (int y = 0; y < 3; ++y) set(normal[x][0], normal[x][1], normal[y][0], normal[y][1], x == y ? a1 : b1);
+  const int shear[3][4] = {{1, 1, 2, 0}, {1, 2, 4, 0}, {2, 2, 4, 1}};
+  for (auto& sh : shear) {
+    set(sh[0], sh[1], sh[0], sh[1], g);
+    set(sh[2], sh[3], sh[2], sh[3], g);
+    set(sh[0], sh[1], sh[2], sh[3], g);
+  }
+  const int bil[3][4] = {{3, 0, 6, 2}, {3, 1, 5, 2}, {5, 0, 6, 1}};
+  for (auto& b : bil) {
+    set(b[0], b[1], b[0], b[1], a2);
+    set(b[2], b[3], b[2], b[3], a2);
+    set(b[0], b[1], b[2], b[3], b2);
+  }
+  const int tri3[3][2] = {{3, 2}, {5, 1}, {6, 0}};
+  for (int x = 0; x < 3; ++x)
+    for (int y = 0; y < 3; ++y) set(tri3[x][0], tri3[x][1], tri3[y][0], tri3[y][1], x == y ? a3 : b3);
+  for (int c = 0; c < 3; ++c) set(7, c, 7, c, a4);
+  double scale = 0.0, err = 0.0;
+  for (int r = 0; r < 24; ++r)
+    for (int s = 0; s < 24; ++s) {
+      scale = std::fmax(scale, std::fabs(Q[r][s]));
+      err = std::fmax(err, std::fabs(Q[r][s] - P[r][s]));
+    }
+  if (!(err <= 1e-13 * scale)) return false;
+  q->d1 = (a1 - b1) / 64.0;
+  q->b1 = b1 / 64.0;
+  q->g = g / 64.0;
+  q->a2 = a2 / 64.0;
+  q->b2 = b2 / 64.0;
+  q->d3 = (a3 - b3) / 64.0;
+  q->b3 = b3 / 64.0;
+  q->a4 = a4 / 64.0;
+  return true;
 }
 
 }  // namespace hexmg

@@ -25,8 +25,29 @@ struct Level {
   const uint8_t* mask;  // per-node support bits (device)
 };
 
+// Haar-basis block coefficients of the unit element (already divided by 64):
+// normal block diag-off d1 and off b1, rank-one shear g, bilinear 2x2 (a2, b2),
+// bilinear 3x3 diag-off d3 and off b3, trilinear a4.
+template <typename T>
+struct HaarCoef {
+  T d1, b1, g, a2, b2, d3, b3, a4;
+};
+// Extracts the block coefficients from the modal quadratic form and checks
+// that Q has exactly the 14-block pattern; returns false if it does not.
+bool haar_coefficients(double nu, HaarCoef<double>* q);
+
+// Streaming-kernel shapes: node rows per thread and waves per workgroup, chosen
+// so that the kernel fits 256 VGPRs (two waves per SIMD) without spilling.
+constexpr int kStreamRows32 = 4, kStreamWaves32 = 4;
+constexpr int kStreamRows64 = 2, kStreamWaves64 = 8;
+
+template <typename T>
+void launch_stream(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
+                   const T* wd, T* y, int zchunk, hipStream_t s);
+
 constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
 constexpr int kBlock = 256;
+constexpr int kGJBlock = 64;  // pivot block of the blocked Gauss-Jordan inverse
 
 // ---- kernel launchers (kernels.hip) --------------------------------------
 template <typename T>
@@ -56,7 +77,6 @@ void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8
 void launch_or_flags(int n, const int* flags, int* out, hipStream_t s);
 
 void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, double* A, hipStream_t s);
-void launch_gj_step(int n, int k, const double* A, double* B, hipStream_t s);
 template <typename T>
 void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, hipStream_t s);
 
@@ -78,6 +98,10 @@ void launch_fill(long long n, double v, double* x, hipStream_t s);
 void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
                         double coef, double pm1, int accumulate, double* dc, hipStream_t s);
 void launch_symmetrize(int n, const double* A, double* B, hipStream_t s);
+// In-place-style blocked Gauss-Jordan inverse of the n x n SPD matrix in A
+// (B is the ping-pong buffer, D kGJBlock^2 and X kGJBlock*n scratch); *result
+// receives the buffer holding the inverse.
+void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double** result, hipStream_t s);
 
 // Device scalar slots used by the PCG (one block of kScalars doubles).
 enum ScalarSlot {
@@ -111,10 +135,18 @@ struct hexmg_grid {
   std::vector<double*> vf64, vu64, vt64, vr64;
   std::vector<float*> vf32, vu32, vt32, vr32;
   double* Abuf[2];  // coarsest operator / Gauss-Jordan ping-pong
+  double* gjD;      // kGJBlock^2
+  double* gjX;      // kGJBlock * n_c
   double* Ainv;     // points at the buffer holding the symmetrized inverse
   int nc;         // coarsest DOFs
   double* Ke64;   // 576
   float* Ke32;
+  hexmg::HaarCoef<double> hq64;
+  hexmg::HaarCoef<float> hq32;
+  // element-product kernel per level and precision ([level][0] binary64, [1] binary32)
+  struct Choice { int kernel; int zchunk; };
+  std::vector<Choice> choice64, choice32;
+  bool tuned;
   // PCG
   double *r, *z, *p, *q;
   double* partials;

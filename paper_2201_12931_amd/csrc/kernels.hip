@@ -295,10 +295,10 @@ __global__ void k_mask_inject(Level F, Level C, const uint8_t* __restrict__ mf, 
 // and the direct solve e = A_c^{-1} f as a GEMV (Alg. 3, coarsest grid).
 __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const double* __restrict__ E,
                                   double* __restrict__ A) {
-  const long long N = 3ll * C.nn;
-  const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= N * N) return;
-  const int r = (int)(idx / N), c = (int)(idx % N);
+  const int N = 3 * C.nn;
+  const int c = blockIdx.x * kBlock + threadIdx.x, r = blockIdx.y;
+  if (c >= N) return;
+  const long long idx = (long long)r * N + c;
   const int m1 = r / 3, c1 = r % 3, m2 = c / 3, c2 = c % 3;
   const bool fixed = ((C.mask[m1] >> c1) & 1) || ((C.mask[m2] >> c2) & 1);
   if (fixed) {
@@ -321,28 +321,87 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
   A[idx] = s;
 }
 
-__global__ void k_gj_step(int n, int k, const double* __restrict__ A, double* __restrict__ B) {
-  const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= (long long)n * n) return;
-  const int i = (int)(idx / n), j = (int)(idx % n);
-  const double p = 1.0 / A[(long long)k * n + k];
+// Blocked Gauss-Jordan.  For the pivot block K (rows/columns k0 .. k0+nb-1):
+//   D = A_KK^{-1};  X = D A_K* (row panel);
+//   B_KK = D,  B_KJ = X_J,  B_IK = -A_IK D,  B_IJ = A_IJ - A_IK X_J,
+// which is nb scalar Gauss-Jordan steps applied at once.  A is read, B written.
+// The diagonal block is inverted by one workgroup in LDS: thread (rg, j) owns
+// column j and rows rg, rg+4, ..., so no index arithmetic needs a division.
+__global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
+                                                         double* __restrict__ D) {
+  __shared__ double s[kGJBlock][kGJBlock + 1];
+  constexpr int kRowGroups = kBlock / kGJBlock;     // 4
+  constexpr int kPer = kGJBlock / kRowGroups;      // 16 rows per thread
+  const int j = threadIdx.x % kGJBlock, rg = threadIdx.x / kGJBlock;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = rg + kRowGroups * q;
+    s[i][j] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const double p = 1.0 / s[k][k];
+    const double skj = s[k][j];
+    double v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = rg + kRowGroups * q;
+      const double sik = s[i][k];
+      if (i == k)
+        v[q] = (j == k) ? p : skj * p;
+      else
+        v[q] = (j == k) ? -sik * p : s[i][j] - sik * skj * p;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) s[rg + kRowGroups * q][j] = v[q];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = rg + kRowGroups * q;
+    if (i < nb && j < nb) D[i * nb + j] = s[i][j];
+  }
+}
+
+// grid (ceil(n / kBlock), nb): X[r][j] = sum_q D[r][q] A[k0+q][j]
+__global__ void k_gj_row_panel(int n, int k0, int nb, const double* __restrict__ A, const double* __restrict__ D,
+                               double* __restrict__ X) {
+  const int j = blockIdx.x * kBlock + threadIdx.x, r = blockIdx.y;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < nb; ++q) s += D[r * nb + q] * A[(long long)(k0 + q) * n + j];
+  X[(long long)r * n + j] = s;
+}
+
+// grid (ceil(n / kBlock), n): one row i per blockIdx.y
+__global__ void k_gj_update(int n, int k0, int nb, const double* __restrict__ A, const double* __restrict__ D,
+                            const double* __restrict__ X, double* __restrict__ B) {
+  const int j = blockIdx.x * kBlock + threadIdx.x, i = blockIdx.y;
+  if (j >= n) return;
+  const bool iK = i >= k0 && i < k0 + nb, jK = j >= k0 && j < k0 + nb;
+  const double* Ai = A + (long long)i * n + k0;
   double v;
-  if (i == k && j == k)
-    v = p;
-  else if (i == k)
-    v = A[(long long)k * n + j] * p;
-  else if (j == k)
-    v = -A[(long long)i * n + k] * p;
-  else
-    v = A[idx] - A[(long long)i * n + k] * A[(long long)k * n + j] * p;
-  B[idx] = v;
+  if (iK && jK) {
+    v = D[(i - k0) * nb + (j - k0)];
+  } else if (iK) {
+    v = X[(long long)(i - k0) * n + j];
+  } else if (jK) {
+    double s = 0.0;
+    for (int q = 0; q < nb; ++q) s += Ai[q] * D[q * nb + (j - k0)];
+    v = -s;
+  } else {
+    double s = 0.0;
+    for (int q = 0; q < nb; ++q) s += Ai[q] * X[(long long)q * n + j];
+    v = A[(long long)i * n + j] - s;
+  }
+  B[(long long)i * n + j] = v;
 }
 
 __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __restrict__ B) {
-  const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= (long long)n * n) return;
-  const int i = (int)(idx / n), j = (int)(idx % n);
-  B[idx] = 0.5 * (A[idx] + A[(long long)j * n + i]);
+  const int j = blockIdx.x * kBlock + threadIdx.x, i = blockIdx.y;
+  if (j >= n) return;
+  B[(long long)i * n + j] = 0.5 * (A[(long long)i * n + j] + A[(long long)j * n + i]);
 }
 
 template <typename T>
@@ -533,14 +592,23 @@ void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8
 }
 
 void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, double* A, hipStream_t s) {
-  const long long N = 3ll * C.nn;
-  k_coarse_assemble<<<blocks_for(N * N), kBlock, 0, s>>>(C, Ke, E, A);
+  const int N = 3 * C.nn;
+  k_coarse_assemble<<<dim3(blocks_for(N), N), kBlock, 0, s>>>(C, Ke, E, A);
 }
-void launch_gj_step(int n, int k, const double* A, double* B, hipStream_t s) {
-  k_gj_step<<<blocks_for((long long)n * n), kBlock, 0, s>>>(n, k, A, B);
+void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double** result, hipStream_t s) {
+  double* buf[2] = {A, B};
+  int cur = 0;
+  for (int k0 = 0; k0 < n; k0 += kGJBlock) {
+    const int nb = (n - k0) < kGJBlock ? (n - k0) : kGJBlock;
+    k_gj_block_inv<<<1, kBlock, 0, s>>>(n, k0, nb, buf[cur], D);
+    k_gj_row_panel<<<dim3(blocks_for(n), nb), kBlock, 0, s>>>(n, k0, nb, buf[cur], D, X);
+    k_gj_update<<<dim3(blocks_for(n), n), kBlock, 0, s>>>(n, k0, nb, buf[cur], D, X, buf[1 - cur]);
+    cur = 1 - cur;
+  }
+  *result = buf[cur];
 }
 void launch_symmetrize(int n, const double* A, double* B, hipStream_t s) {
-  k_symmetrize<<<blocks_for((long long)n * n), kBlock, 0, s>>>(n, A, B);
+  k_symmetrize<<<dim3(blocks_for(n), n), kBlock, 0, s>>>(n, A, B);
 }
 template <typename T>
 void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, hipStream_t s) {

@@ -22,6 +22,7 @@ ERR_INVALID, ERR_WORKSPACE, ERR_DEVICE, ERR_NONFINITE, ERR_BREAKDOWN = -1, -2, -
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 AVG_DENSITY, AVG_MODULUS = 0, 1
+KERNEL_STREAM, KERNEL_GATHER, KERNEL_AUTO = 0, 1, 2
 
 
 class HexmgError(RuntimeError):
@@ -38,7 +39,7 @@ class GridDesc(ctypes.Structure):
         ("penal", ctypes.c_double),
         ("precision", ctypes.c_int), ("smooth_sweeps", ctypes.c_int),
         ("omega", ctypes.c_double), ("coarse_avg", ctypes.c_int), ("max_nrhs", ctypes.c_int),
-        ("fixed_mask", ctypes.c_void_p),
+        ("kernel", ctypes.c_int), ("fixed_mask", ctypes.c_void_p),
     ]
 
 
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
             "hexmg_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_compliance_sensitivity": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
             "hexmg_element_matrix": (i, [d, vp]),
+            "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_profile_enable": (i, [vp, i]),
             "hexmg_profile_query": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(d)]),
             "hexmg_last_error": (ctypes.c_char_p, []),
@@ -232,6 +234,11 @@ class Grid:
             None if w is None else w.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
             None if dc is None else _dev(dc, torch.float64, self.n_elem, "dc"), _stream(stream)))
         return c
+
+    def kernel_choice(self, level, dtype=F32):
+        k, z = ctypes.c_int(), ctypes.c_int()
+        _check(lib().hexmg_kernel_choice(self.handle, level, dtype, ctypes.byref(k), ctypes.byref(z)))
+        return ("stream" if k.value == KERNEL_STREAM else "gather"), z.value
 
     def profile_enable(self, on=True):
         _check(lib().hexmg_profile_enable(self.handle, 1 if on else 0))

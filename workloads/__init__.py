@@ -126,6 +126,8 @@ def random_field_density(g: Grid, seed: int, length_scale: float = 8.0,
     w = rng.standard_normal((g.nz, g.ny, g.nx))
     s = gaussian_filter(w, sigma=length_scale / math.sqrt(2.0), mode="reflect", truncate=4.0)
     smin, smax = float(s.min()), float(s.max())
+    if smax == smin:  # a single element: no spread to map
+        return np.full(g.n_elem, hi, dtype=np.float64)
     s = (s - smin) / (smax - smin)
     return (lo + (hi - lo) * s).reshape(-1).astype(np.float64)
 
