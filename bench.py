@@ -193,7 +193,7 @@ def main():
                       "apply_f64": [n_app, ms_app]},
         "kernel_choice": choices,
         "roofline": {
-            "kernel": "level-0 binary32 damped Jacobi sweep (%s, z-chunk %d)" % choices["L0"]["f32"],
+            "kernel": "level-0 binary32 damped Jacobi sweep (%s, z-chunk %d, shape %d)" % choices["L0"]["f32"],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -157,8 +157,8 @@ hipEvent_t take_event(hexmg_grid* g) {
 
 // z-chunk of the streaming kernel: enough workgroups to fill the chip
 // (about 1024), at least 4 and at most 64 planes per chunk.
-int stream_zchunk(const Level& L, bool f32) {
-  const int rows = f32 ? kStreamWaves32 * kStreamRows32 - 2 : kStreamWaves64 * kStreamRows64 - 2;
+int stream_zchunk(const Level& L, bool f32, int shape) {
+  const int rows = stream_out_rows(f32, shape);
   const long long tiles = (long long)((L.nxn + 61) / 62) * ((L.nyn + rows - 1) / rows);
   long long zc = (L.nzn * tiles + 1023) / 1024;
   if (zc < 4) zc = 4;
@@ -177,7 +177,7 @@ void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int le
     launch_gather<T>(mode, L, Ke, E, u, f, wd, y, s);
   } else {
     const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
-    launch_stream<T>(mode, L, q, E, u, f, wd, y, ch.zchunk, s);
+    launch_stream<T>(mode, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, s);
   }
 }
 
@@ -191,15 +191,17 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_gr
   const size_t bytes = 3ull * L.nn * sizeof(T);
   HIP_TRY(hipMemsetAsync(u, 0, bytes, s));
   HIP_TRY(hipMemsetAsync(f, 0, bytes, s));
+  const bool f32 = sizeof(T) == 4;
   std::vector<hexmg_grid::Choice> cand;
-  for (int zc : {2, 4, 8, 16, 32, 64})
-    if (zc <= L.nzn || zc == 2) cand.push_back({HEXMG_KERNEL_STREAM, zc});
-  cand.push_back({HEXMG_KERNEL_GATHER, 0});
+  for (int sh = 0; sh < stream_shapes(f32); ++sh)
+    for (int zc : {2, 4, 8, 16, 32, 64})
+      if (zc <= L.nzn || zc == 2) cand.push_back({HEXMG_KERNEL_STREAM, zc, sh});
+  cand.push_back({HEXMG_KERNEL_GATHER, 0, 0});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   float best_stream = 1e30f, best_gather = 1e30f;
-  hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4};
+  hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4, 0};
   for (const auto& c : cand) {
     launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, s);
     HIP_TRY(hipEventRecord(e0, s));
@@ -217,7 +219,7 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_gr
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  *out = (best_gather < 0.95f * best_stream) ? hexmg_grid::Choice{HEXMG_KERNEL_GATHER, 0} : bs;
+  *out = (best_gather < 0.95f * best_stream) ? hexmg_grid::Choice{HEXMG_KERNEL_GATHER, 0, 0} : bs;
   return 0;
 }
 
@@ -385,15 +387,15 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   carve(g, static_cast<char*>(workspace));
   for (int l = 0; l < g->L; ++l) g->lv[l].mask = g->mask[l];
   g->tuned = d->kernel != HEXMG_KERNEL_AUTO;
-  g->choice64.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4});
-  g->choice32.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4});
+  g->choice64.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4, 1});
+  g->choice32.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4, 1});
   for (int l = 0; l < g->L; ++l) {
     if (d->kernel == HEXMG_KERNEL_GATHER) {
-      g->choice64[l] = {HEXMG_KERNEL_GATHER, 0};
-      g->choice32[l] = {HEXMG_KERNEL_GATHER, 0};
+      g->choice64[l] = {HEXMG_KERNEL_GATHER, 0, 0};
+      g->choice32[l] = {HEXMG_KERNEL_GATHER, 0, 0};
     } else {
-      g->choice64[l].zchunk = stream_zchunk(g->lv[l], false);
-      g->choice32[l].zchunk = stream_zchunk(g->lv[l], true);
+      g->choice64[l].zchunk = stream_zchunk(g->lv[l], false, 1);
+      g->choice32[l].zchunk = stream_zchunk(g->lv[l], true, 1);
     }
   }
   g->density_set = false;
@@ -658,13 +660,32 @@ int hexmg_element_matrix(double nu, double* Ke) {
   return 0;
 }
 
-int hexmg_kernel_choice(hexmg_grid_t g, int level, int dtype, int* kernel, int* zchunk) {
+int hexmg_kernel_choice(hexmg_grid_t g, int level, int dtype, int* kernel, int* zchunk, int* shape) {
   if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
   if (level < 0 || level >= g->L) return fail(HEXMG_ERR_INVALID, "bad level");
   if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
   const hexmg_grid::Choice& c = dtype == HEXMG_F64 ? g->choice64[level] : g->choice32[level];
   if (kernel) *kernel = c.kernel;
   if (zchunk) *zchunk = c.zchunk;
+  if (shape) *shape = c.shape;
+  return 0;
+}
+
+int hexmg_set_kernel_choice(hexmg_grid_t g, int level, int dtype, int kernel, int zchunk, int shape) {
+  if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
+  if (level < 0 || level >= g->L) return fail(HEXMG_ERR_INVALID, "bad level");
+  if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
+  hexmg_grid::Choice c{kernel, zchunk, shape};
+  if (kernel == HEXMG_KERNEL_GATHER) {
+    c = {HEXMG_KERNEL_GATHER, 0, 0};
+  } else if (kernel == HEXMG_KERNEL_STREAM) {
+    if (zchunk < 1 || shape < 0 || shape >= stream_shapes(dtype == HEXMG_F32))
+      return fail(HEXMG_ERR_INVALID, "bad z-chunk or shape");
+  } else {
+    return fail(HEXMG_ERR_INVALID, "bad kernel");
+  }
+  (dtype == HEXMG_F64 ? g->choice64 : g->choice32)[level] = c;
+  g->tuned = true;
   return 0;
 }
 

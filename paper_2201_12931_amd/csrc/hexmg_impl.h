@@ -36,13 +36,13 @@ struct HaarCoef {
 // that Q has exactly the 14-block pattern; returns false if it does not.
 bool haar_coefficients(double nu, HaarCoef<double>* q);
 
-// Streaming-kernel shapes: node rows per thread and waves per workgroup, chosen
-// so that the kernel fits 256 VGPRs (two waves per SIMD) without spilling.
-constexpr int kStreamRows32 = 4, kStreamWaves32 = 4;
-constexpr int kStreamRows64 = 2, kStreamWaves64 = 8;
+// Streaming-kernel shapes (see stream.hip): number of shapes per precision and
+// output rows per workgroup tile of each.
+int stream_shapes(bool f32);
+int stream_out_rows(bool f32, int shape);
 
 template <typename T>
-void launch_stream(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
+void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
                    const T* wd, T* y, int zchunk, hipStream_t s);
 
 constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
@@ -144,7 +144,7 @@ struct hexmg_grid {
   hexmg::HaarCoef<double> hq64;
   hexmg::HaarCoef<float> hq32;
   // element-product kernel per level and precision ([level][0] binary64, [1] binary32)
-  struct Choice { int kernel; int zchunk; };
+  struct Choice { int kernel; int zchunk; int shape; };
   std::vector<Choice> choice64, choice32;
   bool tuned;
   // PCG

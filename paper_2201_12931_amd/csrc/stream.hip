@@ -30,18 +30,6 @@ namespace hexmg {
 
 namespace {
 
-template <typename T>
-struct StreamArgs {
-  Level L;
-  HaarCoef<T> q;
-  const T* __restrict__ E;
-  const T* __restrict__ u;
-  const T* __restrict__ f;
-  const T* __restrict__ wd;
-  T* __restrict__ y;
-  int zchunk;
-};
-
 // Value held by lane+1 (lane 63 receives 0) / lane-1 (lane 0 receives 0).
 __device__ inline float lane_next(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
@@ -109,37 +97,18 @@ __device__ inline void block_product(const HaarCoef<T>& q, T E, const T (&v)[8][
   for (int c = 0; c < 3; ++c) t[0][c] = T(0);
 }
 
-// Epilogue for one node of a completed plane: A u from the node sum (u itself
-// at fixed DOFs), then y = A u, the Jacobi update or the residual.
-template <typename T, int MODE>
-__device__ inline void finish_node(const StreamArgs<T>& a, long long n, const T (&Ku)[3]) {
-  const int mk = a.L.mask[n];
-  const T* uo = a.u + 3 * n;
-  T* yo = a.y + 3 * n;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T uc = uo[c];
-    const T Au = ((mk >> c) & 1) ? uc : Ku[c];
-    if (MODE == kApply)
-      yo[c] = Au;
-    else if (MODE == kSmooth)
-      yo[c] = uc + a.wd[3 * n + c] * (a.f[3 * n + c] - Au);
-    else
-      yo[c] = a.f[3 * n + c] - Au;
-  }
-}
-
-template <typename T, int MODE, int R, int W>
-__global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
-  const Level& L = a.L;
+template <typename T, int MODE, int R, int W, int MINW>
+__global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
+                                                      const T* __restrict__ ug, const T* __restrict__ fg,
+                                                      const T* __restrict__ wg, T* __restrict__ yg, int zchunk) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   constexpr int kOutRows = W * R - 2;
   const int i = blockIdx.x * 62 - 1 + lane;           // node column of this lane
   const int jt0 = blockIdx.y * kOutRows - 1;          // first (halo) row of the tile
   const int j0 = jt0 + w * R;                         // first row of this wave
-  const int kc0 = blockIdx.z * a.zchunk;
-  const int kc1 = min(kc0 + a.zchunk, L.nzn);         // output planes [kc0, kc1)
+  const int kc0 = blockIdx.z * zchunk;
+  const int kc1 = min(kc0 + zchunk, L.nzn);           // output planes [kc0, kc1)
   const bool lane_out = lane >= 1 && lane <= 62 && i < L.nxn;
   const bool col_in = i >= 0 && i < L.nxn;
   const bool col_elem = i >= 0 && i < L.nx;
@@ -148,37 +117,95 @@ __global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
 
   __shared__ T xch[2][W][6][64];  // [parity][wave][bottom xyz, top xyz][lane]
 
+  // Row r of this wave is node row j0 + r; rows 0..R are read, rows 0..R-1 own
+  // element rows and (when inside the tile's output window) output rows.
+  bool row_in[R + 1], row_elem[R], row_out[R];
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    const int jr = j0 + r;
+    row_in[r] = col_in && jr >= 0 && jr < L.nyn;
+    if (r < R) {
+      row_elem[r] = col_elem && jr >= 0 && jr < L.ny;
+      const int rt = w * R + r;
+      row_out[r] = lane_out && rt >= 1 && rt <= kOutRows && jr < L.nyn;
+    }
+  }
+
+  // Software pipeline: the raw u and support bits of plane kk+1 and the moduli
+  // of element layer kk are requested while plane kk is being processed.
+  T un[R + 1][3], uc[R + 1][3], uo[R][3];
+  int mn[R + 1], mc[R + 1], mo[R];
+  T En[R], Ec[R];
+  auto load_plane = [&](int kk, T (&u)[R + 1][3], int (&m)[R + 1]) {
+    const bool pin = kk >= 0 && kk < L.nzn;
+#pragma unroll
+    for (int r = 0; r <= R; ++r) {
+      const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * kk;
+      const bool ok = pin && row_in[r];
+      m[r] = ok ? (int)L.mask[n] : 7;
+      u[r][0] = ok ? ug[3 * n] : T(0);
+      u[r][1] = ok ? ug[3 * n + 1] : T(0);
+      u[r][2] = ok ? ug[3 * n + 2] : T(0);
+    }
+  };
+  auto load_layer = [&](int ke, T (&E)[R]) {
+    const bool lin = ke >= 0 && ke < L.nz;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long e = (long long)i + (long long)L.nx * (j0 + r) + eplane * ke;
+      E[r] = (lin && row_elem[r]) ? Eg[e] : T(0);
+    }
+  };
+
   T Fp[R][4][3];   // face modes of the previous plane
   T Yp[R][3];      // pending node sums of the previous plane
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+  for (int r = 0; r < R; ++r) {
+    mo[r] = 7;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       Yp[r][c] = T(0);
+      uo[r][c] = T(0);
 #pragma unroll
       for (int m = 0; m < 4; ++m) Fp[r][m][c] = T(0);
     }
+  }
+  load_plane(kc0 - 1, un, mn);
+  load_layer(kc0 - 2, En);
 
   for (int kk = kc0 - 1; kk <= kc1; ++kk) {
-    const bool plane_in = kk >= 0 && kk < L.nzn;
-    // ---- load plane kk, rows 0..R (out of domain or fixed reads as 0) --------
-    T ue[R + 1][3];
+    // rotate the pipeline and request the next plane / layer
 #pragma unroll
     for (int r = 0; r <= R; ++r) {
-      const int jr = j0 + r;
-      T u0 = T(0), u1 = T(0), u2 = T(0);
-      if (plane_in && col_in && jr >= 0 && jr < L.nyn) {
-        const long long n = (long long)i + (long long)L.nxn * jr + plane * kk;
-        const int mk = L.mask[n];
-        const T* p = a.u + 3 * n;
-        u0 = (mk & 1) ? T(0) : p[0];
-        u1 = (mk & 2) ? T(0) : p[1];
-        u2 = (mk & 4) ? T(0) : p[2];
-      }
-      ue[r][0] = u0;
-      ue[r][1] = u1;
-      ue[r][2] = u2;
+      mc[r] = mn[r];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uc[r][c] = un[r][c];
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) Ec[r] = En[r];
+    load_plane(kk + 1, un, mn);
+    load_layer(kk, En);
+    // f and omega/D of plane kk-1 for this iteration's epilogue
+    T fo[R][3], wo[R][3];
+    const bool out_plane = kk - 1 >= kc0;
+    if (MODE != kApply) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1);
+        const bool ok = out_plane && row_out[r];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          fo[r][c] = ok ? fg[3 * n + c] : T(0);
+          wo[r][c] = (MODE == kSmooth && ok) ? wg[3 * n + c] : T(0);
+        }
+      }
+    }
+    // masked u of plane kk (fixed and outside DOFs read as 0)
+    T ue[R + 1][3];
+#pragma unroll
+    for (int r = 0; r <= R; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ue[r][c] = ((mc[r] >> c) & 1) ? T(0) : uc[r][c];
     // x-edge modes of row r: s = u(i+1) + u(i), d = u(i+1) - u(i)
     auto xedge = [&](int r, T (&xe)[2][3]) {
 #pragma unroll
@@ -188,21 +215,32 @@ __global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
         xe[1][c] = nx_ - ue[r][c];
       }
     };
+    // node update of plane kk-1 for row r
+    auto finish = [&](int r, const T (&Ku)[3]) {
+      if (!(out_plane && row_out[r])) return;
+      const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T Au = ((mo[r] >> c) & 1) ? uo[r][c] : Ku[c];
+        T v;
+        if (MODE == kApply)
+          v = Au;
+        else if (MODE == kSmooth)
+          v = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
+        else
+          v = fo[r][c] - Au;
+        yg[3 * n + c] = v;
+      }
+    };
     T xa[2][3], xb[2][3];
     xedge(0, xa);
 
     if (kk >= kc0) {
       // ---- element layer kk-1 (between planes kk-1 and kk) -----------------
-      const int ke = kk - 1;
-      const bool layer_in = ke >= 0 && ke < L.nz;
-      const bool out_plane = ke >= kc0;  // plane kk-1 is an output plane
       T carry_b[2][3], carry_t[2][3];    // "1"-end edge contributions to row r+1
       T x0b[2][3], x0t[2][3];            // row 0 edge sums awaiting the previous wave
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int jr = j0 + r;
-        T Ee = T(0);
-        if (layer_in && col_elem && jr >= 0 && jr < L.ny) Ee = a.E[i + (long long)L.nx * jr + eplane * ke];
         T (&xlo)[2][3] = (r & 1) ? xb : xa;
         T (&xhi)[2][3] = (r & 1) ? xa : xb;
         xedge(r + 1, xhi);
@@ -223,7 +261,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
           }
         }
         T t[8][3];
-        block_product<T>(a.q, Ee, v, t);
+        block_product<T>(q, Ec[r], v, t);
         // z adjoint: bottom face (plane kk-1) = t_s - t_d, top face (plane kk) = t_s + t_d;
         // y adjoint: edge row r ("0" end) = G_s - G_d, edge row r+1 ("1" end) = G_s + G_d.
         T eb0[2][3], et0[2][3];
@@ -260,9 +298,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
             Ku[c] = Yp[r][c] + (bs - bd) + lane_prev(bs + bd);
             Yp[r][c] = (ts - td) + lane_prev(ts + td);
           }
-          const int rt = w * R + r;
-          if (out_plane && lane_out && rt <= kOutRows && jr < L.nyn)
-            finish_node<T, MODE>(a, (long long)i + (long long)L.nxn * jr + plane * ke, Ku);
+          finish(r, Ku);
         }
       }
       // The last face row's "1"-end edge contributions belong to the next
@@ -291,9 +327,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
           Yp[0][c] += prev[3 + c][lane];
         }
       }
-      const int rt0 = w * R;
-      if (out_plane && lane_out && rt0 >= 1 && j0 < L.nyn)
-        finish_node<T, MODE>(a, (long long)i + (long long)L.nxn * j0 + plane * ke, Ku);
+      finish(0, Ku);
     } else {
       // first plane of the chunk: only its face modes are needed
 #pragma unroll
@@ -310,36 +344,62 @@ __global__ __launch_bounds__(64 * W, 2) void k_stream(StreamArgs<T> a) {
           }
       }
     }
+    // plane kk becomes the previous plane
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      mo[r] = mc[r];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uo[r][c] = uc[r][c];
+    }
   }
 }
 
-template <typename T, int R, int W>
-void launch_stream_impl(int mode, const StreamArgs<T>& a, hipStream_t s) {
+template <typename T, int R, int W, int MINW>
+void launch_stream_impl(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
+                        const T* wd, T* y, int zchunk, hipStream_t s) {
   constexpr int kOutRows = W * R - 2;
-  dim3 grid((a.L.nxn + 61) / 62, (a.L.nyn + kOutRows - 1) / kOutRows, (a.L.nzn + a.zchunk - 1) / a.zchunk);
+  dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, (L.nzn + zchunk - 1) / zchunk);
   dim3 block(64 * W);
   if (mode == kApply)
-    k_stream<T, kApply, R, W><<<grid, block, 0, s>>>(a);
+    k_stream<T, kApply, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk);
   else if (mode == kSmooth)
-    k_stream<T, kSmooth, R, W><<<grid, block, 0, s>>>(a);
+    k_stream<T, kSmooth, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk);
   else
-    k_stream<T, kResidual, R, W><<<grid, block, 0, s>>>(a);
+    k_stream<T, kResidual, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk);
 }
 
 }  // namespace
 
-template <typename T>
-void launch_stream(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                   const T* wd, T* y, int zchunk, hipStream_t s) {
-  StreamArgs<T> a{L, q, E, u, f, wd, y, zchunk};
-  if constexpr (sizeof(T) == 4)
-    launch_stream_impl<T, kStreamRows32, kStreamWaves32>(mode, a, s);
-  else
-    launch_stream_impl<T, kStreamRows64, kStreamWaves64>(mode, a, s);
+// Shapes (rows per thread R, waves per workgroup W, minimum waves per SIMD the
+// register allocation targets).  binary32: (2,4,3) (3,4,2) (4,4,1);
+// binary64: (1,8,3) (2,8,1).  All fit without spilling to memory.
+int stream_shapes(bool f32) { return f32 ? 3 : 2; }
+int stream_out_rows(bool f32, int shape) {
+  static const int r32[3] = {4 * 2 - 2, 4 * 3 - 2, 4 * 4 - 2};
+  static const int r64[2] = {8 * 1 - 2, 4 * 2 - 2};
+  return f32 ? r32[shape] : r64[shape];
 }
-template void launch_stream<float>(int, const Level&, const HaarCoef<float>&, const float*, const float*,
+
+template <typename T>
+void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
+                   const T* wd, T* y, int zchunk, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (shape == 0)
+      launch_stream_impl<T, 2, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, s);
+    else if (shape == 1)
+      launch_stream_impl<T, 3, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, s);
+    else
+      launch_stream_impl<T, 4, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, s);
+  } else {
+    if (shape == 0)
+      launch_stream_impl<T, 1, 8, 2>(mode, L, q, E, u, f, wd, y, zchunk, s);
+    else
+      launch_stream_impl<T, 2, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, s);
+  }
+}
+template void launch_stream<float>(int, int, const Level&, const HaarCoef<float>&, const float*, const float*,
                                    const float*, const float*, float*, int, hipStream_t);
-template void launch_stream<double>(int, const Level&, const HaarCoef<double>&, const double*, const double*,
+template void launch_stream<double>(int, int, const Level&, const HaarCoef<double>&, const double*, const double*,
                                     const double*, const double*, double*, int, hipStream_t);
 
 }  // namespace hexmg

@@ -76,7 +76,8 @@ def lib() -> ctypes.CDLL:
             "hexmg_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_compliance_sensitivity": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
             "hexmg_element_matrix": (i, [d, vp]),
-            "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "hexmg_set_kernel_choice": (i, [vp, i, i, i, i, i]),
             "hexmg_profile_enable": (i, [vp, i]),
             "hexmg_profile_query": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(d)]),
             "hexmg_last_error": (ctypes.c_char_p, []),
@@ -236,9 +237,13 @@ class Grid:
         return c
 
     def kernel_choice(self, level, dtype=F32):
-        k, z = ctypes.c_int(), ctypes.c_int()
-        _check(lib().hexmg_kernel_choice(self.handle, level, dtype, ctypes.byref(k), ctypes.byref(z)))
-        return ("stream" if k.value == KERNEL_STREAM else "gather"), z.value
+        k, z, sh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().hexmg_kernel_choice(self.handle, level, dtype, ctypes.byref(k), ctypes.byref(z),
+                                         ctypes.byref(sh)))
+        return ("stream" if k.value == KERNEL_STREAM else "gather"), z.value, sh.value
+
+    def set_kernel_choice(self, level, dtype, kernel, zchunk=4, shape=0):
+        _check(lib().hexmg_set_kernel_choice(self.handle, level, dtype, kernel, zchunk, shape))
 
     def profile_enable(self, on=True):
         _check(lib().hexmg_profile_enable(self.handle, 1 if on else 0))

@@ -324,3 +324,33 @@ def test_stream_and_gather_kernels_agree():
         out[kern] = (z.cpu().numpy(), u.cpu().numpy())
     assert rel(out[0][0], out[1][0]) < 1e-12
     assert rel(out[0][1], out[1][1]) < 1e-10
+
+
+@pytest.mark.parametrize("dtype_name,shape", [("f32", 0), ("f32", 1), ("f32", 2), ("f64", 0), ("f64", 1)])
+@pytest.mark.parametrize("zchunk", [1, 3, 8])
+def test_every_stream_shape(dtype_name, shape, zchunk):
+    """Each streaming tile shape and several z-chunk lengths, forced through
+    hexmg_set_kernel_choice, on a grid that cuts the tiles raggedly (129 node
+    columns, 25 node rows, 17 node planes), in all three modes (K u through
+    apply_K; Jacobi and residual through a one-level-deep V-cycle)."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case stream shape {dtype_name} {shape} zchunk={zchunk}", flush=True)
+    dims, levels = (128, 24, 16), 4
+    g, rho, mask, grid = make_case(dims, levels)
+    dt = hexmg.F32 if dtype_name == "f32" else hexmg.F64
+    npdt = np.float32 if dtype_name == "f32" else np.float64
+    tol = 1e-5 if dtype_name == "f32" else 1e-13
+    grid.set_kernel_choice(0, dt, hexmg.KERNEL_STREAM, zchunk, shape)
+    assert grid.kernel_choice(0, dt) == ("stream", zchunk, shape)
+    h = mg.Hierarchy(*dims, rho, mask, levels)
+    u = W.random_vector(g.n_dof, seed=40)
+    y = torch.empty(g.n_dof, dtype=torch.float32 if dt == hexmg.F32 else torch.float64, device="cuda")
+    grid.apply_K(gpu(u.astype(npdt)), y)
+    ref = h.A[0] @ u.astype(npdt).astype(np.float64)
+    assert rel(y.cpu().numpy(), ref) < tol
+    # smoothing and residual modes run inside the V-cycle
+    r = W.random_vector(g.n_dof, seed=41) * h.free[0]
+    z = torch.empty_like(y)
+    grid.vcycle(gpu(r.astype(npdt)), z)
+    assert rel(z.cpu().numpy(), h.vcycle(r)) < (1e-4 if dt == hexmg.F32 else 1e-10)
