@@ -151,6 +151,27 @@ int hexmg_compliance_sensitivity(hexmg_grid_t grid, const double *f, const doubl
                                  int nrhs, const double *weights_host, double *c_host,
                                  double *dc, void *stream);
 
+/* S13: density filter with the weights of Eqs. 4-5, w_ei = max(0, rmin -
+ * |c_e - c_i|) over the in-domain elements of an nx*ny*nz grid (element
+ * order), 1 < rmin <= 8.  adjoint = 0: out = (H in) / Hs, Hs = H 1;
+ * adjoint != 0: out = H (in / Hs), the transpose (tmp: device, nx*ny*nz
+ * doubles of scratch, distinct from in and out; unused and may be NULL for
+ * the forward filter).  in and out must not overlap.  Asynchronous. */
+int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double *in, double *out,
+                 double *tmp, void *stream);
+
+/* S14: one optimality-criteria update (Eqs. 8-9) on the grid's elements:
+ * x_new = clamp(x B^eta, max(0, x - move), min(1, x + move)),
+ * B = -dc / (lambda dv), with lambda found by bisection in log space on
+ * [1e-12, 1e12] (to a relative width of 1e-12) so that dv^T x_new = volfrac,
+ * where dv = dV/dx (for the filtered volume V = mean(rho~) that is
+ * H (1/(Ne Hs)), so dv^T x is exactly the filtered volume).  x, dc, dv:
+ * device, Ne doubles (dc <= 0, dv > 0); x_new: device, Ne doubles, distinct
+ * from the inputs.  lambda_host (host, may be NULL) receives lambda.
+ * Synchronises the stream once per bisection pass (32 multipliers per pass). */
+int hexmg_oc_update(hexmg_grid_t grid, const double *x, const double *dc, const double *dv, double volfrac,
+                    double move, double eta, double *x_new, double *lambda_host, void *stream);
+
 /* The library's unit element stiffness K0 (24x24, row-major, local DOF 3a+c)
  * for Poisson ratio nu, written to Ke_host.  Host only; needs no GPU. */
 int hexmg_element_matrix(double nu, double *Ke_host);

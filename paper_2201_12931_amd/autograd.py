@@ -1,0 +1,59 @@
+"""torch.autograd.Function wrappers around the hexmg C ABI.
+
+* ``DensityFilter``: rho~ = H x / Hs (Eqs. 4-5 weights); backward is the adjoint
+  filter H (g / Hs).
+* ``Compliance``: c_r = f_r^T u_r with K(rho~) u_r = f_r solved by MGPCG; backward
+  is the hand-written adjoint sensitivity of Eq. 7 with u* = u (the compliance
+  is self-adjoint, so no second solve), weighted by the incoming gradient per
+  load case.
+
+Both run entirely in the HIP library; tensors only carry device memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import hexmg
+
+
+class DensityFilter(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, shape, rmin):
+        nx, ny, nz = shape
+        ctx.shape, ctx.rmin = shape, rmin
+        return hexmg.density_filter(nx, ny, nz, rmin, x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        nx, ny, nz = ctx.shape
+        gx = hexmg.density_filter(nx, ny, nz, ctx.rmin, g.contiguous(), adjoint=True)
+        return gx, None, None
+
+
+class Compliance(torch.autograd.Function):
+    """c = Compliance.apply(rho, grid, f, rtol, maxit): f is [nrhs, N] (or [N])."""
+
+    @staticmethod
+    def forward(ctx, rho, grid, f, rtol=1e-6, maxit=500):
+        rho = rho.detach().contiguous()
+        grid.set_density(rho)
+        u = torch.empty_like(f)
+        code, info = grid.solve(f, u, rtol=rtol, maxit=maxit)
+        c = grid.compliance_sensitivity(f, u)
+        ctx.grid, ctx.version = grid, grid.density_version
+        ctx.save_for_backward(rho, f, u)
+        ctx.info = info
+        grid.last_info = info
+        return torch.as_tensor(c, dtype=torch.float64, device=rho.device).reshape(f.shape[:-1] if f.dim() > 1 else ())
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        rho, f, u = ctx.saved_tensors
+        grid = ctx.grid
+        if grid.density_version != ctx.version:
+            grid.set_density(rho)
+        w = np.atleast_1d(grad_c.detach().double().cpu().numpy()).reshape(-1)
+        dc = torch.empty_like(rho)
+        grid.compliance_sensitivity(f, u, dc=dc, weights=w)
+        return dc, None, None, None, None

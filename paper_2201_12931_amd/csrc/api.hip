@@ -136,6 +136,8 @@ size_t carve(hexmg_grid* g, char* base) {
   g->partials = c.take<double>(kReduceBlocks);
   g->scalars = c.take<double>(kScalars);
   g->flags = c.take<int>(kReduceBlocks + 1);
+  g->oc_partials = c.take<double>((size_t)kReduceBlocks * kOcProbes);
+  g->oc_vol = c.take<double>(kOcProbes);
   return c.off + 256;
 }
 
@@ -412,7 +414,7 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
     delete g;
     return code;
   };
-  if (hipHostMalloc((void**)&g->host_scalars, 2 * kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&g->host_scalars, 8 * kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(HEXMG_ERR_DEVICE, "pinned host allocation failed"));
   if (!haar_coefficients(d->nu, &g->hq64))
     return cleanup(fail(HEXMG_ERR_INVALID, "element stiffness does not have the expected Haar block pattern"));
@@ -650,6 +652,63 @@ int hexmg_compliance_sensitivity(hexmg_grid_t g, const double* f, const double* 
     }
   }
   HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out, double* tmp,
+                 void* stream) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(HEXMG_ERR_INVALID, "grid dimensions must be >= 1");
+  if (!(rmin > 1.0 && rmin <= 8.0)) return fail(HEXMG_ERR_INVALID, "need 1 < rmin <= 8");
+  if (!in || !out || in == out) return fail(HEXMG_ERR_INVALID, "need distinct in and out");
+  if (adjoint && (!tmp || tmp == in || tmp == out)) return fail(HEXMG_ERR_INVALID, "the adjoint needs a separate tmp");
+  if ((long long)nx * ny * nz >= (1ll << 31)) return fail(HEXMG_ERR_INVALID, "grid too large");
+  launch_filter(nx, ny, nz, rmin, adjoint, in, out, tmp, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_oc_update(hexmg_grid_t g, const double* x, const double* dc, const double* dv, double volfrac,
+                    double move, double eta, double* x_new, double* lambda_host, void* stream) {
+  if (!g || !x || !dc || !dv || !x_new) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (x_new == x || x_new == dc || x_new == dv) return fail(HEXMG_ERR_INVALID, "x_new must not overlap the inputs");
+  if (!(volfrac > 0.0 && volfrac < 1.0) || !(move > 0.0 && move <= 1.0) || !(eta > 0.0 && eta <= 1.0))
+    return fail(HEXMG_ERR_INVALID, "need 0 < volfrac < 1, 0 < move <= 1, 0 < eta <= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n = g->lv[0].ne;
+  // bisection on log lambda, kOcProbes interior probes per pass
+  double lo = std::log(1e-12), hi = std::log(1e12);
+  const double rel_tol = 1e-12;
+  int passes = 0;
+  while (std::exp(hi - lo) - 1.0 > rel_tol && passes < 64) {
+    OcProbes pw;
+    double lp[kOcProbes];
+    for (int p = 0; p < kOcProbes; ++p) {
+      lp[p] = lo + (hi - lo) * (p + 1) / (kOcProbes + 1);
+      pw.v[p] = std::exp(-eta * lp[p]);
+    }
+    launch_oc_probe(n, x, dc, dv, eta, move, pw, g->oc_partials, g->oc_vol, s);
+    HIP_TRY(hipMemcpyAsync(g->host_scalars, g->oc_vol, kOcProbes * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // the pinned mirror holds 8*kScalars doubles
+    static_assert(kOcProbes <= 8 * kScalars, "pinned buffer too small");
+    double nlo = lo, nhi = hi;
+    for (int p = 0; p < kOcProbes; ++p) {
+      if (g->host_scalars[p] > volfrac) {
+        nlo = lp[p];
+      } else {
+        nhi = lp[p];
+        break;
+      }
+    }
+    if (!std::isfinite(g->host_scalars[0])) return fail(HEXMG_ERR_NONFINITE, "non-finite OC volume");
+    lo = nlo;
+    hi = nhi;
+    ++passes;
+  }
+  const double lam = std::exp(0.5 * (lo + hi));
+  launch_oc_apply(n, x, dc, dv, eta, move, std::exp(-eta * 0.5 * (lo + hi)), x_new, s);
+  HIP_TRY(hipGetLastError());
+  if (lambda_host) *lambda_host = lam;
   return 0;
 }
 

@@ -46,6 +46,7 @@ void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, co
                    const T* wd, T* y, int zchunk, hipStream_t s);
 
 constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
+constexpr int kOcProbes = 32;       // Lagrange multipliers evaluated per OC pass
 constexpr int kBlock = 256;
 constexpr int kGJBlock = 64;  // pivot block of the blocked Gauss-Jordan inverse
 
@@ -103,6 +104,17 @@ void launch_symmetrize(int n, const double* A, double* B, hipStream_t s);
 // receives the buffer holding the inverse.
 void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double** result, hipStream_t s);
 
+// Density filter and optimality criteria (topopt.hip)
+void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out, double* tmp,
+                   hipStream_t s);
+struct OcProbes {
+  double v[kOcProbes];  // lambda_p^(-eta)
+};
+void launch_oc_probe(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
+                     const OcProbes& lam_pow, double* partials, double* vol, hipStream_t s);
+void launch_oc_apply(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
+                     double lam_pow, double* xn, hipStream_t s);
+
 // Device scalar slots used by the PCG (one block of kScalars doubles).
 enum ScalarSlot {
   kRz = 0,      // r^T z (current)
@@ -152,6 +164,8 @@ struct hexmg_grid {
   double* partials;
   double* scalars;
   int* flags;     // per-block status flags (kReduceBlocks) + 1 result
+  double* oc_partials;  // kReduceBlocks x kOcProbes
+  double* oc_vol;       // kOcProbes
   double* host_scalars;  // pinned host mirror
   bool density_set;
   hipStream_t last_stream;

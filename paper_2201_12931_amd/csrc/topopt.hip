@@ -1,0 +1,139 @@
+// Density filter (weights of Eqs. 4-5) and the optimality-criteria update
+// (Eqs. 8-9) on the GPU.
+//
+// Filter: rho~_e = sum_i w_ei x_i / sum_i w_ei over in-domain elements i with
+// w_ei = max(0, r - |c_e - c_i|).  The weight sum is recomputed per element
+// (it only depends on how the stencil is cut by the domain), so no array of
+// weight sums is stored.  The adjoint is g_x = H (g / Hs) (H is symmetric).
+//
+// OC: x_new(lambda) = clamp(x B^eta, max(0, x - m), min(1, x + m)) with
+// B = -dc / (lambda dv).  Because x B^eta = s_e lambda^(-eta) with
+// s_e = x_e (-dc_e / dv_e)^eta, one pass over the elements evaluates the volume
+// dv^T x_new(lambda) (the filtered volume is linear in x) for kOcProbes values
+// of lambda at once; the host narrows the bracket by that factor per pass.
+#include <cmath>
+
+#include "hexmg_impl.h"
+
+namespace hexmg {
+
+namespace {
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// MODE 0: out = (H in) / Hs;  1: out = in / Hs;  2: out = H in.
+template <int MODE>
+__global__ void k_filter(int nx, int ny, int nz, double rmin, int R, const double* __restrict__ in,
+                         double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= nx) return;
+  const long long me = i + (long long)nx * (j + (long long)ny * k);
+  double s = 0.0, ws = 0.0;
+  for (int dk = -R; dk <= R; ++dk) {
+    const int kk = k + dk;
+    if (kk < 0 || kk >= nz) continue;
+    for (int dj = -R; dj <= R; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= ny) continue;
+      for (int di = -R; di <= R; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= nx) continue;
+        const double w = rmin - sqrt((double)(di * di + dj * dj + dk * dk));
+        if (w <= 0.0) continue;
+        ws += w;
+        if (MODE != 1) s += w * in[ii + (long long)nx * (jj + (long long)ny * kk)];
+      }
+    }
+  }
+  if (MODE == 0)
+    out[me] = s / ws;
+  else if (MODE == 1)
+    out[me] = in[me] / ws;
+  else
+    out[me] = s;
+}
+
+// Volume at kOcProbes multipliers: partial[block][p] = sum_e dv_e x_new_e(lambda_p)
+__global__ __launch_bounds__(kBlock) void k_oc_probe(long long n, const double* __restrict__ x,
+                                                     const double* __restrict__ dc, const double* __restrict__ dv,
+                                                     double eta, double move, OcProbes lam_pow,
+                                                     double* __restrict__ partials) {
+  __shared__ double part[kBlock / 64][kOcProbes];
+  double acc[kOcProbes];
+#pragma unroll
+  for (int p = 0; p < kOcProbes; ++p) acc[p] = 0.0;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
+    const double xe = x[e], ve = dv[e];
+    const double B = -dc[e] / ve;
+    const double se = xe * pow(B > 0.0 ? B : 0.0, eta);
+    const double lo = fmax(0.0, xe - move), hi = fmin(1.0, xe + move);
+#pragma unroll
+    for (int p = 0; p < kOcProbes; ++p) acc[p] += ve * fmin(hi, fmax(lo, se * lam_pow.v[p]));
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < kOcProbes; ++p) {
+    const double v = wave_sum64(acc[p]);
+    if (lane == 0) part[w][p] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kOcProbes) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) s += part[q][threadIdx.x];
+    partials[(long long)blockIdx.x * kOcProbes + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_oc_probe_final(const double* __restrict__ partials, double* __restrict__ vol) {
+  // one thread per probe, fixed order over the blocks
+  const int p = threadIdx.x;
+  if (p >= kOcProbes) return;
+  double s = 0.0;
+  for (int b = 0; b < kReduceBlocks; ++b) s += partials[(long long)b * kOcProbes + p];
+  vol[p] = s;
+}
+
+__global__ void k_oc_apply(long long n, const double* __restrict__ x, const double* __restrict__ dc,
+                           const double* __restrict__ dv, double eta, double move, double lam_pow,
+                           double* __restrict__ xn) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const double xe = x[e];
+  const double B = -dc[e] / dv[e];
+  const double se = xe * pow(B > 0.0 ? B : 0.0, eta);
+  xn[e] = fmin(fmin(1.0, xe + move), fmax(fmax(0.0, xe - move), se * lam_pow));
+}
+
+}  // namespace
+
+void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out, double* tmp,
+                   hipStream_t s) {
+  const int R = (int)std::ceil(rmin) - 1;
+  const int bx = 64;
+  dim3 grid((nx + bx - 1) / bx, ny, nz);
+  if (adjoint) {
+    k_filter<1><<<grid, bx, 0, s>>>(nx, ny, nz, rmin, R, in, tmp);
+    k_filter<2><<<grid, bx, 0, s>>>(nx, ny, nz, rmin, R, tmp, out);
+  } else {
+    k_filter<0><<<grid, bx, 0, s>>>(nx, ny, nz, rmin, R, in, out);
+  }
+}
+
+void launch_oc_probe(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
+                     const OcProbes& lam_pow, double* partials, double* vol, hipStream_t s) {
+  k_oc_probe<<<kReduceBlocks, kBlock, 0, s>>>(n, x, dc, dv, eta, move, lam_pow, partials);
+  k_oc_probe_final<<<1, 64, 0, s>>>(partials, vol);
+}
+
+void launch_oc_apply(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
+                     double lam_pow, double* xn, hipStream_t s) {
+  k_oc_apply<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, x, dc, dv, eta, move, lam_pow, xn);
+}
+
+}  // namespace hexmg

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
             "hexmg_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_compliance_sensitivity": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
             "hexmg_element_matrix": (i, [d, vp]),
+            "hexmg_filter": (i, [i, i, i, d, i, vp, vp, vp, vp]),
+            "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), vp]),
             "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_set_kernel_choice": (i, [vp, i, i, i, i, i]),
             "hexmg_profile_enable": (i, [vp, i]),
@@ -153,6 +155,21 @@ def _dev(t, dtype=None, numel=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def density_filter(nx, ny, nz, rmin, x, out=None, adjoint=False, tmp=None, stream=None):
+    """S13: rho~ = H x / Hs (adjoint: H (x / Hs)) on the GPU; returns out."""
+    import torch
+
+    n = nx * ny * nz
+    if out is None:
+        out = torch.empty_like(x)
+    if adjoint and tmp is None:
+        tmp = torch.empty_like(x)
+    _check(lib().hexmg_filter(nx, ny, nz, float(rmin), 1 if adjoint else 0, _dev(x, torch.float64, n, "x"),
+                              _dev(out, torch.float64, n, "out"),
+                              _dev(tmp, torch.float64, n, "tmp") if adjoint else None, _stream(stream)))
+    return out
+
+
 class Grid:
     """Owns the workspace tensor and the opaque grid handle of one hexmg grid."""
 
@@ -168,6 +185,8 @@ class Grid:
         _check(lib().hexmg_grid_create(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
                                        self.workspace.numel(), _stream(stream), ctypes.byref(h)))
         self.handle = h
+        self.density_version = 0
+        self.last_info = None
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -188,6 +207,7 @@ class Grid:
         import torch
 
         _check(lib().hexmg_set_density(self.handle, _dev(rho, torch.float64, self.n_elem, "rho"), _stream(stream)))
+        self.density_version += 1
 
     def apply_K(self, u, y, level=0, stream=None):
         import torch
@@ -235,6 +255,19 @@ class Grid:
             None if w is None else w.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
             None if dc is None else _dev(dc, torch.float64, self.n_elem, "dc"), _stream(stream)))
         return c
+
+    def oc_update(self, x, dc, dv, volfrac, move=0.2, eta=0.5, x_new=None, stream=None):
+        """S14: returns (x_new, lambda)."""
+        import torch
+
+        if x_new is None:
+            x_new = torch.empty_like(x)
+        lam = ctypes.c_double()
+        n = self.n_elem
+        _check(lib().hexmg_oc_update(self.handle, _dev(x, torch.float64, n, "x"), _dev(dc, torch.float64, n, "dc"),
+                                     _dev(dv, torch.float64, n, "dv"), float(volfrac), float(move), float(eta),
+                                     _dev(x_new, torch.float64, n, "x_new"), ctypes.byref(lam), _stream(stream)))
+        return x_new, lam.value
 
     def kernel_choice(self, level, dtype=F32):
         k, z, sh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
