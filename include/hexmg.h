@@ -136,11 +136,25 @@ typedef struct {
 /* S10: MGPCG (Alg. 1, preconditioned by hexmg_vcycle in the grid's precision)
  * for A u = M f from u0 = 0, stopping when ||r_k||_2 <= rtol ||M f||_2 or after
  * maxit iterations; rtol <= 0 runs exactly maxit iterations.  f, u: device,
- * [nrhs][N] doubles.  info: host array of nrhs entries (may be NULL).
- * Synchronises the stream.  Returns 1 if some right-hand side did not
- * converge, -5 on breakdown (p^T A p <= 0). */
+ * [nrhs][N] doubles.  Up to max_nrhs right-hand sides are solved in lockstep
+ * (one kernel launch covers all of them; each stops on its own criterion);
+ * more are taken in blocks of max_nrhs.  info: host array of nrhs entries (may
+ * be NULL).  Synchronises the stream.  Returns 1 if some right-hand side did
+ * not converge, -5 on breakdown (p^T A p <= 0). */
 int hexmg_solve(hexmg_grid_t grid, const double *f, double *u, int nrhs, double rtol,
                 int maxit, hexmg_solve_info *info, void *stream);
+
+/* S15: solve several grids (distinct objects, each after a successful
+ * hexmg_set_density) together: grid i solves nrhs[i] <= its max_nrhs
+ * right-hand sides f[i] -> u[i] (device, [nrhs[i]][N_i] doubles) exactly as
+ * hexmg_solve would.  The grids advance in lockstep, each on a stream of its
+ * own (created on first use, default priority, destroyed with the grid) that
+ * is ordered after the work already queued on `stream`; every kernel covers
+ * all right-hand sides of its grid, and the host waits once per round for all
+ * grids.  infos: host, sum(nrhs) entries in grid order (may be NULL).
+ * Synchronises `stream`.  Status as hexmg_solve (worst over the batch). */
+int hexmg_batch_solve(hexmg_grid_t *grids, int ngrids, const double *const *f, double *const *u,
+                      const int *nrhs, double rtol, int maxit, hexmg_solve_info *infos, void *stream);
 
 /* S11-S12: compliance c_r = f_r^T u_r (Eq. 6) per right-hand side into
  * c_host (host, nrhs doubles, may be NULL) and the adjoint sensitivity (Eq. 7,

@@ -102,6 +102,7 @@ size_t carve(hexmg_grid* g, char* base) {
   g->vu32.assign(L, nullptr);
   g->vt32.assign(L, nullptr);
   g->vr32.assign(L, nullptr);
+  const size_t R = (size_t)g->desc.max_nrhs;
   for (int l = 0; l < L; ++l) {
     const Level& lv = g->lv[l];
     const size_t N = 3ull * lv.nn;
@@ -111,14 +112,14 @@ size_t carve(hexmg_grid* g, char* base) {
     g->wd64[l] = c.take<double>(N);
     g->wd32[l] = c.take<float>(N);
     g->mask[l] = c.take<uint8_t>(lv.nn);
-    g->vf64[l] = c.take<double>(N);
-    g->vu64[l] = c.take<double>(N);
-    g->vt64[l] = c.take<double>(N);
-    g->vr64[l] = c.take<double>(N);
-    g->vf32[l] = c.take<float>(N);
-    g->vu32[l] = c.take<float>(N);
-    g->vt32[l] = c.take<float>(N);
-    g->vr32[l] = c.take<float>(N);
+    g->vf64[l] = c.take<double>(N * R);
+    g->vu64[l] = c.take<double>(N * R);
+    g->vt64[l] = c.take<double>(N * R);
+    g->vr64[l] = c.take<double>(N * R);
+    g->vf32[l] = c.take<float>(N * R);
+    g->vu32[l] = c.take<float>(N * R);
+    g->vt32[l] = c.take<float>(N * R);
+    g->vr32[l] = c.take<float>(N * R);
   }
   const size_t nc = 3ull * g->lv[L - 1].nn;
   g->nc = (int)nc;
@@ -129,13 +130,14 @@ size_t carve(hexmg_grid* g, char* base) {
   g->Ke64 = c.take<double>(576);
   g->Ke32 = c.take<float>(576);
   const size_t N0 = 3ull * g->lv[0].nn;
-  g->r = c.take<double>(N0);
-  g->z = c.take<double>(N0);
-  g->p = c.take<double>(N0);
-  g->q = c.take<double>(N0);
-  g->partials = c.take<double>(kReduceBlocks);
-  g->scalars = c.take<double>(kScalars);
+  g->r = c.take<double>(N0 * R);
+  g->z = c.take<double>(N0 * R);
+  g->p = c.take<double>(N0 * R);
+  g->q = c.take<double>(N0 * R);
+  g->partials = c.take<double>(kReduceBlocks * R);
+  g->scalars = c.take<double>(kScalars * R);
   g->flags = c.take<int>(kReduceBlocks + 1);
+  g->active = c.take<int>(R);
   g->oc_partials = c.take<double>((size_t)kReduceBlocks * kOcProbes);
   g->oc_vol = c.take<double>(kOcProbes);
   return c.off + 256;
@@ -170,16 +172,16 @@ int stream_zchunk(const Level& L, bool f32, int shape) {
 
 template <typename T>
 void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
-                   const T* wd, T* y, hipStream_t s) {
+                   const T* wd, T* y, int nrhs, hipStream_t s) {
   const bool f32 = sizeof(T) == 4;
   const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
   const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
   const Level& L = g->lv[level];
   if (ch.kernel == HEXMG_KERNEL_GATHER) {
-    launch_gather<T>(mode, L, Ke, E, u, f, wd, y, s);
+    launch_gather<T>(mode, L, Ke, E, u, f, wd, y, nrhs, s);
   } else {
     const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
-    launch_stream<T>(mode, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, s);
+    launch_stream<T>(mode, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, nrhs, s);
   }
 }
 
@@ -205,9 +207,9 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_gr
   float best_stream = 1e30f, best_gather = 1e30f;
   hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4, 0};
   for (const auto& c : cand) {
-    launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, s);
+    launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, 1, s);
     HIP_TRY(hipEventRecord(e0, s));
-    for (int rep = 0; rep < 3; ++rep) launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, s);
+    for (int rep = 0; rep < 3; ++rep) launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, 1, s);
     HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -235,7 +237,8 @@ int tune_kernels(hexmg_grid* g, hipStream_t s) {
 }
 
 template <typename T>
-void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, hipStream_t s) {
+void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, int nrhs,
+            hipStream_t s) {
   const bool f32 = sizeof(T) == 4;
   hipEvent_t a = nullptr, b = nullptr;
   const bool prof = g->profile && level == 0;
@@ -244,7 +247,7 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
     b = take_event(g);
     if (a && b) (void)hipEventRecord(a, s);
   }
-  launch_choice<T>(g, f32 ? g->choice32[level] : g->choice64[level], mode, level, u, f, wd, y, s);
+  launch_choice<T>(g, f32 ? g->choice32[level] : g->choice64[level], mode, level, u, f, wd, y, nrhs, s);
   if (prof && a && b) {
     (void)hipEventRecord(b, s);
     g->recs.push_back({family_of(mode, f32), a, b});
@@ -287,53 +290,61 @@ VView<float> view32(hexmg_grid* g) {
 // scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
 // in `out` without a copy.  f and out must not overlap.
 template <typename T>
-void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, hipStream_t s) {
+void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrhs, hipStream_t s) {
   const Level& L = g->lv[l];
   if (l == g->L - 1) {
-    launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, s);
+    launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, nrhs, s);
     return;
   }
   const long long N = 3ll * L.nn;
   const int nu = g->desc.smooth_sweeps;
   T* buf[2] = {v.t[l], out};
   int cur = 0;
-  launch_jacobi_first<T>(N, v.wd[l], f, buf[0], s);
+  launch_jacobi_first<T>(N, v.wd[l], f, buf[0], nrhs, s);
   for (int it = 1; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], s);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s);
     cur = 1 - cur;
   }
-  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], s);
-  launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], s);
-  vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], s);
-  launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], s);
+  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], nrhs, s);
+  launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], nrhs, s);
+  vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, s);
+  launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, s);
   for (int it = 0; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], s);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s);
     cur = 1 - cur;
   }
 }
 
-// z = V(r) in the grid's precision for one binary64 right-hand side.
-void precondition(hexmg_grid* g, const double* r, double* z, hipStream_t s) {
+// z = V(r) in the grid's precision for nrhs <= max_nrhs binary64 right-hand sides.
+void precondition(hexmg_grid* g, const double* r, double* z, int nrhs, hipStream_t s) {
   const long long N = 3ll * g->lv[0].nn;
   if (g->desc.precision == HEXMG_FP64) {
     VView<double> v = view64(g);
-    vcycle_level<double>(g, v, 0, r, z, s);
+    vcycle_level<double>(g, v, 0, r, z, nrhs, s);
   } else {
     VView<float> v = view32(g);
-    launch_f64_to_f32(N, r, g->vf32[0], s);
-    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], s);
-    launch_f32_to_f64(N, g->vu32[0], z, s);
+    launch_f64_to_f32(N * nrhs, r, g->vf32[0], s);
+    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, s);
+    launch_f32_to_f64(N * nrhs, g->vu32[0], z, s);
   }
 }
 
-void dot(hexmg_grid* g, long long n, const double* x, const double* y, double* out, hipStream_t s) {
-  launch_dot_partial(n, x, y, g->partials, s);
-  launch_reduce_final(g->partials, out, s);
+// out[r * kScalars] = x_r . y_r for each right-hand side r
+void dot(hexmg_grid* g, long long n, const double* x, const double* y, double* out, int nrhs, hipStream_t s) {
+  launch_dot_partial(n, x, y, g->partials, nrhs, s);
+  launch_reduce_final(g->partials, out, kScalars, nrhs, s);
 }
 
-int read_scalars(hexmg_grid* g, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(g->host_scalars, g->scalars, kScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+int read_scalars(hexmg_grid* g, int nrhs, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(g->host_scalars, g->scalars, (size_t)kScalars * nrhs * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int write_active(hexmg_grid* g, const int* act, int nrhs, hipStream_t s) {
+  for (int k = 0; k < nrhs; ++k) g->host_active[k] = act[k];
+  HIP_TRY(hipMemcpyAsync(g->active, g->host_active, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
   return 0;
 }
 
@@ -414,8 +425,13 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
     delete g;
     return code;
   };
-  if (hipHostMalloc((void**)&g->host_scalars, 8 * kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return cleanup(fail(HEXMG_ERR_DEVICE, "pinned host allocation failed"));
+  {
+    const size_t nsc = (size_t)kScalars * (d->max_nrhs > 8 ? d->max_nrhs : 8);
+    if (hipHostMalloc((void**)&g->host_scalars, nsc * sizeof(double) + d->max_nrhs * sizeof(int),
+                      hipHostMallocDefault) != hipSuccess)
+      return cleanup(fail(HEXMG_ERR_DEVICE, "pinned host allocation failed"));
+    g->host_active = reinterpret_cast<int*>(g->host_scalars + nsc);
+  }
   if (!haar_coefficients(d->nu, &g->hq64))
     return cleanup(fail(HEXMG_ERR_INVALID, "element stiffness does not have the expected Haar block pattern"));
   {
@@ -446,6 +462,7 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
 
 int hexmg_grid_destroy(hexmg_grid_t g) {
   if (!g) return 0;
+  if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
   for (auto& r : g->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -503,15 +520,13 @@ int hexmg_apply_K(hexmg_grid_t g, int level, int dtype, const void* u, void* y, 
   if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
   hipStream_t s = (hipStream_t)stream;
   g->last_stream = s;
-  const long long N = 3ll * g->lv[level].nn;
-  for (int r = 0; r < nrhs; ++r) {
-    if (dtype == HEXMG_F64)
-      gather<double>(g, kApply, level, (const double*)u + r * N, nullptr, nullptr, (double*)y + r * N, s);
-    else if (dtype == HEXMG_F32)
-      gather<float>(g, kApply, level, (const float*)u + r * N, nullptr, nullptr, (float*)y + r * N, s);
-    else
-      return fail(HEXMG_ERR_INVALID, "bad dtype");
-  }
+  if (nrhs > 65535) return fail(HEXMG_ERR_INVALID, "nrhs must be <= 65535");
+  if (dtype == HEXMG_F64)
+    gather<double>(g, kApply, level, (const double*)u, nullptr, nullptr, (double*)y, nrhs, s);
+  else if (dtype == HEXMG_F32)
+    gather<float>(g, kApply, level, (const float*)u, nullptr, nullptr, (float*)y, nrhs, s);
+  else
+    return fail(HEXMG_ERR_INVALID, "bad dtype");
   HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -524,20 +539,204 @@ int hexmg_vcycle(hexmg_grid_t g, int dtype, const void* r, void* z, int nrhs, vo
   hipStream_t s = (hipStream_t)stream;
   g->last_stream = s;
   const long long N = 3ll * g->lv[0].nn;
-  for (int k = 0; k < nrhs; ++k) {
+  if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
+  for (int k = 0; k < nrhs; k += g->desc.max_nrhs) {
+    const int nb = (nrhs - k) < g->desc.max_nrhs ? (nrhs - k) : g->desc.max_nrhs;
     if (dtype == HEXMG_F64) {
       VView<double> v = view64(g);
-      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, s);
-    } else if (dtype == HEXMG_F32) {
-      VView<float> v = view32(g);
-      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, s);
+      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, nb, s);
     } else {
-      return fail(HEXMG_ERR_INVALID, "bad dtype");
+      VView<float> v = view32(g);
+      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, nb, s);
     }
   }
   HIP_TRY(hipGetLastError());
   return 0;
 }
+
+}  // extern "C"
+
+namespace {
+
+// PCG (Alg. 1) for nb <= max_nrhs right-hand sides of one grid in lockstep,
+// written as a resumable state machine so that several grids can advance
+// together: each call of advance() consumes the scalars the previous phase
+// copied to the host, decides, and enqueues the next phase on the run's stream
+// (ending with an asynchronous copy of the new scalars and an event).  Every
+// kernel covers all nb right-hand sides; one that has converged (or broken
+// down) is frozen through the device `active` flags.
+struct PcgRun {
+  hexmg_grid* g = nullptr;
+  const double* f = nullptr;
+  double* u = nullptr;
+  int nb = 0;
+  double rtol = 0.0;
+  int maxit = 0;
+  hipStream_t s = nullptr;
+  hexmg_solve_info* info = nullptr;
+  hipEvent_t ready = nullptr, t0 = nullptr, t1 = nullptr;
+  enum Phase { kSetup, kIterate, kFinish, kDone } phase = kSetup;
+  std::vector<double> ff, rr;
+  std::vector<int> st, its, act;
+  int nact = 0, it = 0, status = 0;
+
+  int init() {
+    ff.assign(nb, 0.0);
+    rr.assign(nb, 0.0);
+    st.assign(nb, HEXMG_NOT_CONVERGED);
+    its.assign(nb, 0);
+    act.assign(nb, 0);
+    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    return 0;
+  }
+  void release() {
+    if (ready) (void)hipEventDestroy(ready);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    ready = t0 = t1 = nullptr;
+  }
+  long long N() const { return 3ll * g->lv[0].nn; }
+  int post_scalars() {
+    HIP_TRY(hipMemcpyAsync(g->host_scalars, g->scalars, (size_t)kScalars * nb * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ready, s));
+    return 0;
+  }
+  int begin() {
+    const Level& L0 = g->lv[0];
+    HIP_TRY(hipEventRecord(t0, s));
+    launch_mask_copy(L0, f, g->r, nb, s);  // r0 = M f
+    launch_fill(N() * nb, 0.0, u, s);      // x0 = 0
+    dot(g, N(), g->r, g->r, g->scalars + kFf, nb, s);
+    phase = kSetup;
+    return post_scalars();
+  }
+  // q = A p, alpha, x and r updates, ||r||^2
+  int enqueue_iteration() {
+    double* sc = g->scalars;
+    gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s);
+    dot(g, N(), g->p, g->q, sc + kPq, nb, s);
+    launch_scalar_op(kOpAlpha, sc, nb, s);
+    launch_update_xr(N(), sc, g->active, g->p, g->q, u, g->r, g->partials, nb, s);
+    launch_reduce_final(g->partials, sc + kRr, kScalars, nb, s);
+    return post_scalars();
+  }
+  int enqueue_finish() {
+    const Level& L0 = g->lv[0];
+    double* sc = g->scalars;
+    HIP_TRY(hipEventRecord(t1, s));
+    gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s);  // true residual in binary64
+    launch_mask_copy(L0, f, g->z, nb, s);
+    launch_sub(N() * nb, g->z, g->q, g->z, s);
+    dot(g, N(), g->z, g->z, sc + kTmp, nb, s);
+    dot(g, N(), f, u, sc + kRzNew, nb, s);
+    phase = kFinish;
+    return post_scalars();
+  }
+  // Called once `ready` has completed.
+  int advance() {
+    const double* hs = g->host_scalars;
+    double* sc = g->scalars;
+    if (phase == kSetup) {
+      nact = 0;
+      for (int k = 0; k < nb; ++k) {
+        ff[k] = hs[k * kScalars + kFf];
+        rr[k] = ff[k];
+        if (!std::isfinite(ff[k])) return fail(HEXMG_ERR_NONFINITE, "load vector is not finite");
+        act[k] = ff[k] > 0.0;
+        if (!act[k]) st[k] = HEXMG_OK;
+        nact += act[k];
+      }
+      if (!nact || maxit == 0) return enqueue_finish();
+      if (int e = write_active(g, act.data(), nb, s)) return e;
+      precondition(g, g->r, g->z, nb, s);  // z0 = M^{-1} r0
+      dot(g, N(), g->r, g->z, sc + kRz, nb, s);
+      HIP_TRY(hipMemcpyAsync(g->p, g->z, N() * nb * sizeof(double), hipMemcpyDeviceToDevice, s));  // p0 = z0
+      phase = kIterate;
+      it = 0;
+      return enqueue_iteration();
+    }
+    if (phase == kIterate) {
+      ++it;
+      bool changed = false;
+      for (int k = 0; k < nb; ++k) {
+        if (!act[k]) continue;
+        ++its[k];
+        rr[k] = hs[k * kScalars + kRr];
+        const double pq = hs[k * kScalars + kPq];
+        const double stop = (rtol > 0.0) ? rtol * rtol * ff[k] : -1.0;
+        if (!(pq > 0.0) || !std::isfinite(rr[k]))
+          st[k] = HEXMG_ERR_BREAKDOWN;
+        else if (rr[k] <= stop)
+          st[k] = HEXMG_OK;
+        else
+          continue;
+        act[k] = 0;
+        --nact;
+        changed = true;
+      }
+      if (!nact || it >= maxit) return enqueue_finish();
+      if (changed)
+        if (int e = write_active(g, act.data(), nb, s)) return e;
+      precondition(g, g->r, g->z, nb, s);   // z = M^{-1} r
+      dot(g, N(), g->r, g->z, sc + kRzNew, nb, s);
+      launch_scalar_op(kOpBeta, sc, nb, s);  // beta = r^T z / r_old^T z_old
+      launch_update_p(N(), sc, g->active, g->z, g->p, nb, s);  // p = z + beta p
+      return enqueue_iteration();
+    }
+    // kFinish
+    HIP_TRY(hipGetLastError());
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    status = 0;
+    for (int k = 0; k < nb; ++k) {
+      if (info) {
+        hexmg_solve_info& in = info[k];
+        in.iterations = its[k];
+        in.status = st[k];
+        in.rel_res_recursive = ff[k] > 0 ? std::sqrt(rr[k] / ff[k]) : 0.0;
+        in.rel_res_true = ff[k] > 0 ? std::sqrt(hs[k * kScalars + kTmp] / ff[k]) : 0.0;
+        in.compliance = hs[k * kScalars + kRzNew];
+        in.ms_solve = ms;
+      }
+      if (st[k] < 0)
+        status = st[k];
+      else if (status >= 0 && st[k] > status)
+        status = st[k];
+    }
+    phase = kDone;
+    return 0;
+  }
+};
+
+// Drives a set of runs (distinct grids) to completion: each round waits for
+// every pending run's scalars, then lets each run enqueue its next phase.
+int drive(std::vector<PcgRun>& runs) {
+  for (auto& r : runs)
+    if (int e = r.begin()) return e;
+  for (;;) {
+    bool pending = false;
+    for (auto& r : runs) {
+      if (r.phase == PcgRun::kDone) continue;
+      pending = true;
+      HIP_TRY(hipEventSynchronize(r.ready));
+      if (int e = r.advance()) return e;
+    }
+    if (!pending) return 0;
+  }
+}
+
+int combine_status(int worst, int st) {
+  if (st < 0) return st;
+  if (worst >= 0 && st > worst) return st;
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
 
 int hexmg_solve(hexmg_grid_t g, const double* f, double* u, int nrhs, double rtol, int maxit,
                 hexmg_solve_info* info, void* stream) {
@@ -546,85 +745,81 @@ int hexmg_solve(hexmg_grid_t g, const double* f, double* u, int nrhs, double rto
   if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
   hipStream_t s = (hipStream_t)stream;
   g->last_stream = s;
-  const Level& L0 = g->lv[0];
-  const long long N = 3ll * L0.nn;
-  double* sc = g->scalars;
-  double* hs = g->host_scalars;
+  const long long N = 3ll * g->lv[0].nn;
   int worst = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  HIP_TRY(hipEventCreate(&ev0));
-  HIP_TRY(hipEventCreate(&ev1));
-  for (int k = 0; k < nrhs; ++k) {
-    const double* fk = f + k * N;
-    double* uk = u + k * N;
-    HIP_TRY(hipEventRecord(ev0, s));
-    launch_mask_copy(L0, fk, g->r, s);        // r0 = M f
-    launch_fill(N, 0.0, uk, s);               // x0 = 0
-    dot(g, N, g->r, g->r, sc + kFf, s);
-    int st = 0, its = 0;
-    double ff = 0.0, rr = 0.0;
-    if (int e = read_scalars(g, s)) return e;
-    ff = hs[kFf];
-    rr = ff;
-    if (!std::isfinite(ff)) return fail(HEXMG_ERR_NONFINITE, "load vector is not finite");
-    if (ff > 0.0) {
-      precondition(g, g->r, g->z, s);         // z0 = M^{-1} r0
-      dot(g, N, g->r, g->z, sc + kRz, s);
-      HIP_TRY(hipMemcpyAsync(g->p, g->z, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // p0 = z0
-      st = HEXMG_NOT_CONVERGED;
-      const double stop = (rtol > 0.0) ? rtol * rtol * ff : -1.0;
-      while (its < maxit) {
-        gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, s);  // q = A p
-        dot(g, N, g->p, g->q, sc + kPq, s);
-        launch_scalar_op(kOpAlpha, sc, s);                                 // alpha = r^T z / p^T q
-        launch_update_xr(N, sc, g->p, g->q, uk, g->r, g->partials, s);     // x += alpha p, r -= alpha q
-        launch_reduce_final(g->partials, sc + kRr, s);
-        ++its;
-        if (int e = read_scalars(g, s)) return e;
-        rr = hs[kRr];
-        if (!(hs[kPq] > 0.0) || !std::isfinite(rr)) {
-          st = HEXMG_ERR_BREAKDOWN;
-          break;
-        }
-        if (rr <= stop) {
-          st = HEXMG_OK;
-          break;
-        }
-        if (its == maxit) break;
-        precondition(g, g->r, g->z, s);       // z = M^{-1} r
-        dot(g, N, g->r, g->z, sc + kRzNew, s);
-        launch_scalar_op(kOpBeta, sc, s);     // beta = r^T z / r_old^T z_old
-        launch_update_p(N, sc, g->z, g->p, s);  // p = z + beta p
-      }
-    }
-    HIP_TRY(hipEventRecord(ev1, s));
-    // true residual and compliance in binary64
-    gather<double>(g, kApply, 0, uk, nullptr, nullptr, g->q, s);
-    launch_mask_copy(L0, fk, g->z, s);
-    launch_sub(N, g->z, g->q, g->z, s);
-    dot(g, N, g->z, g->z, sc + kTmp, s);
-    dot(g, N, fk, uk, sc + kRzNew, s);
-    if (int e = read_scalars(g, s)) return e;
-    HIP_TRY(hipGetLastError());
-    if (info) {
-      hexmg_solve_info& in = info[k];
-      in.iterations = its;
-      in.status = st;
-      in.rel_res_recursive = ff > 0 ? std::sqrt(rr / ff) : 0.0;
-      in.rel_res_true = ff > 0 ? std::sqrt(hs[kTmp] / ff) : 0.0;
-      in.compliance = hs[kRzNew];
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ev0, ev1);
-      in.ms_solve = ms;
-    }
-    if (st < 0)
-      worst = st;
-    else if (st > worst && worst >= 0)
-      worst = st;
+  for (int k = 0; k < nrhs; k += g->desc.max_nrhs) {
+    std::vector<PcgRun> runs(1);
+    PcgRun& r = runs[0];
+    r.g = g;
+    r.f = f + k * N;
+    r.u = u + k * N;
+    r.nb = (nrhs - k) < g->desc.max_nrhs ? (nrhs - k) : g->desc.max_nrhs;
+    r.rtol = rtol;
+    r.maxit = maxit;
+    r.s = s;
+    r.info = info ? info + k : nullptr;
+    int e = r.init();
+    if (!e) e = drive(runs);
+    r.release();
+    if (e) return e;
+    worst = combine_status(worst, r.status);
   }
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   if (worst == HEXMG_ERR_BREAKDOWN) return fail(worst, "PCG breakdown (p^T A p <= 0 or non-finite residual)");
+  if (worst == HEXMG_NOT_CONVERGED) g_err = "not converged within maxit";
+  return worst;
+}
+
+int hexmg_batch_solve(hexmg_grid_t* grids, int ngrids, const double* const* f, double* const* u, const int* nrhs,
+                      double rtol, int maxit, hexmg_solve_info* infos, void* stream) {
+  if (!grids || !f || !u || !nrhs || ngrids < 1) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (maxit < 0) return fail(HEXMG_ERR_INVALID, "bad maxit");
+  for (int i = 0; i < ngrids; ++i) {
+    if (!grids[i] || !f[i] || !u[i]) return fail(HEXMG_ERR_INVALID, "null grid or vector");
+    if (nrhs[i] < 1 || nrhs[i] > grids[i]->desc.max_nrhs)
+      return fail(HEXMG_ERR_INVALID, "nrhs[i] must be in [1, max_nrhs of grid i]");
+    if (!grids[i]->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded on every grid");
+    for (int j = 0; j < i; ++j)
+      if (grids[j] == grids[i]) return fail(HEXMG_ERR_INVALID, "a grid appears twice in the batch");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // Fork: each grid runs on a stream of its own (default priority), after the
+  // work already queued on the caller's stream; join at the end.
+  hipEvent_t fork = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(fork, s));
+  std::vector<PcgRun> runs(ngrids);
+  int e = 0, off = 0;
+  for (int i = 0; i < ngrids && !e; ++i) {
+    hexmg_grid* g = grids[i];
+    if (!g->own_stream && hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking) != hipSuccess)
+      e = fail(HEXMG_ERR_DEVICE, "stream creation failed");
+    if (!e && hipStreamWaitEvent(g->own_stream, fork, 0) != hipSuccess) e = fail(HEXMG_ERR_DEVICE, "stream wait failed");
+    PcgRun& r = runs[i];
+    r.g = g;
+    r.f = f[i];
+    r.u = u[i];
+    r.nb = nrhs[i];
+    r.rtol = rtol;
+    r.maxit = maxit;
+    r.s = g->own_stream;
+    r.info = infos ? infos + off : nullptr;
+    off += nrhs[i];
+    if (!e) e = r.init();
+  }
+  if (!e) e = drive(runs);
+  int worst = 0;
+  for (auto& r : runs) {
+    if (!e && r.s) {
+      if (hipEventRecord(r.ready, r.s) != hipSuccess || hipStreamWaitEvent(s, r.ready, 0) != hipSuccess)
+        e = fail(HEXMG_ERR_DEVICE, "join failed");
+    }
+    worst = combine_status(worst, r.status);
+  }
+  if (!e) (void)hipStreamSynchronize(s);
+  for (auto& r : runs) r.release();
+  (void)hipEventDestroy(fork);
+  if (e) return e;
+  if (worst == HEXMG_ERR_BREAKDOWN) return fail(worst, "PCG breakdown in the batch");
   if (worst == HEXMG_NOT_CONVERGED) g_err = "not converged within maxit";
   return worst;
 }
@@ -646,8 +841,8 @@ int hexmg_compliance_sensitivity(hexmg_grid_t g, const double* f, const double* 
                          k > 0, dc, s);
     }
     if (c_host) {
-      dot(g, N, f + k * N, u + k * N, g->scalars + kTmp, s);
-      if (int e = read_scalars(g, s)) return e;
+      dot(g, N, f + k * N, u + k * N, g->scalars + kTmp, 1, s);
+      if (int e = read_scalars(g, 1, s)) return e;
       c_host[k] = g->host_scalars[kTmp];
     }
   }

@@ -43,7 +43,7 @@ int stream_out_rows(bool f32, int shape);
 
 template <typename T>
 void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                   const T* wd, T* y, int zchunk, hipStream_t s);
+                   const T* wd, T* y, int zchunk, int nrhs, hipStream_t s);
 
 constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
 constexpr int kOcProbes = 32;       // Lagrange multipliers evaluated per OC pass
@@ -53,16 +53,16 @@ constexpr int kGJBlock = 64;  // pivot block of the blocked Gauss-Jordan inverse
 // ---- kernel launchers (kernels.hip) --------------------------------------
 template <typename T>
 void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
-                   const T* wdinv, T* y, hipStream_t s);
+                   const T* wdinv, T* y, int nrhs, hipStream_t s);
 // mode: 0 y = A u; 1 y = u + wdinv (f - A u); 2 y = f - A u
 enum { kApply = 0, kSmooth = 1, kResidual = 2 };
 
 template <typename T>
-void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, hipStream_t s);
+void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, hipStream_t s);
 template <typename T>
-void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, hipStream_t s);
+void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, hipStream_t s);
 template <typename T>
-void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, hipStream_t s);
+void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, hipStream_t s);
 
 void launch_simp(int ne, const double* rho, double E0, double Emin, double p, double scale,
                  double* E64, float* E32, double* rho_copy, int* bad_flags, hipStream_t s);
@@ -79,18 +79,20 @@ void launch_or_flags(int n, const int* flags, int* out, hipStream_t s);
 
 void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, double* A, hipStream_t s);
 template <typename T>
-void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, hipStream_t s);
+void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, hipStream_t s);
 
 // BLAS-1 in binary64 with deterministic two-stage reductions.
-void launch_dot_partial(long long n, const double* x, const double* y, double* partials, hipStream_t s);
-// out[0] = sum of partials[0..kReduceBlocks)
-void launch_reduce_final(const double* partials, double* out, hipStream_t s);
-// scalars: see ScalarSlot
-void launch_scalar_op(int op, double* sc, hipStream_t s);
-void launch_update_xr(long long n, const double* sc, const double* p, const double* q, double* x,
-                      double* r, double* partials, hipStream_t s);
-void launch_update_p(long long n, const double* sc, const double* z, double* p, hipStream_t s);
-void launch_mask_copy(const Level& L, const double* f, double* r, hipStream_t s);
+// All take nrhs vectors stored [nrhs][n]; partials are [nrhs][kReduceBlocks],
+// scalars [nrhs][kScalars].
+void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, hipStream_t s);
+// out[r * stride] = sum of partials[r][0..kReduceBlocks)
+void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s);
+void launch_scalar_op(int op, double* sc, int nrhs, hipStream_t s);
+void launch_update_xr(long long n, const double* sc, const int* active, const double* p, const double* q, double* x,
+                      double* r, double* partials, int nrhs, hipStream_t s);
+void launch_update_p(long long n, const double* sc, const int* active, const double* z, double* p, int nrhs,
+                     hipStream_t s);
+void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s);
 void launch_f64_to_f32(long long n, const double* a, float* b, hipStream_t s);
 void launch_f32_to_f64(long long n, const float* a, double* b, hipStream_t s);
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);
@@ -164,11 +166,14 @@ struct hexmg_grid {
   double* partials;
   double* scalars;
   int* flags;     // per-block status flags (kReduceBlocks) + 1 result
+  int* active;    // per right-hand side: 1 while its CG iteration runs
+  int* host_active;  // pinned mirror
   double* oc_partials;  // kReduceBlocks x kOcProbes
   double* oc_vol;       // kOcProbes
   double* host_scalars;  // pinned host mirror
   bool density_set;
   hipStream_t last_stream;
+  hipStream_t own_stream = nullptr;  // created on first use by a batched solve
   // profiling
   bool profile;
   struct Rec { int family; hipEvent_t a, b; };

@@ -53,6 +53,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(Level L, const T* __restrict_
                                                    const T* __restrict__ wdinv, T* __restrict__ y) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= L.nn) return;
+  {  // right-hand side blockIdx.y: vectors are [nrhs][3 nn]
+    const long long off = 3ll * L.nn * blockIdx.y;
+    u += off;
+    y += off;
+    if (MODE != kApply) f += off;
+  }
   int i, j, k;
   node_coords(L, n, i, j, k);
   T un[27][3];
@@ -126,7 +132,8 @@ template <typename T>
 __global__ void k_jacobi_first(long long n, const T* __restrict__ wdinv, const T* __restrict__ f,
                                T* __restrict__ u) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) u[i] = wdinv[i] * f[i];
+  const long long off = n * blockIdx.y;  // right-hand side
+  if (i < n) u[off + i] = wdinv[i] * f[off + i];
 }
 
 // Coarse right-hand side f_c = M_c P^T r: trilinear weights 1, 1/2 per axis.
@@ -134,6 +141,8 @@ template <typename T>
 __global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restrict__ fc) {
   const int m = blockIdx.x * kBlock + threadIdx.x;
   if (m >= C.nn) return;
+  r += 3ll * F.nn * blockIdx.y;  // right-hand side
+  fc += 3ll * C.nn * blockIdx.y;
   int I, J, K;
   node_coords(C, m, I, J, K);
   T s0 = 0, s1 = 0, s2 = 0;
@@ -167,6 +176,8 @@ template <typename T>
 __global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= F.nn) return;
+  ec += 3ll * C.nn * blockIdx.y;  // right-hand side
+  u += 3ll * F.nn * blockIdx.y;
   int i, j, k;
   node_coords(F, n, i, j, k);
   T s0 = 0, s1 = 0, s2 = 0;
@@ -410,6 +421,8 @@ __global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const T* _
   const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;  // uniform per wave
+  x += (long long)n * blockIdx.y;  // right-hand side
+  y += (long long)n * blockIdx.y;
   double s = 0.0;
   for (int c = lane; c < n; c += 64) s += Ainv[(long long)row * n + c] * (double)x[c];
   s = wave_sum(s);
@@ -420,6 +433,9 @@ __global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const T* _
 // PCG vector kernels (binary64).
 __global__ void k_dot_partial(long long n, const double* __restrict__ x, const double* __restrict__ y,
                               double* __restrict__ partials) {
+  x += n * blockIdx.y;  // right-hand side
+  y += n * blockIdx.y;
+  partials += (long long)kReduceBlocks * blockIdx.y;
   double s = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
     s += x[i] * y[i];
@@ -427,15 +443,19 @@ __global__ void k_dot_partial(long long n, const double* __restrict__ x, const d
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_reduce_final(const double* __restrict__ partials, double* __restrict__ out) {
+// block r: out[r * stride] = sum of partials[r][0 .. kReduceBlocks)
+__global__ void k_reduce_final(const double* __restrict__ partials, double* __restrict__ out, int stride) {
+  partials += (long long)kReduceBlocks * blockIdx.x;
   double s = 0.0;
   for (int i = threadIdx.x; i < kReduceBlocks; i += kBlock) s += partials[i];
   s = block_sum(s);
-  if (threadIdx.x == 0) out[0] = s;
+  if (threadIdx.x == 0) out[(long long)stride * blockIdx.x] = s;
 }
 
-__global__ void k_scalar_op(int op, double* __restrict__ sc) {
-  if (threadIdx.x != 0) return;
+__global__ void k_scalar_op(int op, int nrhs, double* __restrict__ sc) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  sc += kScalars * r;
   if (op == kOpAlpha) {
     sc[kAlpha] = sc[kRz] / sc[kPq];
   } else {
@@ -444,10 +464,22 @@ __global__ void k_scalar_op(int op, double* __restrict__ sc) {
   }
 }
 
-__global__ void k_update_xr(long long n, const double* __restrict__ sc, const double* __restrict__ p,
-                            const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
-                            double* __restrict__ partials) {
-  const double alpha = sc[kAlpha];
+// grid (kReduceBlocks, nrhs); right-hand sides with active[r] == 0 are left alone
+__global__ void k_update_xr(long long n, const double* __restrict__ sc, const int* __restrict__ active,
+                            const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
+                            double* __restrict__ r, double* __restrict__ partials) {
+  const int rhs = blockIdx.y;
+  const long long off = n * rhs;
+  p += off;
+  q += off;
+  x += off;
+  r += off;
+  partials += (long long)kReduceBlocks * rhs;
+  if (!active[rhs]) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const double alpha = sc[kScalars * rhs + kAlpha];
   double s = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     x[i] += alpha * p[i];
@@ -459,18 +491,22 @@ __global__ void k_update_xr(long long n, const double* __restrict__ sc, const do
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_update_p(long long n, const double* __restrict__ sc, const double* __restrict__ z,
-                           double* __restrict__ p) {
-  const double beta = sc[kBeta];
+__global__ void k_update_p(long long n, const double* __restrict__ sc, const int* __restrict__ active,
+                           const double* __restrict__ z, double* __restrict__ p) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const double beta = sc[kScalars * rhs + kBeta];
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = z[i] + beta * p[i];
+  const long long off = n * rhs;
+  if (i < n) p[off + i] = z[off + i] + beta * p[off + i];
 }
 
 __global__ void k_mask_copy(Level L, const double* __restrict__ f, double* __restrict__ r) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (i >= 3ll * L.nn) return;
+  const long long off = 3ll * L.nn * blockIdx.y;  // right-hand side
   const int n = (int)(i / 3), c = (int)(i % 3);
-  r[i] = ((L.mask[n] >> c) & 1) ? 0.0 : f[i];
+  r[off + i] = ((L.mask[n] >> c) & 1) ? 0.0 : f[off + i];
 }
 
 __global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* __restrict__ b) {
@@ -527,8 +563,8 @@ __global__ void k_sensitivity(Level L, const double* __restrict__ Ke, const doub
 // ---- launchers ------------------------------------------------------------
 template <typename T>
 void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
-                   const T* wdinv, T* y, hipStream_t s) {
-  const int g = blocks_for(L.nn);
+                   const T* wdinv, T* y, int nrhs, hipStream_t s) {
+  const dim3 g(blocks_for(L.nn), nrhs);
   if (mode == kApply)
     k_gather<T, kApply><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
   else if (mode == kSmooth)
@@ -537,30 +573,30 @@ void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u
     k_gather<T, kResidual><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
 }
 template void launch_gather<double>(int, const Level&, const double*, const double*, const double*,
-                                    const double*, const double*, double*, hipStream_t);
+                                    const double*, const double*, double*, int, hipStream_t);
 template void launch_gather<float>(int, const Level&, const float*, const float*, const float*,
-                                   const float*, const float*, float*, hipStream_t);
+                                   const float*, const float*, float*, int, hipStream_t);
 
 template <typename T>
-void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, hipStream_t s) {
-  k_jacobi_first<T><<<blocks_for(n), kBlock, 0, s>>>(n, wdinv, f, u);
+void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, hipStream_t s) {
+  k_jacobi_first<T><<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, wdinv, f, u);
 }
-template void launch_jacobi_first<double>(long long, const double*, const double*, double*, hipStream_t);
-template void launch_jacobi_first<float>(long long, const float*, const float*, float*, hipStream_t);
+template void launch_jacobi_first<double>(long long, const double*, const double*, double*, int, hipStream_t);
+template void launch_jacobi_first<float>(long long, const float*, const float*, float*, int, hipStream_t);
 
 template <typename T>
-void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, hipStream_t s) {
-  k_restrict<T><<<blocks_for(C.nn), kBlock, 0, s>>>(F, C, r, fc);
+void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, hipStream_t s) {
+  k_restrict<T><<<dim3(blocks_for(C.nn), nrhs), kBlock, 0, s>>>(F, C, r, fc);
 }
-template void launch_restrict<double>(const Level&, const Level&, const double*, double*, hipStream_t);
-template void launch_restrict<float>(const Level&, const Level&, const float*, float*, hipStream_t);
+template void launch_restrict<double>(const Level&, const Level&, const double*, double*, int, hipStream_t);
+template void launch_restrict<float>(const Level&, const Level&, const float*, float*, int, hipStream_t);
 
 template <typename T>
-void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, hipStream_t s) {
-  k_prolong_add<T><<<blocks_for(F.nn), kBlock, 0, s>>>(F, C, ec, u);
+void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, hipStream_t s) {
+  k_prolong_add<T><<<dim3(blocks_for(F.nn), nrhs), kBlock, 0, s>>>(F, C, ec, u);
 }
-template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, hipStream_t);
-template void launch_prolong_add<float>(const Level&, const Level&, const float*, float*, hipStream_t);
+template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, int, hipStream_t);
+template void launch_prolong_add<float>(const Level&, const Level&, const float*, float*, int, hipStream_t);
 
 void launch_simp(int ne, const double* rho, double E0, double Emin, double p, double scale,
                  double* E64, float* E32, double* rho_copy, int* bad_flags, hipStream_t s) {
@@ -611,29 +647,32 @@ void launch_symmetrize(int n, const double* A, double* B, hipStream_t s) {
   k_symmetrize<<<dim3(blocks_for(n), n), kBlock, 0, s>>>(n, A, B);
 }
 template <typename T>
-void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, hipStream_t s) {
+void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, hipStream_t s) {
   const int rows_per_block = kBlock / 64;
-  k_coarse_gemv<T><<<(n + rows_per_block - 1) / rows_per_block, kBlock, 0, s>>>(n, Ainv, x, y);
+  k_coarse_gemv<T><<<dim3((n + rows_per_block - 1) / rows_per_block, nrhs), kBlock, 0, s>>>(n, Ainv, x, y);
 }
-template void launch_coarse_gemv<double>(int, const double*, const double*, double*, hipStream_t);
-template void launch_coarse_gemv<float>(int, const double*, const float*, float*, hipStream_t);
+template void launch_coarse_gemv<double>(int, const double*, const double*, double*, int, hipStream_t);
+template void launch_coarse_gemv<float>(int, const double*, const float*, float*, int, hipStream_t);
 
-void launch_dot_partial(long long n, const double* x, const double* y, double* partials, hipStream_t s) {
-  k_dot_partial<<<kReduceBlocks, kBlock, 0, s>>>(n, x, y, partials);
+void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, hipStream_t s) {
+  k_dot_partial<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, x, y, partials);
 }
-void launch_reduce_final(const double* partials, double* out, hipStream_t s) {
-  k_reduce_final<<<1, kBlock, 0, s>>>(partials, out);
+void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s) {
+  k_reduce_final<<<nrhs, kBlock, 0, s>>>(partials, out, stride);
 }
-void launch_scalar_op(int op, double* sc, hipStream_t s) { k_scalar_op<<<1, 64, 0, s>>>(op, sc); }
-void launch_update_xr(long long n, const double* sc, const double* p, const double* q, double* x,
-                      double* r, double* partials, hipStream_t s) {
-  k_update_xr<<<kReduceBlocks, kBlock, 0, s>>>(n, sc, p, q, x, r, partials);
+void launch_scalar_op(int op, double* sc, int nrhs, hipStream_t s) {
+  k_scalar_op<<<1, ((nrhs + 63) / 64) * 64, 0, s>>>(op, nrhs, sc);
 }
-void launch_update_p(long long n, const double* sc, const double* z, double* p, hipStream_t s) {
-  k_update_p<<<blocks_for(n), kBlock, 0, s>>>(n, sc, z, p);
+void launch_update_xr(long long n, const double* sc, const int* active, const double* p, const double* q, double* x,
+                      double* r, double* partials, int nrhs, hipStream_t s) {
+  k_update_xr<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, active, p, q, x, r, partials);
 }
-void launch_mask_copy(const Level& L, const double* f, double* r, hipStream_t s) {
-  k_mask_copy<<<blocks_for(3ll * L.nn), kBlock, 0, s>>>(L, f, r);
+void launch_update_p(long long n, const double* sc, const int* active, const double* z, double* p, int nrhs,
+                     hipStream_t s) {
+  k_update_p<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, sc, active, z, p);
+}
+void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s) {
+  k_mask_copy<<<dim3(blocks_for(3ll * L.nn), nrhs), kBlock, 0, s>>>(L, f, r);
 }
 void launch_f64_to_f32(long long n, const double* a, float* b, hipStream_t s) {
   k_f64_to_f32<<<blocks_for(n), kBlock, 0, s>>>(n, a, b);

@@ -100,14 +100,21 @@ __device__ inline void block_product(const HaarCoef<T>& q, T E, const T (&v)[8][
 template <typename T, int MODE, int R, int W, int MINW>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
-                                                      const T* __restrict__ wg, T* __restrict__ yg, int zchunk) {
+                                                      const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
+                                                      int nchunks) {
+  {  // blockIdx.z = z-chunk + nchunks * right-hand side; vectors are [nrhs][3 nn]
+    const long long off = 3ll * L.nn * (blockIdx.z / nchunks);
+    ug += off;
+    yg += off;
+    if (MODE != kApply) fg += off;
+  }
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   constexpr int kOutRows = W * R - 2;
   const int i = blockIdx.x * 62 - 1 + lane;           // node column of this lane
   const int jt0 = blockIdx.y * kOutRows - 1;          // first (halo) row of the tile
   const int j0 = jt0 + w * R;                         // first row of this wave
-  const int kc0 = blockIdx.z * zchunk;
+  const int kc0 = (blockIdx.z % nchunks) * zchunk;
   const int kc1 = min(kc0 + zchunk, L.nzn);           // output planes [kc0, kc1)
   const bool lane_out = lane >= 1 && lane <= 62 && i < L.nxn;
   const bool col_in = i >= 0 && i < L.nxn;
@@ -356,16 +363,17 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 
 template <typename T, int R, int W, int MINW>
 void launch_stream_impl(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                        const T* wd, T* y, int zchunk, hipStream_t s) {
+                        const T* wd, T* y, int zchunk, int nrhs, hipStream_t s) {
   constexpr int kOutRows = W * R - 2;
-  dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, (L.nzn + zchunk - 1) / zchunk);
+  const int nchunks = (L.nzn + zchunk - 1) / zchunk;
+  dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
   dim3 block(64 * W);
   if (mode == kApply)
-    k_stream<T, kApply, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk);
+    k_stream<T, kApply, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk, nchunks);
   else if (mode == kSmooth)
-    k_stream<T, kSmooth, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk);
+    k_stream<T, kSmooth, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk, nchunks);
   else
-    k_stream<T, kResidual, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk);
+    k_stream<T, kResidual, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk, nchunks);
 }
 
 }  // namespace
@@ -382,24 +390,24 @@ int stream_out_rows(bool f32, int shape) {
 
 template <typename T>
 void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                   const T* wd, T* y, int zchunk, hipStream_t s) {
+                   const T* wd, T* y, int zchunk, int nrhs, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
     if (shape == 0)
-      launch_stream_impl<T, 2, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, s);
+      launch_stream_impl<T, 2, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
     else if (shape == 1)
-      launch_stream_impl<T, 3, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, s);
+      launch_stream_impl<T, 3, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
     else
-      launch_stream_impl<T, 4, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, s);
+      launch_stream_impl<T, 4, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
   } else {
     if (shape == 0)
-      launch_stream_impl<T, 1, 8, 2>(mode, L, q, E, u, f, wd, y, zchunk, s);
+      launch_stream_impl<T, 1, 8, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
     else
-      launch_stream_impl<T, 2, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, s);
+      launch_stream_impl<T, 2, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
   }
 }
 template void launch_stream<float>(int, int, const Level&, const HaarCoef<float>&, const float*, const float*,
-                                   const float*, const float*, float*, int, hipStream_t);
+                                   const float*, const float*, float*, int, int, hipStream_t);
 template void launch_stream<double>(int, int, const Level&, const HaarCoef<double>&, const double*, const double*,
-                                    const double*, const double*, double*, int, hipStream_t);
+                                    const double*, const double*, double*, int, int, hipStream_t);
 
 }  // namespace hexmg

@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
             "hexmg_vcycle": (i, [vp, i, vp, vp, i, vp]),
             "hexmg_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_compliance_sensitivity": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
+            "hexmg_batch_solve": (i, [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(i), d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_element_matrix": (i, [d, vp]),
             "hexmg_filter": (i, [i, i, i, d, i, vp, vp, vp, vp]),
             "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), vp]),
@@ -168,6 +170,31 @@ def density_filter(nx, ny, nz, rmin, x, out=None, adjoint=False, tmp=None, strea
                               _dev(out, torch.float64, n, "out"),
                               _dev(tmp, torch.float64, n, "tmp") if adjoint else None, _stream(stream)))
     return out
+
+
+def batch_solve(grids, fs, us, rtol=1e-6, maxit=500, stream=None, check=True):
+    """S15: solve grids[i] with right-hand sides fs[i] ([nrhs_i, N_i] or [N_i]) into us[i]
+    together.  Returns (status, list of per-grid info lists)."""
+    import torch
+
+    n = len(grids)
+    nr = [f.numel() // g.n_dof for g, f in zip(grids, fs)]
+    for g, f, u in zip(grids, fs, us):
+        if f.numel() % g.n_dof or u.shape != f.shape:
+            raise ValueError("f, u must be [nrhs, N] for their grid")
+    H = (ctypes.c_void_p * n)(*[g.handle.value for g in grids])
+    F = (ctypes.c_void_p * n)(*[_dev(f, torch.float64, name="f").value for f in fs])
+    U = (ctypes.c_void_p * n)(*[_dev(u, torch.float64, name="u").value for u in us])
+    R = (ctypes.c_int * n)(*nr)
+    infos = (SolveInfo * sum(nr))()
+    code = lib().hexmg_batch_solve(H, n, F, U, R, float(rtol), int(maxit), infos, _stream(stream))
+    if check:
+        _check(code, ok=(OK, NOT_CONVERGED))
+    out, k = [], 0
+    for m in nr:
+        out.append([infos[k + j].as_dict() for j in range(m)])
+        k += m
+    return code, out
 
 
 class Grid:
