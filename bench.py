@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--workload", default="cantilever_128x64x64_rf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ku-reps", type=int, default=20)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run 3 device copies of this many MiB (calibration for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -152,6 +154,13 @@ def main():
     mixed.apply_K(u64, y64)
     ms32 = time_events(lambda: mixed.apply_K(u32, y32), args.ku_reps, stream)
     ms64 = time_events(lambda: mixed.apply_K(u64, y64), args.ku_reps, stream)
+
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     avg_smooth_ms = ms_smooth / max(n_smooth, 1)
     sb = smooth_bytes_per_launch(g)
