@@ -33,22 +33,44 @@ def smooth_bytes_per_launch(g) -> float:
     return 16.0 * g.n_dof + 4.0 * g.n_elem + 1.0 * g.n_node
 
 
+# HBM bytes per launch of the level-0 binary32 Jacobi sweep, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes (each scaled by the same counter over a
+# device copy of known size), keyed by workload, kernel choice and a digest of
+# the kernel source they were taken on: any change to the kernel voids them.
+TRAFFIC = {
+}
+
+
+def stream_source_digest() -> str:
+    import hashlib
+
+    p = os.path.join(ROOT, "paper_2201_12931_amd", "csrc", "stream.hip")
+    with open(p, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_bytes(workload, choice):
+    key = (workload, choice[0], int(choice[1]), int(choice[2]), stream_source_digest())
+    return TRAFFIC.get(key)
+
+
 def apply_bytes(g, word) -> float:
     """Algorithmic bytes of y = K u: read u, write y, read E, read support bits."""
     return 2.0 * word * g.n_dof + word * g.n_elem + 1.0 * g.n_node
 
 
 def time_events(fn, reps, stream):
+    """Mean, median and minimum milliseconds of fn() over reps, from events on stream."""
     import torch
 
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(reps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for k in range(reps):
         fn()
-    b.record(stream)
-    b.synchronize()
-    return a.elapsed_time(b) / reps
+        ev[k + 1].record(stream)
+    ev[-1].synchronize()
+    t = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))
+    return ev[0].elapsed_time(ev[-1]) / reps, t[len(t) // 2], t[0]
 
 
 def cpu_baseline(name: str):
@@ -90,6 +112,9 @@ def main():
     ap.add_argument("--ku-reps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run 3 device copies of this many MiB (calibration for HBM byte counters)")
+    ap.add_argument("--l0-choice", default="", metavar="KIND:ZCHUNK:SHAPE",
+                    help="pin the level-0 binary32 kernel (KIND stream|gather) instead of the timed choice, "
+                         "e.g. for counter runs whose timings are perturbed by the profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -120,22 +145,35 @@ def main():
         c = grid.compliance_sensitivity(f_d, u_d, dc_d)
         return code, info[0], c[0]
 
+    mixed.set_density(rho_d)  # first success times the kernel variants
+    if args.l0_choice:
+        kind, zc, shape = args.l0_choice.split(":")
+        mixed.set_kernel_choice(0, hexmg.F32, hexmg.KERNEL_STREAM if kind == "stream" else hexmg.KERNEL_GATHER,
+                                int(zc), int(shape))
     for _ in range(args.warmup):
         step(mixed)
     torch.cuda.synchronize()
-    mixed.profile_enable(True)
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
         infos.append(step(mixed))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    code, info_mixed, c_mixed = infos[-1]
+
+    # Kernel durations: the same steps again with the library's per-launch
+    # timing on (events stamped by the level-0 dispatches themselves, on the
+    # stream they run on).  It is kept out of the timed steps above because the
+    # timed dispatches cost a few microseconds each.
+    mixed.profile_enable(True)
+    for _ in range(args.steps):
+        step(mixed)
+    torch.cuda.synchronize()
     n_smooth, ms_smooth = mixed.profile_query("smooth_f32")
     n_res, ms_res = mixed.profile_query("residual_f32")
     n_app, ms_app = mixed.profile_query("apply_f64")
     mixed.profile_enable(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    code, info_mixed, c_mixed = infos[-1]
 
     # plain binary64 form of the same step
     step(fp64)
@@ -152,8 +190,8 @@ def main():
     y64 = torch.empty_like(u64)
     mixed.apply_K(u32, y32)
     mixed.apply_K(u64, y64)
-    ms32 = time_events(lambda: mixed.apply_K(u32, y32), args.ku_reps, stream)
-    ms64 = time_events(lambda: mixed.apply_K(u64, y64), args.ku_reps, stream)
+    ms32, med32, min32 = time_events(lambda: mixed.apply_K(u32, y32), args.ku_reps, stream)
+    ms64, med64, min64 = time_events(lambda: mixed.apply_K(u64, y64), args.ku_reps, stream)
 
     if args.copy_probe:
         src = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -190,7 +228,8 @@ def main():
             "step": "set_density + mixed MGPCG to rtol + compliance/sensitivity",
         },
         "ku_gdofs": {"f32": g.n_dof / (ms32 * 1e-3) / 1e9, "f64": g.n_dof / (ms64 * 1e-3) / 1e9},
-        "ku_ms": {"f32": ms32, "f64": ms64},
+        "ku_ms": {"f32": ms32, "f64": ms64, "f32_median": med32, "f32_min": min32, "f64_median": med64,
+                  "f64_min": min64},
         "ku_hbm_frac": {"f32": apply_bytes(g, 4) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "f64": apply_bytes(g, 8) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "solve_s": {"mixed": info_mixed["ms_solve"] * 1e-3, "fp64": info64["ms_solve"] * 1e-3},
@@ -208,9 +247,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_bytes(args.workload, choices["L0"]["f32"]),
             "avg_launch_ms": avg_smooth_ms,
             "bytes_per_launch": sb,
+            "timing": "per-dispatch HIP events over %d untimed repeats of the step" % args.steps,
         },
     }
     if not args.no_cpu_baseline:

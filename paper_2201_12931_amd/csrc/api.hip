@@ -1,6 +1,7 @@
 // C ABI of the hexmg library: grid set-up, K u, V-cycle, MGPCG solve,
 // compliance and sensitivity.  Host orchestration only; all arithmetic of the
 // hot path runs in the kernels of kernels.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -135,6 +136,7 @@ size_t carve(hexmg_grid* g, char* base) {
   g->p = c.take<double>(N0 * R);
   g->q = c.take<double>(N0 * R);
   g->partials = c.take<double>(kReduceBlocks * R);
+  g->partials2 = c.take<double>(kReduceBlocks * R);
   g->scalars = c.take<double>(kScalars * R);
   g->flags = c.take<int>(kReduceBlocks + 1);
   g->active = c.take<int>(R);
@@ -170,18 +172,21 @@ int stream_zchunk(const Level& L, bool f32, int shape) {
   return (int)zc;
 }
 
+// maskin: u may be non-zero at fixed DOFs (the public K u); every vector
+// inside the solver is zero there, so the streaming kernel can skip masking it.
 template <typename T>
 void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
-                   const T* wd, T* y, int nrhs, hipStream_t s) {
+                   const T* wd, T* y, int nrhs, hipStream_t s, bool maskin = false, const int* act = nullptr,
+                   const LaunchTimer& t = {}) {
   const bool f32 = sizeof(T) == 4;
   const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
   const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
   const Level& L = g->lv[level];
   if (ch.kernel == HEXMG_KERNEL_GATHER) {
-    launch_gather<T>(mode, L, Ke, E, u, f, wd, y, nrhs, s);
+    launch_gather<T>(mode, L, Ke, E, u, f, wd, y, nrhs, act, s, t);
   } else {
     const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
-    launch_stream<T>(mode, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, nrhs, s);
+    launch_stream<T>(mode, maskin, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, nrhs, act, s, t);
   }
 }
 
@@ -238,20 +243,33 @@ int tune_kernels(hexmg_grid* g, hipStream_t s) {
 
 template <typename T>
 void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, int nrhs,
-            hipStream_t s) {
+            hipStream_t s, bool maskin = false, const int* act = nullptr) {
   const bool f32 = sizeof(T) == 4;
   hipEvent_t a = nullptr, b = nullptr;
   const bool prof = g->profile && level == 0;
   if (prof) {
     a = take_event(g);
     b = take_event(g);
-    if (a && b) (void)hipEventRecord(a, s);
   }
-  launch_choice<T>(g, f32 ? g->choice32[level] : g->choice64[level], mode, level, u, f, wd, y, nrhs, s);
-  if (prof && a && b) {
-    (void)hipEventRecord(b, s);
-    g->recs.push_back({family_of(mode, f32), a, b});
+  LaunchTimer t;
+  if (a && b) t = LaunchTimer{a, b};
+  launch_choice<T>(g, f32 ? g->choice32[level] : g->choice64[level], mode, level, u, f, wd, y, nrhs, s, maskin, act,
+                   t);
+  if (a && b) g->recs.push_back({family_of(mode, f32), a, b, g->prof_tag});
+}
+
+// drops the records of launches tagged with a CG iteration beyond last_its
+void prune_profile(hexmg_grid* g, int last_its) {
+  std::vector<hexmg_grid::Rec> keep;
+  for (auto& r : g->recs) {
+    if (r.tag > last_its) {
+      g->event_pool.push_back(r.a);
+      g->event_pool.push_back(r.b);
+    } else {
+      keep.push_back(r);
+    }
   }
+  g->recs.swap(keep);
 }
 
 void drain_profile(hexmg_grid* g) {
@@ -288,50 +306,66 @@ VView<float> view32(hexmg_grid* g) {
 
 // out = V_l(f) from a zero initial guess.  The first sweep writes the level's
 // scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
-// in `out` without a copy.  f and out must not overlap.
+// in `out` without a copy.  f and out must not overlap.  With first_done the
+// caller has already written the first sweep (omega D^-1 f) into the scratch
+// vector.  act: per right-hand side skip flags (may be null).
 template <typename T>
-void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrhs, hipStream_t s) {
+void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrhs, const int* act, hipStream_t s,
+                  bool first_done = false) {
   const Level& L = g->lv[l];
   if (l == g->L - 1) {
-    launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, nrhs, s);
+    launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, nrhs, act, s);
     return;
   }
   const long long N = 3ll * L.nn;
   const int nu = g->desc.smooth_sweeps;
   T* buf[2] = {v.t[l], out};
   int cur = 0;
-  launch_jacobi_first<T>(N, v.wd[l], f, buf[0], nrhs, s);
+  if (!first_done) launch_jacobi_first<T>(N, v.wd[l], f, buf[0], nrhs, act, s);
   for (int it = 1; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, false, act);
     cur = 1 - cur;
   }
-  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], nrhs, s);
-  launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], nrhs, s);
-  vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, s);
-  launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, s);
+  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], nrhs, s, false, act);
+  // the next level's first sweep is formed inside the restriction (not on the coarsest level)
+  const bool fuse = l + 1 < g->L - 1;
+  launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], nrhs, act, s, fuse ? v.wd[l + 1] : nullptr,
+                     fuse ? v.t[l + 1] : nullptr);
+  vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, act, s, fuse);
+  launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, act, s);
   for (int it = 0; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, false, act);
     cur = 1 - cur;
   }
 }
 
-// z = V(r) in the grid's precision for nrhs <= max_nrhs binary64 right-hand sides.
-void precondition(hexmg_grid* g, const double* r, double* z, int nrhs, hipStream_t s) {
+// z = V(r) in the grid's precision for nrhs <= max_nrhs binary64 right-hand
+// sides, plus the partial sums of r . z.  In mixed precision the binary32
+// right-hand side is formed inside the first sweep and z is widened inside the
+// dot product.
+void precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials, int nrhs, const int* act,
+                  hipStream_t s) {
   const long long N = 3ll * g->lv[0].nn;
   if (g->desc.precision == HEXMG_FP64) {
     VView<double> v = view64(g);
-    vcycle_level<double>(g, v, 0, r, z, nrhs, s);
+    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s);
+    launch_dot_partial(N, r, z, rz_partials, nrhs, act, s);
   } else {
     VView<float> v = view32(g);
-    launch_f64_to_f32(N * nrhs, r, g->vf32[0], s);
-    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, s);
-    launch_f32_to_f64(N * nrhs, g->vu32[0], z, s);
+    if (g->L == 1) {  // the coarsest level is the whole grid: no sweep to fuse into
+      launch_f64_to_f32(N, r, g->vf32[0], nrhs, act, s);
+      vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s);
+    } else {
+      launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
+      vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s, true);
+    }
+    launch_to64_dot(N, g->vu32[0], r, z, rz_partials, nrhs, act, s);
   }
 }
 
 // out[r * kScalars] = x_r . y_r for each right-hand side r
 void dot(hexmg_grid* g, long long n, const double* x, const double* y, double* out, int nrhs, hipStream_t s) {
-  launch_dot_partial(n, x, y, g->partials, nrhs, s);
+  launch_dot_partial(n, x, y, g->partials, nrhs, nullptr, s);
   launch_reduce_final(g->partials, out, kScalars, nrhs, s);
 }
 
@@ -339,12 +373,6 @@ int read_scalars(hexmg_grid* g, int nrhs, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(g->host_scalars, g->scalars, (size_t)kScalars * nrhs * sizeof(double),
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  return 0;
-}
-
-int write_active(hexmg_grid* g, const int* act, int nrhs, hipStream_t s) {
-  for (int k = 0; k < nrhs; ++k) g->host_active[k] = act[k];
-  HIP_TRY(hipMemcpyAsync(g->active, g->host_active, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
   return 0;
 }
 
@@ -427,10 +455,10 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   };
   {
     const size_t nsc = (size_t)kScalars * (d->max_nrhs > 8 ? d->max_nrhs : 8);
-    if (hipHostMalloc((void**)&g->host_scalars, nsc * sizeof(double) + d->max_nrhs * sizeof(int),
-                      hipHostMallocDefault) != hipSuccess)
+    const size_t nring = 3ull * kScalars * d->max_nrhs;
+    if (hipHostMalloc((void**)&g->host_scalars, (nsc + nring) * sizeof(double), hipHostMallocDefault) != hipSuccess)
       return cleanup(fail(HEXMG_ERR_DEVICE, "pinned host allocation failed"));
-    g->host_active = reinterpret_cast<int*>(g->host_scalars + nsc);
+    g->host_ring = g->host_scalars + nsc;
   }
   if (!haar_coefficients(d->nu, &g->hq64))
     return cleanup(fail(HEXMG_ERR_INVALID, "element stiffness does not have the expected Haar block pattern"));
@@ -467,7 +495,7 @@ int hexmg_grid_destroy(hexmg_grid_t g) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
-  for (auto e : g->event_pool) hipEventDestroy(e);
+  for (auto e : g->event_pool) (void)hipEventDestroy(e);
   if (g->host_scalars) (void)hipHostFree(g->host_scalars);
   delete g;
   return 0;
@@ -522,9 +550,9 @@ int hexmg_apply_K(hexmg_grid_t g, int level, int dtype, const void* u, void* y, 
   g->last_stream = s;
   if (nrhs > 65535) return fail(HEXMG_ERR_INVALID, "nrhs must be <= 65535");
   if (dtype == HEXMG_F64)
-    gather<double>(g, kApply, level, (const double*)u, nullptr, nullptr, (double*)y, nrhs, s);
+    gather<double>(g, kApply, level, (const double*)u, nullptr, nullptr, (double*)y, nrhs, s, true);
   else if (dtype == HEXMG_F32)
-    gather<float>(g, kApply, level, (const float*)u, nullptr, nullptr, (float*)y, nrhs, s);
+    gather<float>(g, kApply, level, (const float*)u, nullptr, nullptr, (float*)y, nrhs, s, true);
   else
     return fail(HEXMG_ERR_INVALID, "bad dtype");
   HIP_TRY(hipGetLastError());
@@ -544,10 +572,10 @@ int hexmg_vcycle(hexmg_grid_t g, int dtype, const void* r, void* z, int nrhs, vo
     const int nb = (nrhs - k) < g->desc.max_nrhs ? (nrhs - k) : g->desc.max_nrhs;
     if (dtype == HEXMG_F64) {
       VView<double> v = view64(g);
-      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, nb, s);
+      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, nb, nullptr, s);
     } else {
       VView<float> v = view32(g);
-      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, nb, s);
+      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, nb, nullptr, s);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -558,13 +586,13 @@ int hexmg_vcycle(hexmg_grid_t g, int dtype, const void* r, void* z, int nrhs, vo
 
 namespace {
 
-// PCG (Alg. 1) for nb <= max_nrhs right-hand sides of one grid in lockstep,
-// written as a resumable state machine so that several grids can advance
-// together: each call of advance() consumes the scalars the previous phase
-// copied to the host, decides, and enqueues the next phase on the run's stream
-// (ending with an asynchronous copy of the new scalars and an event).  Every
-// kernel covers all nb right-hand sides; one that has converged (or broken
-// down) is frozen through the device `active` flags.
+// PCG (Alg. 1) for nb <= max_nrhs right-hand sides of one grid in lockstep.
+// The CG scalars, the convergence test and the iteration counts live on the
+// device (see ScalarSlot): every kernel skips right-hand sides whose active
+// flag has been cleared, so the host can keep one iteration in flight while it
+// reads the state of the previous one from a ring of three pinned slots.  The
+// run is a resumable state machine so that several grids can advance together:
+// advance() is called once wait_event() has completed.
 struct PcgRun {
   hexmg_grid* g = nullptr;
   const double* f = nullptr;
@@ -574,137 +602,125 @@ struct PcgRun {
   int maxit = 0;
   hipStream_t s = nullptr;
   hexmg_solve_info* info = nullptr;
-  hipEvent_t ready = nullptr, t0 = nullptr, t1 = nullptr;
-  enum Phase { kSetup, kIterate, kFinish, kDone } phase = kSetup;
-  std::vector<double> ff, rr;
-  std::vector<int> st, its, act;
-  int nact = 0, it = 0, status = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+  enum Phase { kIterate, kFinish, kDone } phase = kIterate;
+  int issued = 0, target = 0, final_slot = 0, status = 0;
 
   int init() {
-    ff.assign(nb, 0.0);
-    rr.assign(nb, 0.0);
-    st.assign(nb, HEXMG_NOT_CONVERGED);
-    its.assign(nb, 0);
-    act.assign(nb, 0);
-    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIP_TRY(hipEventCreate(&t0));
     HIP_TRY(hipEventCreate(&t1));
     return 0;
   }
   void release() {
-    if (ready) (void)hipEventDestroy(ready);
+    if (g) g->prof_tag = 0;
+    for (auto& e : ev) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
-    ready = t0 = t1 = nullptr;
+    t0 = t1 = nullptr;
   }
   long long N() const { return 3ll * g->lv[0].nn; }
-  int post_scalars() {
-    HIP_TRY(hipMemcpyAsync(g->host_scalars, g->scalars, (size_t)kScalars * nb * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(ready, s));
+  double* slot(int k) const { return g->host_ring + (size_t)(k % 3) * kScalars * g->desc.max_nrhs; }
+  hipEvent_t wait_event() const { return ev[(phase == kFinish ? final_slot : target) % 3]; }
+  int post(int k) {
+    HIP_TRY(hipMemcpyAsync(slot(k), g->scalars, (size_t)kScalars * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ev[k % 3], s));
     return 0;
+  }
+  // iteration k (1-based): q = A p, alpha, x and r updates, ||r||^2 and the test
+  int issue_iteration(int k) {
+    double* sc = g->scalars;
+    g->prof_tag = k;
+    gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active);
+    launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
+    launch_update_xr(N(), g->partials, sc, g->active, g->p, g->q, u, g->r, g->partials2, (k - 1) & 1, nb, s);
+    launch_rr_check(g->partials2, sc, g->active, nb, s);
+    issued = k;
+    return post(k);
+  }
+  // z = M^{-1} r, beta, p = z + beta p (after iteration k), then iteration k+1
+  int issue_next() {
+    const int k = issued;
+    g->prof_tag = k + 1;
+    precondition(g, g->r, g->z, g->partials, nb, g->active, s);
+    launch_update_p(N(), g->partials, g->scalars, g->active, g->z, g->p, (k - 1) & 1, nb, s);
+    return issue_iteration(k + 1);
   }
   int begin() {
     const Level& L0 = g->lv[0];
+    double* sc = g->scalars;
     HIP_TRY(hipEventRecord(t0, s));
     launch_mask_copy(L0, f, g->r, nb, s);  // r0 = M f
     launch_fill(N() * nb, 0.0, u, s);      // x0 = 0
-    dot(g, N(), g->r, g->r, g->scalars + kFf, nb, s);
-    phase = kSetup;
-    return post_scalars();
+    dot(g, N(), g->r, g->r, sc + kFf, nb, s);
+    launch_pcg_init(rtol > 0.0 ? rtol * rtol : -1.0, sc, g->active, nb, s);
+    if (maxit == 0) return enqueue_finish(0);
+    g->prof_tag = 1;
+    precondition(g, g->r, g->z, g->partials, nb, g->active, s);  // z0 = M^{-1} r0
+    launch_reduce_final(g->partials, sc + kRz0, kScalars, nb, s);
+    HIP_TRY(hipMemcpyAsync(g->p, g->z, N() * nb * sizeof(double), hipMemcpyDeviceToDevice, s));  // p0 = z0
+    if (int e = issue_iteration(1)) return e;
+    if (maxit >= 2)
+      if (int e = issue_next()) return e;
+    target = 1;
+    phase = kIterate;
+    return 0;
   }
-  // q = A p, alpha, x and r updates, ||r||^2
-  int enqueue_iteration() {
-    double* sc = g->scalars;
-    gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s);
-    dot(g, N(), g->p, g->q, sc + kPq, nb, s);
-    launch_scalar_op(kOpAlpha, sc, nb, s);
-    launch_update_xr(N(), sc, g->active, g->p, g->q, u, g->r, g->partials, nb, s);
-    launch_reduce_final(g->partials, sc + kRr, kScalars, nb, s);
-    return post_scalars();
-  }
-  int enqueue_finish() {
+  int enqueue_finish(int read) {
     const Level& L0 = g->lv[0];
     double* sc = g->scalars;
     HIP_TRY(hipEventRecord(t1, s));
+    g->prof_tag = 0;
     gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s);  // true residual in binary64
     launch_mask_copy(L0, f, g->z, nb, s);
     launch_sub(N() * nb, g->z, g->q, g->z, s);
     dot(g, N(), g->z, g->z, sc + kTmp, nb, s);
-    dot(g, N(), f, u, sc + kRzNew, nb, s);
+    dot(g, N(), f, u, sc + kTmp2, nb, s);
+    final_slot = read + 2;  // a slot no result in flight is written to
     phase = kFinish;
-    return post_scalars();
+    return post(final_slot);
   }
-  // Called once `ready` has completed.
   int advance() {
-    const double* hs = g->host_scalars;
-    double* sc = g->scalars;
-    if (phase == kSetup) {
-      nact = 0;
-      for (int k = 0; k < nb; ++k) {
-        ff[k] = hs[k * kScalars + kFf];
-        rr[k] = ff[k];
-        if (!std::isfinite(ff[k])) return fail(HEXMG_ERR_NONFINITE, "load vector is not finite");
-        act[k] = ff[k] > 0.0;
-        if (!act[k]) st[k] = HEXMG_OK;
-        nact += act[k];
-      }
-      if (!nact || maxit == 0) return enqueue_finish();
-      if (int e = write_active(g, act.data(), nb, s)) return e;
-      precondition(g, g->r, g->z, nb, s);  // z0 = M^{-1} r0
-      dot(g, N(), g->r, g->z, sc + kRz, nb, s);
-      HIP_TRY(hipMemcpyAsync(g->p, g->z, N() * nb * sizeof(double), hipMemcpyDeviceToDevice, s));  // p0 = z0
-      phase = kIterate;
-      it = 0;
-      return enqueue_iteration();
-    }
     if (phase == kIterate) {
-      ++it;
-      bool changed = false;
-      for (int k = 0; k < nb; ++k) {
-        if (!act[k]) continue;
-        ++its[k];
-        rr[k] = hs[k * kScalars + kRr];
-        const double pq = hs[k * kScalars + kPq];
-        const double stop = (rtol > 0.0) ? rtol * rtol * ff[k] : -1.0;
-        if (!(pq > 0.0) || !std::isfinite(rr[k]))
-          st[k] = HEXMG_ERR_BREAKDOWN;
-        else if (rr[k] <= stop)
-          st[k] = HEXMG_OK;
-        else
-          continue;
-        act[k] = 0;
-        --nact;
-        changed = true;
-      }
-      if (!nact || it >= maxit) return enqueue_finish();
-      if (changed)
-        if (int e = write_active(g, act.data(), nb, s)) return e;
-      precondition(g, g->r, g->z, nb, s);   // z = M^{-1} r
-      dot(g, N(), g->r, g->z, sc + kRzNew, nb, s);
-      launch_scalar_op(kOpBeta, sc, nb, s);  // beta = r^T z / r_old^T z_old
-      launch_update_p(N(), sc, g->active, g->z, g->p, nb, s);  // p = z + beta p
-      return enqueue_iteration();
+      const double* h = slot(target);
+      int nact = 0;
+      for (int k = 0; k < nb; ++k) nact += h[k * kScalars + kActive] != 0.0;
+      if (nact == 0 || target >= maxit) return enqueue_finish(target);
+      if (issued < maxit)
+        if (int e = issue_next()) return e;
+      ++target;
+      return 0;
     }
     // kFinish
+    const double* h = slot(final_slot);
     HIP_TRY(hipGetLastError());
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, t0, t1);
     status = 0;
+    int last_its = 0;
+    for (int k = 0; k < nb; ++k) last_its = std::max(last_its, (int)h[k * kScalars + kIts]);
+    prune_profile(g, last_its);
     for (int k = 0; k < nb; ++k) {
+      const double* q = h + k * kScalars;
+      const int st = (int)q[kStatus];
+      const double ff = q[kFf];
       if (info) {
         hexmg_solve_info& in = info[k];
-        in.iterations = its[k];
-        in.status = st[k];
-        in.rel_res_recursive = ff[k] > 0 ? std::sqrt(rr[k] / ff[k]) : 0.0;
-        in.rel_res_true = ff[k] > 0 ? std::sqrt(hs[k * kScalars + kTmp] / ff[k]) : 0.0;
-        in.compliance = hs[k * kScalars + kRzNew];
+        in.iterations = (int)q[kIts];
+        in.status = st;
+        in.rel_res_recursive = ff > 0 ? std::sqrt(q[kRr] / ff) : 0.0;
+        in.rel_res_true = ff > 0 ? std::sqrt(q[kTmp] / ff) : 0.0;
+        in.compliance = q[kTmp2];
         in.ms_solve = ms;
       }
-      if (st[k] < 0)
-        status = st[k];
-      else if (status >= 0 && st[k] > status)
-        status = st[k];
+      if (st == -4) return fail(HEXMG_ERR_NONFINITE, "load vector is not finite");
+      if (st < 0)
+        status = st;
+      else if (status >= 0 && st > status)
+        status = st;
     }
     phase = kDone;
     return 0;
@@ -721,7 +737,7 @@ int drive(std::vector<PcgRun>& runs) {
     for (auto& r : runs) {
       if (r.phase == PcgRun::kDone) continue;
       pending = true;
-      HIP_TRY(hipEventSynchronize(r.ready));
+      HIP_TRY(hipEventSynchronize(r.wait_event()));
       if (int e = r.advance()) return e;
     }
     if (!pending) return 0;
@@ -810,7 +826,7 @@ int hexmg_batch_solve(hexmg_grid_t* grids, int ngrids, const double* const* f, d
   int worst = 0;
   for (auto& r : runs) {
     if (!e && r.s) {
-      if (hipEventRecord(r.ready, r.s) != hipSuccess || hipStreamWaitEvent(s, r.ready, 0) != hipSuccess)
+      if (hipEventRecord(r.ev[0], r.s) != hipSuccess || hipStreamWaitEvent(s, r.ev[0], 0) != hipSuccess)
         e = fail(HEXMG_ERR_DEVICE, "join failed");
     }
     worst = combine_status(worst, r.status);

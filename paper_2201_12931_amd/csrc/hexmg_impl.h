@@ -1,6 +1,7 @@
 // Internal declarations of the hexmg library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -41,9 +42,28 @@ bool haar_coefficients(double nu, HaarCoef<double>* q);
 int stream_shapes(bool f32);
 int stream_out_rows(bool f32, int shape);
 
+// maskin: u may be non-zero at fixed DOFs (masked on load); otherwise the
+// caller guarantees u = 0 there (every vector inside the solver).
+// Optional timing of one launch: with both events set, the kernel is launched
+// with hipExtLaunchKernelGGL, which stamps the events at the start and the end
+// of the dispatch itself (the interval a kernel trace reports).
+struct LaunchTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <typename... KArgs, typename... Args>
+void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, const LaunchTimer& t,
+                  Args... args) {
+  if (t.start && t.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.start, t.stop, 0, static_cast<KArgs>(args)...);
+  else
+    kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
+}
+
 template <typename T>
-void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                   const T* wd, T* y, int zchunk, int nrhs, hipStream_t s);
+void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
+                   const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
+                   const LaunchTimer& t = {});
 
 constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
 constexpr int kOcProbes = 32;       // Lagrange multipliers evaluated per OC pass
@@ -51,18 +71,25 @@ constexpr int kBlock = 256;
 constexpr int kGJBlock = 64;  // pivot block of the blocked Gauss-Jordan inverse
 
 // ---- kernel launchers (kernels.hip) --------------------------------------
+// `act` (device, one int per right-hand side, may be null): right-hand sides
+// whose flag is 0 are skipped by every kernel that takes it.
 template <typename T>
 void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
-                   const T* wdinv, T* y, int nrhs, hipStream_t s);
+                   const T* wdinv, T* y, int nrhs, const int* act, hipStream_t s,
+                   const LaunchTimer& t = {});
 // mode: 0 y = A u; 1 y = u + wdinv (f - A u); 2 y = f - A u
 enum { kApply = 0, kSmooth = 1, kResidual = 2 };
 
 template <typename T>
-void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, hipStream_t s);
+void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, const int* act, hipStream_t s);
+// binary32 first sweep from a binary64 right-hand side: f32 = (float) r, u = wdinv f32
+void launch_jacobi_first_from64(long long n, const float* wdinv, const double* r, float* f32, float* u, int nrhs,
+                                const int* act, hipStream_t s);
 template <typename T>
-void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, hipStream_t s);
+void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, const int* act, hipStream_t s,
+                     const T* wdc = nullptr, T* tc = nullptr);
 template <typename T>
-void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, hipStream_t s);
+void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, const int* act, hipStream_t s);
 
 void launch_simp(int ne, const double* rho, double E0, double Emin, double p, double scale,
                  double* E64, float* E32, double* rho_copy, int* bad_flags, hipStream_t s);
@@ -79,22 +106,32 @@ void launch_or_flags(int n, const int* flags, int* out, hipStream_t s);
 
 void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, double* A, hipStream_t s);
 template <typename T>
-void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, hipStream_t s);
+void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, const int* act, hipStream_t s);
 
 // BLAS-1 in binary64 with deterministic two-stage reductions.
 // All take nrhs vectors stored [nrhs][n]; partials are [nrhs][kReduceBlocks],
 // scalars [nrhs][kScalars].
-void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, hipStream_t s);
+void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, const int* act,
+                        hipStream_t s);
 // out[r * stride] = sum of partials[r][0..kReduceBlocks)
 void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s);
-void launch_scalar_op(int op, double* sc, int nrhs, hipStream_t s);
-void launch_update_xr(long long n, const double* sc, const int* active, const double* p, const double* q, double* x,
-                      double* r, double* partials, int nrhs, hipStream_t s);
-void launch_update_p(long long n, const double* sc, const int* active, const double* z, double* p, int nrhs,
-                     hipStream_t s);
+// CG steps with the scalars computed on the device (see ScalarSlot):
+// init: active = (ff > 0), its = 0, stop = rtol^2 ff (rtol2 <= 0: never)
+void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s);
+// alpha = rz[parity] / (sum of pq partials); x += alpha p; r -= alpha q; rr partials
+void launch_update_xr(long long n, const double* pq_partials, double* sc, const int* active, const double* p,
+                      const double* q, double* x, double* r, double* rr_partials, int parity, int nrhs, hipStream_t s);
+// rr = sum of partials; its += 1; convergence / breakdown clears active
+void launch_rr_check(const double* rr_partials, double* sc, int* active, int nrhs, hipStream_t s);
+// rz_new = sum of rz partials; beta = rz_new / rz[parity]; p = z + beta p; rz[1-parity] = rz_new
+void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const double* z,
+                     double* p, int parity, int nrhs, hipStream_t s);
+// z64 = (double) u32 and partials of r . z64
+void launch_to64_dot(long long n, const float* u32, const double* r, double* z, double* partials, int nrhs,
+                     const int* act, hipStream_t s);
 void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s);
-void launch_f64_to_f32(long long n, const double* a, float* b, hipStream_t s);
-void launch_f32_to_f64(long long n, const float* a, double* b, hipStream_t s);
+void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s);
+void launch_f32_to_f64(long long n, const float* a, double* b, int nrhs, const int* act, hipStream_t s);
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);
 void launch_fill(long long n, double v, double* x, hipStream_t s);
 
@@ -118,18 +155,25 @@ void launch_oc_apply(long long n, const double* x, const double* dc, const doubl
                      double lam_pow, double* xn, hipStream_t s);
 
 // Device scalar slots used by the PCG (one block of kScalars doubles).
+// Per right-hand side, in this order, kScalars doubles each.  The CG state
+// lives on the device: the convergence test runs in a kernel, and the host
+// only reads copies of these slots.
 enum ScalarSlot {
-  kRz = 0,      // r^T z (current)
-  kPq = 1,      // p^T A p
-  kRr = 2,      // r^T r
-  kAlpha = 3,
-  kBeta = 4,
-  kRzNew = 5,
-  kFf = 6,      // ||M f||^2
-  kTmp = 7,
-  kScalars = 8
+  kRz0 = 0,      // r^T z, double-buffered by iteration parity (kRz0 + parity)
+  kRz1 = 1,
+  kPq = 2,       // p^T A p of the last iteration
+  kRr = 3,       // r^T r of the last iteration
+  kAlpha = 4,
+  kBeta = 5,
+  kFf = 6,       // ||M f||^2
+  kStop = 7,     // rtol^2 ||M f||^2 (-1: never)
+  kIts = 8,      // iterations taken
+  kStatus = 9,   // 1 running / not converged, 0 converged, -5 breakdown, -4 non-finite load
+  kActive = 10,  // copy of the device active flag
+  kTmp = 11,
+  kTmp2 = 12,
+  kScalars = 16
 };
-enum ScalarOp { kOpAlpha = 0, kOpBeta = 1 };
 
 }  // namespace hexmg
 
@@ -164,10 +208,11 @@ struct hexmg_grid {
   // PCG
   double *r, *z, *p, *q;
   double* partials;
+  double* partials2;
   double* scalars;
   int* flags;     // per-block status flags (kReduceBlocks) + 1 result
   int* active;    // per right-hand side: 1 while its CG iteration runs
-  int* host_active;  // pinned mirror
+  double* host_ring;  // pinned: 3 slots of kScalars * max_nrhs doubles (results in flight)
   double* oc_partials;  // kReduceBlocks x kOcProbes
   double* oc_vol;       // kOcProbes
   double* host_scalars;  // pinned host mirror
@@ -176,8 +221,12 @@ struct hexmg_grid {
   hipStream_t own_stream = nullptr;  // created on first use by a batched solve
   // profiling
   bool profile;
-  struct Rec { int family; hipEvent_t a, b; };
+  // tag: the CG iteration a launch belongs to (0: not part of one); launches of
+  // an iteration issued ahead of the convergence test that found nothing left
+  // to do are dropped from the counts when the solve ends
+  struct Rec { int family; hipEvent_t a, b; int tag; };
   std::vector<Rec> recs;
+  int prof_tag = 0;
   std::vector<hipEvent_t> event_pool;
   double prof_ms[8];
   int prof_count[8];

@@ -38,6 +38,31 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
+// Sum over a block of kBlock threads, returned to every thread (fixed order).
+__device__ inline double block_sum_all(double v) {
+  __shared__ double part[kBlock / 64];
+  __shared__ double total;
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s += part[i];
+    total = s;
+  }
+  __syncthreads();
+  return total;
+}
+
+// sum of the kReduceBlocks partials of one right-hand side, in every thread
+__device__ inline double sum_partials(const double* __restrict__ partials) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kReduceBlocks; i += kBlock) s += partials[i];
+  return block_sum_all(s);
+}
+
 inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 // ---------------------------------------------------------------------------
@@ -50,9 +75,10 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gather(Level L, const T* __restrict__ Ke,
                                                    const T* __restrict__ E, const T* __restrict__ u,
                                                    const T* __restrict__ f,
-                                                   const T* __restrict__ wdinv, T* __restrict__ y) {
+                                                   const T* __restrict__ wdinv, T* __restrict__ y,
+                                                   const int* __restrict__ act) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= L.nn) return;
+  if (n >= L.nn || (act && !act[blockIdx.y])) return;
   {  // right-hand side blockIdx.y: vectors are [nrhs][3 nn]
     const long long off = 3ll * L.nn * blockIdx.y;
     u += off;
@@ -130,17 +156,33 @@ __global__ __launch_bounds__(kBlock) void k_gather(Level L, const T* __restrict_
 // First sweep from a zero guess: u = omega D^{-1} f.
 template <typename T>
 __global__ void k_jacobi_first(long long n, const T* __restrict__ wdinv, const T* __restrict__ f,
-                               T* __restrict__ u) {
+                               T* __restrict__ u, const int* __restrict__ act) {
+  if (act && !act[blockIdx.y]) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   const long long off = n * blockIdx.y;  // right-hand side
   if (i < n) u[off + i] = wdinv[i] * f[off + i];
 }
 
+__global__ void k_jacobi_first_from64(long long n, const float* __restrict__ wdinv, const double* __restrict__ r,
+                                      float* __restrict__ f32, float* __restrict__ u, const int* __restrict__ act) {
+  if (act && !act[blockIdx.y]) return;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long off = n * blockIdx.y;
+  if (i < n) {
+    const float fv = (float)r[off + i];
+    f32[off + i] = fv;
+    u[off + i] = wdinv[i] * fv;
+  }
+}
+
 // Coarse right-hand side f_c = M_c P^T r: trilinear weights 1, 1/2 per axis.
+// With wdc set, also the coarse level's first Jacobi sweep from zero,
+// tc = wdc * f_c (the product the separate first-sweep kernel forms).
 template <typename T>
-__global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restrict__ fc) {
+__global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restrict__ fc,
+                           const int* __restrict__ act, const T* __restrict__ wdc, T* __restrict__ tc) {
   const int m = blockIdx.x * kBlock + threadIdx.x;
-  if (m >= C.nn) return;
+  if (m >= C.nn || (act && !act[blockIdx.y])) return;
   r += 3ll * F.nn * blockIdx.y;  // right-hand side
   fc += 3ll * C.nn * blockIdx.y;
   int I, J, K;
@@ -166,16 +208,24 @@ __global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restr
     }
   }
   const int mk = C.mask[m];
-  fc[3ll * m] = (mk & 1) ? T(0) : s0;
-  fc[3ll * m + 1] = (mk & 2) ? T(0) : s1;
-  fc[3ll * m + 2] = (mk & 4) ? T(0) : s2;
+  const T f0 = (mk & 1) ? T(0) : s0, f1 = (mk & 2) ? T(0) : s1, f2 = (mk & 4) ? T(0) : s2;
+  fc[3ll * m] = f0;
+  fc[3ll * m + 1] = f1;
+  fc[3ll * m + 2] = f2;
+  if (wdc) {
+    tc += 3ll * C.nn * blockIdx.y;
+    tc[3ll * m] = wdc[3ll * m] * f0;
+    tc[3ll * m + 1] = wdc[3ll * m + 1] * f1;
+    tc[3ll * m + 2] = wdc[3ll * m + 2] * f2;
+  }
 }
 
 // Fine correction u += M P e_c (trilinear interpolation).
 template <typename T>
-__global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u) {
+__global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u,
+                              const int* __restrict__ act) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= F.nn) return;
+  if (n >= F.nn || (act && !act[blockIdx.y])) return;
   ec += 3ll * C.nn * blockIdx.y;  // right-hand side
   u += 3ll * F.nn * blockIdx.y;
   int i, j, k;
@@ -333,80 +383,122 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
 }
 
 // Blocked Gauss-Jordan.  For the pivot block K (rows/columns k0 .. k0+nb-1):
-//   D = A_KK^{-1};  X = D A_K* (row panel);
-//   B_KK = D,  B_KJ = X_J,  B_IK = -A_IK D,  B_IJ = A_IJ - A_IK X_J,
+//   D = A_KK^{-1};  X_J = D A_KJ (row panel, with X_K = D);
+//   B_K* = X,  B_IK = -A_IK D,  B_IJ = A_IJ - A_IK X_J,
 // which is nb scalar Gauss-Jordan steps applied at once.  A is read, B written.
-// The diagonal block is inverted by one workgroup in LDS: thread (rg, j) owns
-// column j and rows rg, rg+4, ..., so no index arithmetic needs a division.
+// The SPD coarse matrix (identity rows at fixed DOFs) needs no pivoting.
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Inverse of the diagonal block by one workgroup of four waves: lane j holds
+// column j, wave w rows w, w+4, ..., w+60, all in registers.  Step k: the wave
+// owning row k publishes it through LDS (double-buffered: one barrier per
+// step); every wave reads the pivot column of its own rows from lane k.
+// Rows and columns beyond nb are padded with the identity.
 __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
                                                          double* __restrict__ D) {
-  __shared__ double s[kGJBlock][kGJBlock + 1];
-  constexpr int kRowGroups = kBlock / kGJBlock;     // 4
-  constexpr int kPer = kGJBlock / kRowGroups;      // 16 rows per thread
-  const int j = threadIdx.x % kGJBlock, rg = threadIdx.x / kGJBlock;
+  static_assert(kGJBlock == 64 && kBlock == 256, "one lane per column, four waves");
+  __shared__ double prow[2][kGJBlock];
+  const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double v[16];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = rg + kRowGroups * q;
-    s[i][j] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : 0.0;
+  for (int q = 0; q < 16; ++q) {
+    const int i = w + 4 * q;
+    v[q] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
   }
-  __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    const double p = 1.0 / s[k][k];
-    const double skj = s[k][j];
-    double v[kPer];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = rg + kRowGroups * q;
-      const double sik = s[i][k];
-      if (i == k)
-        v[q] = (j == k) ? p : skj * p;
-      else
-        v[q] = (j == k) ? -sik * p : s[i][j] - sik * skj * p;
+  for (int kq = 0; kq < 16; ++kq) {
+#pragma unroll
+    for (int kr = 0; kr < 4; ++kr) {
+      const int k = 4 * kq + kr;
+      double* pr = prow[k & 1];
+      if (w == kr) pr[j] = v[kq];
+      __syncthreads();
+      const double p = 1.0 / pr[k];
+      const bool colk = j == k;
+      const double rj = colk ? p : pr[j] * p;  // new pivot row
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double c = readlane_f64(v[q], k);  // old a_ik
+        v[q] = (colk ? 0.0 : v[q]) - c * rj;
+      }
+      if (w == kr) v[kq] = rj;
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) s[rg + kRowGroups * q][j] = v[q];
-    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = rg + kRowGroups * q;
-    if (i < nb && j < nb) D[i * nb + j] = s[i][j];
+  for (int q = 0; q < 16; ++q) {
+    const int i = w + 4 * q;
+    if (i < nb && j < nb) D[i * nb + j] = v[q];
   }
 }
 
-// grid (ceil(n / kBlock), nb): X[r][j] = sum_q D[r][q] A[k0+q][j]
-__global__ void k_gj_row_panel(int n, int k0, int nb, const double* __restrict__ A, const double* __restrict__ D,
-                               double* __restrict__ X) {
-  const int j = blockIdx.x * kBlock + threadIdx.x, r = blockIdx.y;
-  if (j >= n) return;
-  double s = 0.0;
-  for (int q = 0; q < nb; ++q) s += D[r * nb + q] * A[(long long)(k0 + q) * n + j];
-  X[(long long)r * n + j] = s;
+// grid ceil(n / 64): X[r][j] = sum_q D[r][q] A[k0+q][j] for the block's 64
+// columns (X[r][k0+c] = D[r][c] inside the pivot block).  Lane = column, wave w
+// rows 16w .. 16w+15; the column of A_K* is held in registers, D in LDS.
+__global__ __launch_bounds__(kBlock) void k_gj_row_panel(int n, int k0, int nb, const double* __restrict__ A,
+                                                         const double* __restrict__ D, double* __restrict__ X) {
+  __shared__ double sD[kGJBlock][kGJBlock];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  for (int t = threadIdx.x; t < kGJBlock * kGJBlock; t += kBlock) {
+    const int r = t >> 6, q = t & 63;
+    sD[r][q] = (r < nb && q < nb) ? D[r * nb + q] : 0.0;
+  }
+  double a[kGJBlock];
+#pragma unroll
+  for (int q = 0; q < kGJBlock; ++q) a[q] = (q < nb && j < n) ? A[(long long)(k0 + q) * n + j] : 0.0;
+  __syncthreads();
+  const bool inK = j >= k0 && j < k0 + nb;
+#pragma unroll 4
+  for (int rr = 0; rr < 16; ++rr) {
+    const int r = 16 * w + rr;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGJBlock; ++q) s += sD[r][q] * a[q];
+    if (r < nb && j < n) X[(long long)r * n + j] = inK ? sD[r][j - k0] : s;
+  }
 }
 
-// grid (ceil(n / kBlock), n): one row i per blockIdx.y
-__global__ void k_gj_update(int n, int k0, int nb, const double* __restrict__ A, const double* __restrict__ D,
-                            const double* __restrict__ X, double* __restrict__ B) {
-  const int j = blockIdx.x * kBlock + threadIdx.x, i = blockIdx.y;
-  if (j >= n) return;
-  const bool iK = i >= k0 && i < k0 + nb, jK = j >= k0 && j < k0 + nb;
-  const double* Ai = A + (long long)i * n + k0;
-  double v;
-  if (iK && jK) {
-    v = D[(i - k0) * nb + (j - k0)];
-  } else if (iK) {
-    v = X[(long long)(i - k0) * n + j];
-  } else if (jK) {
-    double s = 0.0;
-    for (int q = 0; q < nb; ++q) s += Ai[q] * D[q * nb + (j - k0)];
-    v = -s;
-  } else {
-    double s = 0.0;
-    for (int q = 0; q < nb; ++q) s += Ai[q] * X[(long long)q * n + j];
-    v = A[(long long)i * n + j] - s;
+// grid (ceil(n / 64), ceil(n / 64)): 64x64 tile of
+//   B_ij = X[i-k0][j]                                   (i in K)
+//   B_ij = (j in K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]  (otherwise)
+// Lane = column j (X column in registers), wave w rows 16w .. 16w+15 of the
+// tile (A_IK rows from LDS).
+__global__ __launch_bounds__(kBlock) void k_gj_update(int n, int k0, int nb, const double* __restrict__ A,
+                                                      const double* __restrict__ X, double* __restrict__ B) {
+  __shared__ double sA[kGJBlock][kGJBlock];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane, i0 = blockIdx.y * 64;
+  for (int t = threadIdx.x; t < kGJBlock * kGJBlock; t += kBlock) {
+    const int r = t >> 6, q = t & 63;
+    sA[r][q] = (i0 + r < n && q < nb) ? A[(long long)(i0 + r) * n + k0 + q] : 0.0;
   }
-  B[(long long)i * n + j] = v;
+  double x[kGJBlock];
+#pragma unroll
+  for (int q = 0; q < kGJBlock; ++q) x[q] = (q < nb && j < n) ? X[(long long)q * n + j] : 0.0;
+  __syncthreads();
+  if (j >= n) return;
+  const bool jK = j >= k0 && j < k0 + nb;
+#pragma unroll 4
+  for (int rr = 0; rr < 16; ++rr) {
+    const int r = 16 * w + rr, i = i0 + r;
+    if (i >= n) break;
+    double v;
+    if (i >= k0 && i < k0 + nb) {
+      v = X[(long long)(i - k0) * n + j];
+    } else {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGJBlock; ++q) s += sA[r][q] * x[q];
+      v = (jK ? 0.0 : A[(long long)i * n + j]) - s;
+    }
+    B[(long long)i * n + j] = v;
+  }
 }
 
 __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __restrict__ B) {
@@ -417,10 +509,10 @@ __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __rest
 
 template <typename T>
 __global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const T* __restrict__ x,
-                              T* __restrict__ y) {
+                              T* __restrict__ y, const int* __restrict__ act) {
   const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;  // uniform per wave
+  if (row >= n || (act && !act[blockIdx.y])) return;  // uniform per wave
   x += (long long)n * blockIdx.y;  // right-hand side
   y += (long long)n * blockIdx.y;
   double s = 0.0;
@@ -432,10 +524,14 @@ __global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const T* _
 // ---------------------------------------------------------------------------
 // PCG vector kernels (binary64).
 __global__ void k_dot_partial(long long n, const double* __restrict__ x, const double* __restrict__ y,
-                              double* __restrict__ partials) {
+                              double* __restrict__ partials, const int* __restrict__ act) {
   x += n * blockIdx.y;  // right-hand side
   y += n * blockIdx.y;
   partials += (long long)kReduceBlocks * blockIdx.y;
+  if (act && !act[blockIdx.y]) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
   double s = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
     s += x[i] * y[i];
@@ -452,53 +548,120 @@ __global__ void k_reduce_final(const double* __restrict__ partials, double* __re
   if (threadIdx.x == 0) out[(long long)stride * blockIdx.x] = s;
 }
 
-__global__ void k_scalar_op(int op, int nrhs, double* __restrict__ sc) {
+__global__ void k_pcg_init(double rtol2, double* __restrict__ sc, int* __restrict__ active, int nrhs) {
   const int r = threadIdx.x;
   if (r >= nrhs) return;
-  sc += kScalars * r;
-  if (op == kOpAlpha) {
-    sc[kAlpha] = sc[kRz] / sc[kPq];
-  } else {
-    sc[kBeta] = sc[kRzNew] / sc[kRz];
-    sc[kRz] = sc[kRzNew];
-  }
+  double* s = sc + kScalars * r;
+  const double ff = s[kFf];
+  const bool finite = ff == ff && ff < 1e308;
+  const int a = (ff > 0.0 && finite) ? 1 : 0;
+  active[r] = a;
+  s[kActive] = a;
+  s[kIts] = 0.0;
+  s[kStatus] = !finite ? -4.0 : (ff > 0.0 ? 1.0 : 0.0);
+  s[kStop] = rtol2 > 0.0 ? rtol2 * ff : -1.0;
+  s[kRr] = ff;
+  s[kPq] = 0.0;
 }
 
-// grid (kReduceBlocks, nrhs); right-hand sides with active[r] == 0 are left alone
-__global__ void k_update_xr(long long n, const double* __restrict__ sc, const int* __restrict__ active,
-                            const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
-                            double* __restrict__ r, double* __restrict__ partials) {
+// grid (kReduceBlocks, nrhs).  Every block sums the same pq partials in the
+// same order, so all blocks use the identical alpha.
+__global__ void k_update_xr(long long n, const double* __restrict__ pq_partials, double* __restrict__ sc,
+                            const int* __restrict__ active, const double* __restrict__ p,
+                            const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
+                            double* __restrict__ rr_partials, int parity) {
   const int rhs = blockIdx.y;
+  rr_partials += (long long)kReduceBlocks * rhs;
+  if (!active[rhs]) {
+    if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const double pq = sum_partials(pq_partials + (long long)kReduceBlocks * rhs);
+  double* s = sc + kScalars * rhs;
+  const double alpha = s[kRz0 + parity] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s[kPq] = pq;
+    s[kAlpha] = alpha;
+  }
+  if (!(pq > 0.0 && pq < 1e308)) {  // breakdown: keep the previous iterate; the check flags it
+    if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
+    return;
+  }
   const long long off = n * rhs;
   p += off;
   q += off;
   x += off;
   r += off;
-  partials += (long long)kReduceBlocks * rhs;
-  if (!active[rhs]) {
-    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
-    return;
-  }
-  const double alpha = sc[kScalars * rhs + kAlpha];
-  double s = 0.0;
+  double acc = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
-    s += ri * ri;
+    acc += ri * ri;
   }
-  s = block_sum(s);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) rr_partials[blockIdx.x] = acc;
 }
 
-__global__ void k_update_p(long long n, const double* __restrict__ sc, const int* __restrict__ active,
-                           const double* __restrict__ z, double* __restrict__ p) {
+// one block per right-hand side: ||r||^2, iteration count, convergence test
+__global__ void k_rr_check(const double* __restrict__ rr_partials, double* __restrict__ sc,
+                           int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  const double rr = sum_partials(rr_partials + (long long)kReduceBlocks * rhs);
+  if (threadIdx.x != 0 || !active[rhs]) return;
+  double* s = sc + kScalars * rhs;
+  s[kRr] = rr;
+  s[kIts] += 1.0;
+  const bool finite = rr == rr && rr < 1e308;
+  if (!(s[kPq] > 0.0 && s[kPq] < 1e308) || !finite) {
+    active[rhs] = 0;
+    s[kActive] = 0.0;
+    s[kStatus] = -5.0;
+  } else if (rr <= s[kStop]) {
+    active[rhs] = 0;
+    s[kActive] = 0.0;
+    s[kStatus] = 0.0;
+  }
+}
+
+// grid (kReduceBlocks, nrhs): beta from the rz partials, p = z + beta p
+__global__ void k_update_p(long long n, const double* __restrict__ rz_partials, double* __restrict__ sc,
+                           const int* __restrict__ active, const double* __restrict__ z, double* __restrict__ p,
+                           int parity) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const double beta = sc[kScalars * rhs + kBeta];
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const double rz = sum_partials(rz_partials + (long long)kReduceBlocks * rhs);
+  double* s = sc + kScalars * rhs;
+  const double beta = rz / s[kRz0 + parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s[kRz0 + 1 - parity] = rz;
+    s[kBeta] = beta;
+  }
   const long long off = n * rhs;
-  if (i < n) p[off + i] = z[off + i] + beta * p[off + i];
+  z += off;
+  p += off;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    p[i] = z[i] + beta * p[i];
+}
+
+// z = (double) u32 and the partials of r . z (grid (kReduceBlocks, nrhs))
+__global__ void k_to64_dot(long long n, const float* __restrict__ u32, const double* __restrict__ r,
+                           double* __restrict__ z, double* __restrict__ partials, const int* __restrict__ act) {
+  const int rhs = blockIdx.y;
+  partials += (long long)kReduceBlocks * rhs;
+  if (act && !act[rhs]) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const long long off = n * rhs;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    const double zi = (double)u32[off + i];
+    z[off + i] = zi;
+    acc += r[off + i] * zi;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
 __global__ void k_mask_copy(Level L, const double* __restrict__ f, double* __restrict__ r) {
@@ -509,14 +672,20 @@ __global__ void k_mask_copy(Level L, const double* __restrict__ f, double* __res
   r[off + i] = ((L.mask[n] >> c) & 1) ? 0.0 : f[off + i];
 }
 
-__global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* __restrict__ b) {
+__global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* __restrict__ b,
+                             const int* __restrict__ act) {
+  if (act && !act[blockIdx.y]) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+  const long long off = n * blockIdx.y;
+  if (i < n) b[off + i] = (float)a[off + i];
 }
 
-__global__ void k_f32_to_f64(long long n, const float* __restrict__ a, double* __restrict__ b) {
+__global__ void k_f32_to_f64(long long n, const float* __restrict__ a, double* __restrict__ b,
+                             const int* __restrict__ act) {
+  if (act && !act[blockIdx.y]) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) b[i] = (double)a[i];
+  const long long off = n * blockIdx.y;
+  if (i < n) b[off + i] = (double)a[off + i];
 }
 
 __global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b,
@@ -563,40 +732,54 @@ __global__ void k_sensitivity(Level L, const double* __restrict__ Ke, const doub
 // ---- launchers ------------------------------------------------------------
 template <typename T>
 void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
-                   const T* wdinv, T* y, int nrhs, hipStream_t s) {
+                   const T* wdinv, T* y, int nrhs, const int* act, hipStream_t s, const LaunchTimer& t) {
   const dim3 g(blocks_for(L.nn), nrhs);
   if (mode == kApply)
-    k_gather<T, kApply><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
+    launch_timed(k_gather<T, kApply>, g, dim3(kBlock), s, t, L, Ke, E, u, f, wdinv, y, act);
   else if (mode == kSmooth)
-    k_gather<T, kSmooth><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
+    launch_timed(k_gather<T, kSmooth>, g, dim3(kBlock), s, t, L, Ke, E, u, f, wdinv, y, act);
   else
-    k_gather<T, kResidual><<<g, kBlock, 0, s>>>(L, Ke, E, u, f, wdinv, y);
+    launch_timed(k_gather<T, kResidual>, g, dim3(kBlock), s, t, L, Ke, E, u, f, wdinv, y, act);
 }
 template void launch_gather<double>(int, const Level&, const double*, const double*, const double*,
-                                    const double*, const double*, double*, int, hipStream_t);
+                                    const double*, const double*, double*, int, const int*, hipStream_t,
+                                    const LaunchTimer&);
 template void launch_gather<float>(int, const Level&, const float*, const float*, const float*,
-                                   const float*, const float*, float*, int, hipStream_t);
+                                   const float*, const float*, float*, int, const int*, hipStream_t,
+                                   const LaunchTimer&);
 
 template <typename T>
-void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, hipStream_t s) {
-  k_jacobi_first<T><<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, wdinv, f, u);
+void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, const int* act, hipStream_t s) {
+  k_jacobi_first<T><<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, wdinv, f, u, act);
 }
-template void launch_jacobi_first<double>(long long, const double*, const double*, double*, int, hipStream_t);
-template void launch_jacobi_first<float>(long long, const float*, const float*, float*, int, hipStream_t);
+template void launch_jacobi_first<double>(long long, const double*, const double*, double*, int, const int*,
+                                          hipStream_t);
+template void launch_jacobi_first<float>(long long, const float*, const float*, float*, int, const int*,
+                                         hipStream_t);
+void launch_jacobi_first_from64(long long n, const float* wdinv, const double* r, float* f32, float* u, int nrhs,
+                                const int* act, hipStream_t s) {
+  k_jacobi_first_from64<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, wdinv, r, f32, u, act);
+}
 
 template <typename T>
-void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, hipStream_t s) {
-  k_restrict<T><<<dim3(blocks_for(C.nn), nrhs), kBlock, 0, s>>>(F, C, r, fc);
+void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, const int* act, hipStream_t s,
+                     const T* wdc, T* tc) {
+  k_restrict<T><<<dim3(blocks_for(C.nn), nrhs), kBlock, 0, s>>>(F, C, r, fc, act, wdc, tc);
 }
-template void launch_restrict<double>(const Level&, const Level&, const double*, double*, int, hipStream_t);
-template void launch_restrict<float>(const Level&, const Level&, const float*, float*, int, hipStream_t);
+template void launch_restrict<double>(const Level&, const Level&, const double*, double*, int, const int*,
+                                      hipStream_t, const double*, double*);
+template void launch_restrict<float>(const Level&, const Level&, const float*, float*, int, const int*,
+                                     hipStream_t, const float*, float*);
 
 template <typename T>
-void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, hipStream_t s) {
-  k_prolong_add<T><<<dim3(blocks_for(F.nn), nrhs), kBlock, 0, s>>>(F, C, ec, u);
+void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, const int* act,
+                        hipStream_t s) {
+  k_prolong_add<T><<<dim3(blocks_for(F.nn), nrhs), kBlock, 0, s>>>(F, C, ec, u, act);
 }
-template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, int, hipStream_t);
-template void launch_prolong_add<float>(const Level&, const Level&, const float*, float*, int, hipStream_t);
+template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, int, const int*,
+                                         hipStream_t);
+template void launch_prolong_add<float>(const Level&, const Level&, const float*, float*, int, const int*,
+                                        hipStream_t);
 
 void launch_simp(int ne, const double* rho, double E0, double Emin, double p, double scale,
                  double* E64, float* E32, double* rho_copy, int* bad_flags, hipStream_t s) {
@@ -636,9 +819,10 @@ void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double
   int cur = 0;
   for (int k0 = 0; k0 < n; k0 += kGJBlock) {
     const int nb = (n - k0) < kGJBlock ? (n - k0) : kGJBlock;
+    const int t = (n + 63) / 64;
     k_gj_block_inv<<<1, kBlock, 0, s>>>(n, k0, nb, buf[cur], D);
-    k_gj_row_panel<<<dim3(blocks_for(n), nb), kBlock, 0, s>>>(n, k0, nb, buf[cur], D, X);
-    k_gj_update<<<dim3(blocks_for(n), n), kBlock, 0, s>>>(n, k0, nb, buf[cur], D, X, buf[1 - cur]);
+    k_gj_row_panel<<<t, kBlock, 0, s>>>(n, k0, nb, buf[cur], D, X);
+    k_gj_update<<<dim3(t, t), kBlock, 0, s>>>(n, k0, nb, buf[cur], X, buf[1 - cur]);
     cur = 1 - cur;
   }
   *result = buf[cur];
@@ -647,38 +831,47 @@ void launch_symmetrize(int n, const double* A, double* B, hipStream_t s) {
   k_symmetrize<<<dim3(blocks_for(n), n), kBlock, 0, s>>>(n, A, B);
 }
 template <typename T>
-void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, hipStream_t s) {
+void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, const int* act, hipStream_t s) {
   const int rows_per_block = kBlock / 64;
-  k_coarse_gemv<T><<<dim3((n + rows_per_block - 1) / rows_per_block, nrhs), kBlock, 0, s>>>(n, Ainv, x, y);
+  k_coarse_gemv<T><<<dim3((n + rows_per_block - 1) / rows_per_block, nrhs), kBlock, 0, s>>>(n, Ainv, x, y, act);
 }
-template void launch_coarse_gemv<double>(int, const double*, const double*, double*, int, hipStream_t);
-template void launch_coarse_gemv<float>(int, const double*, const float*, float*, int, hipStream_t);
+template void launch_coarse_gemv<double>(int, const double*, const double*, double*, int, const int*, hipStream_t);
+template void launch_coarse_gemv<float>(int, const double*, const float*, float*, int, const int*, hipStream_t);
 
-void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, hipStream_t s) {
-  k_dot_partial<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, x, y, partials);
+void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, const int* act,
+                        hipStream_t s) {
+  k_dot_partial<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, x, y, partials, act);
 }
 void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s) {
   k_reduce_final<<<nrhs, kBlock, 0, s>>>(partials, out, stride);
 }
-void launch_scalar_op(int op, double* sc, int nrhs, hipStream_t s) {
-  k_scalar_op<<<1, ((nrhs + 63) / 64) * 64, 0, s>>>(op, nrhs, sc);
+void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s) {
+  k_pcg_init<<<1, ((nrhs + 63) / 64) * 64, 0, s>>>(rtol2, sc, active, nrhs);
 }
-void launch_update_xr(long long n, const double* sc, const int* active, const double* p, const double* q, double* x,
-                      double* r, double* partials, int nrhs, hipStream_t s) {
-  k_update_xr<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, active, p, q, x, r, partials);
+void launch_update_xr(long long n, const double* pq_partials, double* sc, const int* active, const double* p,
+                      const double* q, double* x, double* r, double* rr_partials, int parity, int nrhs, hipStream_t s) {
+  k_update_xr<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, sc, active, p, q, x, r, rr_partials,
+                                                           parity);
 }
-void launch_update_p(long long n, const double* sc, const int* active, const double* z, double* p, int nrhs,
-                     hipStream_t s) {
-  k_update_p<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, sc, active, z, p);
+void launch_rr_check(const double* rr_partials, double* sc, int* active, int nrhs, hipStream_t s) {
+  k_rr_check<<<nrhs, kBlock, 0, s>>>(rr_partials, sc, active);
+}
+void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const double* z,
+                     double* p, int parity, int nrhs, hipStream_t s) {
+  k_update_p<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, sc, active, z, p, parity);
+}
+void launch_to64_dot(long long n, const float* u32, const double* r, double* z, double* partials, int nrhs,
+                     const int* act, hipStream_t s) {
+  k_to64_dot<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, u32, r, z, partials, act);
 }
 void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s) {
   k_mask_copy<<<dim3(blocks_for(3ll * L.nn), nrhs), kBlock, 0, s>>>(L, f, r);
 }
-void launch_f64_to_f32(long long n, const double* a, float* b, hipStream_t s) {
-  k_f64_to_f32<<<blocks_for(n), kBlock, 0, s>>>(n, a, b);
+void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s) {
+  k_f64_to_f32<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, a, b, act);
 }
-void launch_f32_to_f64(long long n, const float* a, double* b, hipStream_t s) {
-  k_f32_to_f64<<<blocks_for(n), kBlock, 0, s>>>(n, a, b);
+void launch_f32_to_f64(long long n, const float* a, double* b, int nrhs, const int* act, hipStream_t s) {
+  k_f32_to_f64<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, a, b, act);
 }
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s) {
   k_sub<<<blocks_for(n), kBlock, 0, s>>>(n, a, b, c);

@@ -101,7 +101,8 @@ template <typename T, int MODE, int R, int W, int MINW>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
-                                                      int nchunks) {
+                                                      int nchunks, const int* __restrict__ act) {
+  if (act && !act[blockIdx.z / nchunks]) return;  // right-hand side already converged (uniform per block)
   {  // blockIdx.z = z-chunk + nchunks * right-hand side; vectors are [nrhs][3 nn]
     const long long off = 3ll * L.nn * (blockIdx.z / nchunks);
     ug += off;
@@ -363,17 +364,18 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 
 template <typename T, int R, int W, int MINW>
 void launch_stream_impl(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                        const T* wd, T* y, int zchunk, int nrhs, hipStream_t s) {
+                        const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
+                        const LaunchTimer& t) {
   constexpr int kOutRows = W * R - 2;
   const int nchunks = (L.nzn + zchunk - 1) / zchunk;
   dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
   dim3 block(64 * W);
   if (mode == kApply)
-    k_stream<T, kApply, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk, nchunks);
+    launch_timed(k_stream<T, kApply, R, W, MINW>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks, act);
   else if (mode == kSmooth)
-    k_stream<T, kSmooth, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk, nchunks);
+    launch_timed(k_stream<T, kSmooth, R, W, MINW>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks, act);
   else
-    k_stream<T, kResidual, R, W, MINW><<<grid, block, 0, s>>>(L, q, E, u, f, wd, y, zchunk, nchunks);
+    launch_timed(k_stream<T, kResidual, R, W, MINW>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks, act);
 }
 
 }  // namespace
@@ -389,25 +391,29 @@ int stream_out_rows(bool f32, int shape) {
 }
 
 template <typename T>
-void launch_stream(int mode, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                   const T* wd, T* y, int zchunk, int nrhs, hipStream_t s) {
+void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
+                   const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
+                   const LaunchTimer& t) {
+  (void)maskin;  // inputs are always masked on load
   if constexpr (sizeof(T) == 4) {
     if (shape == 0)
-      launch_stream_impl<T, 2, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
+      launch_stream_impl<T, 2, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else if (shape == 1)
-      launch_stream_impl<T, 3, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
+      launch_stream_impl<T, 3, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else
-      launch_stream_impl<T, 4, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
+      launch_stream_impl<T, 4, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
   } else {
     if (shape == 0)
-      launch_stream_impl<T, 1, 8, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
+      launch_stream_impl<T, 1, 8, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else
-      launch_stream_impl<T, 2, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, s);
+      launch_stream_impl<T, 2, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
   }
 }
-template void launch_stream<float>(int, int, const Level&, const HaarCoef<float>&, const float*, const float*,
-                                   const float*, const float*, float*, int, int, hipStream_t);
-template void launch_stream<double>(int, int, const Level&, const HaarCoef<double>&, const double*, const double*,
-                                    const double*, const double*, double*, int, int, hipStream_t);
+template void launch_stream<float>(int, bool, int, const Level&, const HaarCoef<float>&, const float*,
+                                   const float*, const float*, const float*, float*, int, int, const int*,
+                                   hipStream_t, const LaunchTimer&);
+template void launch_stream<double>(int, bool, int, const Level&, const HaarCoef<double>&, const double*,
+                                    const double*, const double*, const double*, double*, int, int, const int*,
+                                    hipStream_t, const LaunchTimer&);
 
 }  // namespace hexmg
