@@ -205,6 +205,8 @@ def main():
     achieved = sb / (avg_smooth_ms * 1e-3) / 1e9
     choices = {f"L{l}": {"f32": mixed.kernel_choice(l, hexmg.F32), "f64": mixed.kernel_choice(l, hexmg.F64)}
                for l in range(levels)}
+    choices["coarse_cycle"] = {"f32": mixed.coarse_cycle_choice(hexmg.F32),
+                               "f64": mixed.coarse_cycle_choice(hexmg.F64)}
     out = {
         "metric": METRIC,
         "value": g.n_dof / (ms_per_step * 1e-3) / 1e9,

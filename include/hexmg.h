@@ -205,6 +205,25 @@ int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int *kernel, in
  * Returns -1 for an unknown kernel, shape or level. */
 int hexmg_set_kernel_choice(hexmg_grid_t grid, int level, int dtype, int kernel, int zchunk, int shape);
 
+/* The coarse part of the V-cycle (Alg. 3) may run as one cooperative launch
+ * (a grid-stride kernel whose phases -- sweeps, residual, restriction,
+ * coarsest solve, prolongation -- are separated by grid-wide barriers) instead
+ * of one launch per step; the arithmetic is that of the node-gather kernels.
+ * *level = first level of that launch (1 .. levels-2) or 0 when every level is
+ * launched step by step; *blocks = its workgroup count.  By default the choice
+ * is made by timing both forms on the grid's stream during the first
+ * successful hexmg_set_density.  Either output pointer may be NULL.
+ * The cooperative launch needs its workgroups resident together; a grid used
+ * concurrently with another grid's solve on a different stream should be set
+ * to 0 (hexmg_batch_solve does this itself for the duration of the call). */
+int hexmg_coarse_cycle_choice(hexmg_grid_t grid, int dtype, int *level, int *blocks);
+
+/* Overrides that choice for dtype: level 0 (off) or 1 .. levels-2; blocks 0 =
+ * as many workgroups as can be resident at once (larger values are clamped to
+ * that).  Later automatic tuning does not undo it.  Returns -1 for a bad level,
+ * -3 if the device cannot launch the kernel cooperatively. */
+int hexmg_set_coarse_cycle(hexmg_grid_t grid, int dtype, int level, int blocks);
+
 /* Per-kernel device timing with stream events (off by default).  While
  * enabled, every finest-level launch of the named kernel family is bracketed
  * by events on its stream; hexmg_profile_query returns the number of launches and their

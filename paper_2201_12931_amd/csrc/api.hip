@@ -304,6 +304,38 @@ VView<float> view32(hexmg_grid* g) {
   return v;
 }
 
+template <typename T>
+CoarseCycle<T> make_cycle(hexmg_grid* g) {
+  CoarseCycle<T> a{};
+  for (int l = 0; l < g->L; ++l) {
+    a.lv[l] = g->lv[l];
+    if constexpr (sizeof(T) == 4) {
+      a.E[l] = g->E32[l];
+      a.wd[l] = g->wd32[l];
+      a.u[l] = g->vu32[l];
+      a.t[l] = g->vt32[l];
+      a.r[l] = g->vr32[l];
+      a.f[l] = g->vf32[l];
+    } else {
+      a.E[l] = g->E64[l];
+      a.wd[l] = g->wd64[l];
+      a.u[l] = g->vu64[l];
+      a.t[l] = g->vt64[l];
+      a.r[l] = g->vr64[l];
+      a.f[l] = g->vf64[l];
+    }
+  }
+  if constexpr (sizeof(T) == 4)
+    a.Ke = g->Ke32;
+  else
+    a.Ke = g->Ke64;
+  a.Ainv = g->Ainv;
+  a.nc = g->nc;
+  a.L = g->L;
+  a.nu = g->desc.smooth_sweeps;
+  return a;
+}
+
 // out = V_l(f) from a zero initial guess.  The first sweep writes the level's
 // scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
 // in `out` without a copy.  f and out must not overlap.  With first_done the
@@ -331,12 +363,88 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   const bool fuse = l + 1 < g->L - 1;
   launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], nrhs, act, s, fuse ? v.wd[l + 1] : nullptr,
                      fuse ? v.t[l + 1] : nullptr);
-  vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, act, s, fuse);
+  int& tail = sizeof(T) == 4 ? g->tail32 : g->tail64;
+  const int blocks = sizeof(T) == 4 ? g->tail_blocks32 : g->tail_blocks64;
+  bool done = false;
+  if (fuse && tail == l + 1) {  // the rest of the cycle as one cooperative launch
+    done = launch_coarse_cycle<T>(make_cycle<T>(g), l + 1, nrhs, act, blocks, s) == hipSuccess;
+    if (!done) {
+      (void)hipGetLastError();
+      tail = 0;  // not launchable here: back to one launch per step from now on
+    }
+  }
+  if (!done) vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, act, s, fuse);
   launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, act, s);
   for (int it = 0; it < nu; ++it) {
     gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, false, act);
     cur = 1 - cur;
   }
+}
+
+// Times the rest of the V-cycle from each level ls >= 1 launched step by step
+// against the cooperative launch (several workgroup counts) and keeps the
+// cooperative launch from the level where it saves the most, if it saves more
+// than 5% there.
+template <typename T>
+int tune_tail(hexmg_grid* g, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  int& tail = f32 ? g->tail32 : g->tail64;
+  int& tblocks = f32 ? g->tail_blocks32 : g->tail_blocks64;
+  tail = 0;
+  tblocks = 0;
+  const int maxb = coarse_cycle_max_blocks<T>();
+  if (g->L < 3 || maxb <= 0) return 0;
+  VView<T> v = [&] {
+    if constexpr (sizeof(T) == 4)
+      return view32(g);
+    else
+      return view64(g);
+  }();
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto time3 = [&](auto&& fn, float* ms) -> int {
+    fn();
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 3; ++rep) fn();
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    return 0;
+  };
+  float best_gain = 0.f;
+  const CoarseCycle<T> cyc = make_cycle<T>(g);
+  for (int ls = 1; ls <= g->L - 2; ++ls) {
+    const size_t bytes = 3ull * g->lv[ls].nn * sizeof(T);
+    HIP_TRY(hipMemsetAsync(v.f[ls], 0, bytes, s));
+    HIP_TRY(hipMemsetAsync(v.t[ls], 0, bytes, s));
+    float ms_launch = 0.f;
+    if (int e = time3([&] { vcycle_level<T>(g, v, ls, v.f[ls], v.u[ls], 1, nullptr, s, true); }, &ms_launch))
+      return e;
+    int prev = -1;
+    for (int b : {64, 128, 256, 512, 1024}) {
+      b = b < maxb ? b : maxb;
+      if (b == prev) continue;
+      prev = b;
+      bool ok = true;
+      float ms = 0.f;
+      if (int e = time3([&] { ok = ok && launch_coarse_cycle<T>(cyc, ls, 1, nullptr, b, s) == hipSuccess; }, &ms))
+        return e;
+      if (!ok) {
+        (void)hipGetLastError();
+        continue;
+      }
+      const float gain = ms_launch - ms;
+      if (gain > 0.05f * ms_launch && gain > best_gain) {
+        best_gain = gain;
+        tail = ls;
+        tblocks = b;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return 0;
 }
 
 // z = V(r) in the grid's precision for nrhs <= max_nrhs binary64 right-hand
@@ -537,6 +645,11 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
   g->density_set = true;
   if (!g->tuned) {
     if (int e = tune_kernels(g, s)) return e;
+  }
+  if (!g->tail_tuned) {
+    if (int e = tune_tail<double>(g, s)) return e;
+    if (int e = tune_tail<float>(g, s)) return e;
+    g->tail_tuned = true;
   }
   return 0;
 }
@@ -804,6 +917,15 @@ int hexmg_batch_solve(hexmg_grid_t* grids, int ngrids, const double* const* f, d
   HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(fork, s));
   std::vector<PcgRun> runs(ngrids);
+  // The grids run concurrently on their own streams; two cooperative launches
+  // resident at once could each hold workgroups the other's grid barrier waits
+  // for, so the coarse part of the cycle is launched step by step here.
+  struct Tail { int t64, t32; };
+  std::vector<Tail> saved(ngrids);
+  for (int i = 0; i < ngrids; ++i) {
+    saved[i] = {grids[i]->tail64, grids[i]->tail32};
+    grids[i]->tail64 = grids[i]->tail32 = 0;
+  }
   int e = 0, off = 0;
   for (int i = 0; i < ngrids && !e; ++i) {
     hexmg_grid* g = grids[i];
@@ -833,6 +955,10 @@ int hexmg_batch_solve(hexmg_grid_t* grids, int ngrids, const double* const* f, d
   }
   if (!e) (void)hipStreamSynchronize(s);
   for (auto& r : runs) r.release();
+  for (int i = 0; i < ngrids; ++i) {
+    grids[i]->tail64 = saved[i].t64;
+    grids[i]->tail32 = saved[i].t32;
+  }
   (void)hipEventDestroy(fork);
   if (e) return e;
   if (worst == HEXMG_ERR_BREAKDOWN) return fail(worst, "PCG breakdown in the batch");
@@ -956,6 +1082,32 @@ int hexmg_set_kernel_choice(hexmg_grid_t g, int level, int dtype, int kernel, in
   }
   (dtype == HEXMG_F64 ? g->choice64 : g->choice32)[level] = c;
   g->tuned = true;
+  return 0;
+}
+
+int hexmg_coarse_cycle_choice(hexmg_grid_t g, int dtype, int* level, int* blocks) {
+  if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
+  if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
+  if (level) *level = dtype == HEXMG_F32 ? g->tail32 : g->tail64;
+  if (blocks) *blocks = dtype == HEXMG_F32 ? g->tail_blocks32 : g->tail_blocks64;
+  return 0;
+}
+
+int hexmg_set_coarse_cycle(hexmg_grid_t g, int dtype, int level, int blocks) {
+  if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
+  if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
+  if (level != 0 && (level < 1 || level > g->L - 2))
+    return fail(HEXMG_ERR_INVALID, "level must be 0 (off) or in [1, levels - 2]");
+  if (blocks < 0) return fail(HEXMG_ERR_INVALID, "blocks must be >= 0");
+  int b = 0;
+  if (level) {
+    const int maxb = dtype == HEXMG_F32 ? coarse_cycle_max_blocks<float>() : coarse_cycle_max_blocks<double>();
+    if (maxb <= 0) return fail(HEXMG_ERR_DEVICE, "cooperative launch not available");
+    b = (blocks == 0 || blocks > maxb) ? maxb : blocks;
+  }
+  (dtype == HEXMG_F32 ? g->tail32 : g->tail64) = level;
+  (dtype == HEXMG_F32 ? g->tail_blocks32 : g->tail_blocks64) = b;
+  g->tail_tuned = true;
   return 0;
 }
 

@@ -154,6 +154,31 @@ void launch_oc_probe(long long n, const double* x, const double* dc, const doubl
 void launch_oc_apply(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
                      double lam_pow, double* xn, hipStream_t s);
 
+// The coarse part of the V-cycle in one cooperative launch (coarse.hip):
+// levels, operators and vectors of one precision.  f[ls] holds the restricted
+// right-hand side of the first level ls of the launch and t[ls] its first
+// Jacobi sweep; the cycle's result lands in u[ls].
+constexpr int kMaxLevels = 12;
+template <typename T>
+struct CoarseCycle {
+  Level lv[kMaxLevels];
+  const T* E[kMaxLevels];
+  const T* wd[kMaxLevels];
+  T* u[kMaxLevels];
+  T* t[kMaxLevels];
+  T* r[kMaxLevels];
+  T* f[kMaxLevels];
+  const T* Ke;
+  const double* Ainv;
+  int nc, L, nu;
+};
+// Most workgroups of k_coarse_cycle<T> that can be resident at once (0 on error).
+template <typename T>
+int coarse_cycle_max_blocks();
+template <typename T>
+hipError_t launch_coarse_cycle(const CoarseCycle<T>& a, int ls, int nrhs, const int* act, int blocks,
+                               hipStream_t s);
+
 // Device scalar slots used by the PCG (one block of kScalars doubles).
 // Per right-hand side, in this order, kScalars doubles each.  The CG state
 // lives on the device: the convergence test runs in a kernel, and the host
@@ -204,6 +229,10 @@ struct hexmg_grid {
   // element-product kernel per level and precision ([level][0] binary64, [1] binary32)
   struct Choice { int kernel; int zchunk; int shape; };
   std::vector<Choice> choice64, choice32;
+  // first level of the cooperative coarse-cycle launch per precision (0: every
+  // level launched step by step) and its workgroup count
+  int tail64 = 0, tail32 = 0, tail_blocks64 = 0, tail_blocks32 = 0;
+  bool tail_tuned = false;
   bool tuned;
   // PCG
   double *r, *z, *p, *q;

@@ -1,0 +1,173 @@
+// Per-node device operations shared by the one-launch-per-step kernels
+// (kernels.hip) and the cooperative coarse-level V-cycle (coarse.hip).
+#pragma once
+
+#include "hexmg_impl.h"
+
+namespace hexmg {
+
+__device__ inline void node_coords(const Level& L, int n, int& i, int& j, int& k) {
+  i = n % L.nxn;
+  const int t = n / L.nxn;
+  j = t % L.nyn;
+  k = t / L.nyn;
+}
+
+// Matrix-free K u (Sec. 4.2.1) at node n: the node gathers the rows of its
+// <= 8 adjacent elements, y_n = sum_e E_e K0[a_e(n), :] u_e, so no global
+// matrix and no scatter conflicts.  Supports: u is read as M u; fixed DOFs
+// return u.  MODE 0: y = A u;  1: y = u + wdinv (f - A u) (damped Jacobi,
+// Eq. 21);  2: y = f - A u (residual, Eq. 19).  Vectors of one right-hand side.
+template <typename T, int MODE>
+__device__ inline void gather_node(const Level& L, const T* __restrict__ Ke, const T* __restrict__ E,
+                                   const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ wdinv,
+                                   T* __restrict__ y, int n) {
+  int i, j, k;
+  node_coords(L, n, i, j, k);
+  T un[27][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int o = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        T v0 = 0, v1 = 0, v2 = 0;
+        if (ii >= 0 && ii < L.nxn && jj >= 0 && jj < L.nyn && kk >= 0 && kk < L.nzn) {
+          const int m = n + dx + L.nxn * (dy + L.nyn * dz);
+          const int mk = L.mask[m];
+          const T* um = u + 3ll * m;
+          v0 = (mk & 1) ? T(0) : um[0];
+          v1 = (mk & 2) ? T(0) : um[1];
+          v2 = (mk & 4) ? T(0) : um[2];
+        }
+        un[o][0] = v0;
+        un[o][1] = v1;
+        un[o][2] = v2;
+      }
+  T acc0 = 0, acc1 = 0, acc2 = 0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const int ei = i - ax, ej = j - ay, ek = k - az;
+    if (ei < 0 || ei >= L.nx || ej < 0 || ej >= L.ny || ek < 0 || ek >= L.nz) continue;
+    const T Ee = E[ei + L.nx * (ej + L.ny * ek)];
+    T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+      const int o = (bz - az + 1) * 9 + (by - ay + 1) * 3 + (bx - ax + 1);
+      const T* kr = Ke + (3 * a) * 24 + 3 * b;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        s0 += kr[d] * un[o][d];
+        s1 += kr[24 + d] * un[o][d];
+        s2 += kr[48 + d] * un[o][d];
+      }
+    }
+    acc0 += Ee * s0;
+    acc1 += Ee * s1;
+    acc2 += Ee * s2;
+  }
+  const int mk = L.mask[n];
+  const long long b = 3ll * n;
+  const T Au0 = (mk & 1) ? u[b] : acc0;
+  const T Au1 = (mk & 2) ? u[b + 1] : acc1;
+  const T Au2 = (mk & 4) ? u[b + 2] : acc2;
+  if (MODE == kApply) {
+    y[b] = Au0;
+    y[b + 1] = Au1;
+    y[b + 2] = Au2;
+  } else if (MODE == kSmooth) {
+    y[b] = u[b] + wdinv[b] * (f[b] - Au0);
+    y[b + 1] = u[b + 1] + wdinv[b + 1] * (f[b + 1] - Au1);
+    y[b + 2] = u[b + 2] + wdinv[b + 2] * (f[b + 2] - Au2);
+  } else {
+    y[b] = f[b] - Au0;
+    y[b + 1] = f[b + 1] - Au1;
+    y[b + 2] = f[b + 2] - Au2;
+  }
+}
+
+// Coarse right-hand side at coarse node m: f_c = M_c P^T r with trilinear
+// weights 1, 1/2 per axis.  With wdc set, also the coarse level's first Jacobi
+// sweep from zero, tc = wdc * f_c.  Vectors of one right-hand side.
+template <typename T>
+__device__ inline void restrict_node(const Level& F, const Level& C, const T* __restrict__ r, T* __restrict__ fc,
+                                     const T* __restrict__ wdc, T* __restrict__ tc, int m) {
+  int I, J, K;
+  node_coords(C, m, I, J, K);
+  T s0 = 0, s1 = 0, s2 = 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int kk = 2 * K + dz;
+    if (kk < 0 || kk >= F.nzn) continue;
+    const T wz = dz ? T(0.5) : T(1);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jj = 2 * J + dy;
+      if (jj < 0 || jj >= F.nyn) continue;
+      const T wy = dy ? T(0.5) : T(1);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = 2 * I + dx;
+        if (ii < 0 || ii >= F.nxn) continue;
+        const T w = (dx ? T(0.5) : T(1)) * wy * wz;
+        const T* rn = r + 3ll * (ii + F.nxn * (jj + F.nyn * kk));
+        s0 += w * rn[0];
+        s1 += w * rn[1];
+        s2 += w * rn[2];
+      }
+    }
+  }
+  const int mk = C.mask[m];
+  const T f0 = (mk & 1) ? T(0) : s0, f1 = (mk & 2) ? T(0) : s1, f2 = (mk & 4) ? T(0) : s2;
+  fc[3ll * m] = f0;
+  fc[3ll * m + 1] = f1;
+  fc[3ll * m + 2] = f2;
+  if (wdc) {
+    tc[3ll * m] = wdc[3ll * m] * f0;
+    tc[3ll * m + 1] = wdc[3ll * m + 1] * f1;
+    tc[3ll * m + 2] = wdc[3ll * m + 2] * f2;
+  }
+}
+
+// Fine correction at fine node n: u += M P e_c (trilinear interpolation).
+template <typename T>
+__device__ inline void prolong_node(const Level& F, const Level& C, const T* __restrict__ ec, T* __restrict__ u,
+                                    int n) {
+  int i, j, k;
+  node_coords(F, n, i, j, k);
+  T s0 = 0, s1 = 0, s2 = 0;
+  const int oz = k & 1, oy = j & 1, ox = i & 1;
+  const T wz = oz ? T(0.5) : T(1), wy = oy ? T(0.5) : T(1), wx = ox ? T(0.5) : T(1);
+  for (int cz = 0; cz <= oz; ++cz)
+    for (int cy = 0; cy <= oy; ++cy)
+      for (int cx = 0; cx <= ox; ++cx) {
+        const int m = ((i >> 1) + cx) + C.nxn * (((j >> 1) + cy) + C.nyn * ((k >> 1) + cz));
+        const T w = wx * wy * wz;
+        s0 += w * ec[3ll * m];
+        s1 += w * ec[3ll * m + 1];
+        s2 += w * ec[3ll * m + 2];
+      }
+  const int mk = F.mask[n];
+  if (!(mk & 1)) u[3ll * n] += s0;
+  if (!(mk & 2)) u[3ll * n + 1] += s1;
+  if (!(mk & 4)) u[3ll * n + 2] += s2;
+}
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Row `row` of y = Ainv x by one wave (the coarsest solve); binary64 sum.
+template <typename T>
+__device__ inline void gemv_row(int n, const double* __restrict__ Ainv, const T* __restrict__ x, T* __restrict__ y,
+                                int row, int lane) {
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s += Ainv[(long long)row * n + c] * (double)x[c];
+  s = wave_sum64(s);
+  if (lane == 0) y[row] = (T)s;
+}
+
+}  // namespace hexmg

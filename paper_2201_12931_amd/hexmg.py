@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
             "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), vp]),
             "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_set_kernel_choice": (i, [vp, i, i, i, i, i]),
+            "hexmg_coarse_cycle_choice": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "hexmg_set_coarse_cycle": (i, [vp, i, i, i]),
             "hexmg_profile_enable": (i, [vp, i]),
             "hexmg_profile_query": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(d)]),
             "hexmg_last_error": (ctypes.c_char_p, []),
@@ -304,6 +306,15 @@ class Grid:
 
     def set_kernel_choice(self, level, dtype, kernel, zchunk=4, shape=0):
         _check(lib().hexmg_set_kernel_choice(self.handle, level, dtype, kernel, zchunk, shape))
+
+    def coarse_cycle_choice(self, dtype=F32):
+        """(first level of the cooperative coarse-cycle launch or 0, workgroups)."""
+        lv, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().hexmg_coarse_cycle_choice(self.handle, dtype, ctypes.byref(lv), ctypes.byref(b)))
+        return lv.value, b.value
+
+    def set_coarse_cycle(self, dtype, level, blocks=0):
+        _check(lib().hexmg_set_coarse_cycle(self.handle, dtype, level, blocks))
 
     def profile_enable(self, on=True):
         _check(lib().hexmg_profile_enable(self.handle, 1 if on else 0))

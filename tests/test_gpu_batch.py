@@ -36,6 +36,8 @@ def test_multi_rhs_solve_equals_single(precision):
         for l in range(levels):  # same kernels on both grids
             for dt in (hexmg.F32, hexmg.F64):
                 grid.set_kernel_choice(l, dt, hexmg.KERNEL_STREAM, 4, 0)
+        for dt in (hexmg.F32, hexmg.F64):
+            grid.set_coarse_cycle(dt, 0)
     U = torch.empty_like(F)
     code, info = multi.solve(F, U, rtol=1e-8)  # blocks of 2, 2, 1 in lockstep
     assert code == 0
