@@ -174,6 +174,14 @@ int hexmg_compliance_sensitivity(hexmg_grid_t grid, const double *f, const doubl
 int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double *in, double *out,
                  double *tmp, void *stream);
 
+/* Sensitivity filter (Eq. 3) with the same weights:
+ *   out_e = (sum_i w_ei x_i dc_i) / (max(gamma, x_e) sum_i w_ei),
+ * 0 < rmin <= 8, gamma > 0 (the paper's small constant against division by
+ * zero; 1e-3 is usual).  x, dc, out: device, nx*ny*nz doubles in element
+ * order; out must not overlap x or dc.  Asynchronous. */
+int hexmg_sensitivity_filter(int nx, int ny, int nz, double rmin, double gamma, const double *x,
+                             const double *dc, double *out, void *stream);
+
 /* S14: one optimality-criteria update (Eqs. 8-9) on the grid's elements:
  * x_new = clamp(x B^eta, max(0, x - move), min(1, x + move)),
  * B = -dc / (lambda dv), with lambda found by bisection in log space on

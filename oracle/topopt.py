@@ -6,6 +6,9 @@
   applies them to the design, rho~ = (H x) / Hs with Hs = H 1, truncated at the
   domain boundary (only in-domain elements enter both sums).  Its adjoint is
   g_x = H^T (g / Hs) (H is symmetric).
+* Sensitivity filter (Eq. 3), the paper's own regularisation: the filtered
+  derivative of element e is sum_i w_ei x_i dc_i / (max(gamma, x_e) sum_i w_ei)
+  with the same weights; the design is then the physical density itself.
 * Optimality criteria (Eqs. 8-9): B_e = -dc/dx_e / (lambda dV/dx_e),
   x_new = clamp(x B^eta, max(0, x - m), min(1, x + m)), with the Lagrange
   multiplier found by bisection so that the volume constraint holds.  We read the
@@ -53,6 +56,12 @@ def density_filter(H, Hs, x):
 def density_filter_adjoint(H, Hs, g):
     """g_x = H^T (g / Hs)."""
     return H.T @ (np.asarray(g, dtype=np.float64) / Hs)
+
+
+def sensitivity_filter(H, Hs, x, dc, gamma=1e-3):
+    """Eq. 3: dc~_e = (sum_i H_ei x_i dc_i) / (max(gamma, x_e) Hs_e)."""
+    x = np.asarray(x, dtype=np.float64)
+    return (H @ (x * np.asarray(dc, dtype=np.float64))) / (np.maximum(gamma, x) * Hs)
 
 
 def oc_update(x, dc, dv, volume_of, volfrac, move=0.2, eta=0.5,

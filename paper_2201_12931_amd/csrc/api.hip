@@ -1004,6 +1004,18 @@ int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double*
   return 0;
 }
 
+int hexmg_sensitivity_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,
+                             double* out, void* stream) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(HEXMG_ERR_INVALID, "grid dimensions must be >= 1");
+  if (!(rmin > 0.0 && rmin <= 8.0)) return fail(HEXMG_ERR_INVALID, "need 0 < rmin <= 8");
+  if (!(gamma > 0.0)) return fail(HEXMG_ERR_INVALID, "need gamma > 0");
+  if (!x || !dc || !out || out == x || out == dc) return fail(HEXMG_ERR_INVALID, "out must not overlap x or dc");
+  if ((long long)nx * ny * nz >= (1ll << 31)) return fail(HEXMG_ERR_INVALID, "grid too large");
+  launch_sens_filter(nx, ny, nz, rmin, gamma, x, dc, out, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int hexmg_oc_update(hexmg_grid_t g, const double* x, const double* dc, const double* dv, double volfrac,
                     double move, double eta, double* x_new, double* lambda_host, void* stream) {
   if (!g || !x || !dc || !dv || !x_new) return fail(HEXMG_ERR_INVALID, "null argument");

@@ -146,6 +146,8 @@ void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double
 // Density filter and optimality criteria (topopt.hip)
 void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out, double* tmp,
                    hipStream_t s);
+void launch_sens_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,
+                        double* out, hipStream_t s);
 struct OcProbes {
   double v[kOcProbes];  // lambda_p^(-eta)
 };

@@ -58,6 +58,34 @@ __global__ void k_filter(int nx, int ny, int nz, double rmin, int R, const doubl
     out[me] = s;
 }
 
+// Sensitivity filter (Eq. 3): out_e = (sum_i w_ei x_i dc_i) / (max(gamma, x_e) sum_i w_ei)
+__global__ void k_sens_filter(int nx, int ny, int nz, double rmin, int R, double gamma, const double* __restrict__ x,
+                              const double* __restrict__ dc, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= nx) return;
+  const long long me = i + (long long)nx * (j + (long long)ny * k);
+  double s = 0.0, ws = 0.0;
+  for (int dk = -R; dk <= R; ++dk) {
+    const int kk = k + dk;
+    if (kk < 0 || kk >= nz) continue;
+    for (int dj = -R; dj <= R; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= ny) continue;
+      for (int di = -R; di <= R; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= nx) continue;
+        const double w = rmin - sqrt((double)(di * di + dj * dj + dk * dk));
+        if (w <= 0.0) continue;
+        const long long o = ii + (long long)nx * (jj + (long long)ny * kk);
+        ws += w;
+        s += w * x[o] * dc[o];
+      }
+    }
+  }
+  out[me] = s / (fmax(gamma, x[me]) * ws);
+}
+
 // Volume at kOcProbes multipliers: partial[block][p] = sum_e dv_e x_new_e(lambda_p)
 __global__ __launch_bounds__(kBlock) void k_oc_probe(long long n, const double* __restrict__ x,
                                                      const double* __restrict__ dc, const double* __restrict__ dv,
@@ -123,6 +151,13 @@ void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const doubl
   } else {
     k_filter<0><<<grid, bx, 0, s>>>(nx, ny, nz, rmin, R, in, out);
   }
+}
+
+void launch_sens_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,
+                        double* out, hipStream_t s) {
+  const int R = (int)std::ceil(rmin) - 1;
+  const int bx = 64;
+  k_sens_filter<<<dim3((nx + bx - 1) / bx, ny, nz), bx, 0, s>>>(nx, ny, nz, rmin, R, gamma, x, dc, out);
 }
 
 void launch_oc_probe(long long n, const double* x, const double* dc, const double* dv, double eta, double move,

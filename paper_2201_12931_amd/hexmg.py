@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(i), d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_element_matrix": (i, [d, vp]),
             "hexmg_filter": (i, [i, i, i, d, i, vp, vp, vp, vp]),
+            "hexmg_sensitivity_filter": (i, [i, i, i, d, d, vp, vp, vp, vp]),
             "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), vp]),
             "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_set_kernel_choice": (i, [vp, i, i, i, i, i]),
@@ -171,6 +172,19 @@ def density_filter(nx, ny, nz, rmin, x, out=None, adjoint=False, tmp=None, strea
     _check(lib().hexmg_filter(nx, ny, nz, float(rmin), 1 if adjoint else 0, _dev(x, torch.float64, n, "x"),
                               _dev(out, torch.float64, n, "out"),
                               _dev(tmp, torch.float64, n, "tmp") if adjoint else None, _stream(stream)))
+    return out
+
+
+def sensitivity_filter(nx, ny, nz, rmin, x, dc, out=None, gamma=1e-3, stream=None):
+    """Eq. 3: dc~ = H (x dc) / (max(gamma, x) Hs) on the GPU; returns out."""
+    import torch
+
+    n = nx * ny * nz
+    if out is None:
+        out = torch.empty_like(dc)
+    _check(lib().hexmg_sensitivity_filter(nx, ny, nz, float(rmin), float(gamma), _dev(x, torch.float64, n, "x"),
+                                          _dev(dc, torch.float64, n, "dc"), _dev(out, torch.float64, n, "out"),
+                                          _stream(stream)))
     return out
 
 

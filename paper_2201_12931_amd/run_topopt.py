@@ -4,6 +4,8 @@ gradient.
 
     python -m paper_2201_12931_amd.run_topopt --nx 256 --ny 128 --nz 128 --levels 6 \\
         --iters 20 --volfrac 0.12 --fd 64
+    python -m paper_2201_12931_amd.run_topopt --nx 64 --ny 32 --nz 32 --levels 4 \\
+        --filter sensitivity --volfrac 0.3 --iters 300 --until 0.01
 
 Prints one JSON line per OC iteration and a summary line.  The finite-difference
 check compares dc/dx_e from the adjoint with the central difference
@@ -41,9 +43,16 @@ def fd_check(opt: TopOpt, f, elems, h=1e-4, rtol=1e-10, levels=None):
     the adjoint gradient from a binary64 solve (and the solver's own gradient)."""
     nx, ny, nz = opt.shape
     grid = hexmg.Grid(nx, ny, nz, levels or opt.grid.levels, precision=hexmg.FP64)
-    _, grad_run, rho = opt.gradient(opt.x)
+    # the unfiltered derivative of c(x) (with the sensitivity filter the
+    # optimiser uses a filtered one, which is not a derivative)
+    xg = opt.x.detach().clone().requires_grad_(True)
+    c_run, rho = opt.objective(xg)
+    c_run.backward()
+    grad_run = xg.grad.detach()
+    rho = rho.detach()
     xr = opt.x.detach().clone().requires_grad_(True)
-    c = Compliance.apply(DensityFilter.apply(xr, opt.shape, opt.rmin), grid, f, rtol, 1000)
+    phys = DensityFilter.apply(xr, opt.shape, opt.rmin) if opt.filter == "density" else xr
+    c = Compliance.apply(phys, grid, f, rtol, 1000)
     c.backward()
     grad = xr.grad.detach()
     out = []
@@ -51,12 +60,13 @@ def fd_check(opt: TopOpt, f, elems, h=1e-4, rtol=1e-10, levels=None):
     d = torch.empty_like(f)
     ym = torch.empty_like(f)
     yp = torch.empty_like(f)
+    dens = opt.filter == "density"
     for e in elems:
         xp, xm = opt.x.clone(), opt.x.clone()
         xp[e] += h
         xm[e] -= h
-        rp = hexmg.density_filter(nx, ny, nz, opt.rmin, xp)
-        rm = hexmg.density_filter(nx, ny, nz, opt.rmin, xm)
+        rp = hexmg.density_filter(nx, ny, nz, opt.rmin, xp) if dens else xp
+        rm = hexmg.density_filter(nx, ny, nz, opt.rmin, xm) if dens else xm
         grid.set_density(rm)
         grid.solve(f, u, rtol=rtol, maxit=1000)
         grid.apply_K(u, ym)
@@ -86,16 +96,21 @@ def main():
     ap.add_argument("--fd-seed", type=int, default=2)
     ap.add_argument("--fp64", action="store_true", help="binary64 V-cycle instead of the mixed-precision one")
     ap.add_argument("--coarse-avg", choices=["density", "modulus"], default="density")
+    ap.add_argument("--filter", choices=["density", "sensitivity"], default="density")
+    ap.add_argument("--until", type=float, default=0.0,
+                    help="stop once the largest design change is below this (Alg. 4 uses 0.01); 0 = run --iters")
     args = ap.parse_args()
 
     g = W.Grid(args.nx, args.ny, args.nz)
     f = torch.from_numpy(W.cantilever_line_load(g)).cuda()
     opt = TopOpt(args.nx, args.ny, args.nz, args.levels, f, args.volfrac, rmin=args.rmin, rtol=args.rtol,
                  precision=hexmg.FP64 if args.fp64 else hexmg.MIXED,
-                 coarse_avg=hexmg.AVG_DENSITY if args.coarse_avg == "density" else hexmg.AVG_MODULUS)
+                 coarse_avg=hexmg.AVG_DENSITY if args.coarse_avg == "density" else hexmg.AVG_MODULUS,
+                 filter=args.filter)
     summary = {"grid": [args.nx, args.ny, args.nz], "elements": g.n_elem, "dofs": g.n_dof,
                "levels": args.levels, "volfrac": args.volfrac, "rmin": args.rmin, "rtol": args.rtol,
-               "coarse_avg": args.coarse_avg, "precision": "fp64" if args.fp64 else "mixed"}
+               "coarse_avg": args.coarse_avg, "precision": "fp64" if args.fp64 else "mixed",
+               "filter": args.filter, "until": args.until}
     rng = np.random.Generator(np.random.PCG64(args.fd_seed))
 
     def fd_elements():
@@ -103,7 +118,8 @@ def main():
         # x +- h inside [0, 1]
         h = 1e-4
         with torch.no_grad():
-            rho = hexmg.density_filter(args.nx, args.ny, args.nz, args.rmin, opt.x).cpu().numpy()
+            rho = (hexmg.density_filter(args.nx, args.ny, args.nz, args.rmin, opt.x) if args.filter == "density"
+                   else opt.x).cpu().numpy()
         x = opt.x.cpu().numpy()
         cand = np.flatnonzero((rho >= 0.05) & (x >= h) & (x <= 1.0 - h))
         return rng.choice(cand, size=min(args.fd, cand.size), replace=False)
@@ -126,8 +142,11 @@ def main():
         rec["seconds"] = time.perf_counter() - ts
         hist.append(rec)
         print(json.dumps(rec), flush=True)
+        if args.until > 0 and r.change < args.until:
+            break
     summary["oc_seconds"] = time.perf_counter() - t0
-    summary["seconds_per_iteration"] = summary["oc_seconds"] / max(args.iters, 1)
+    summary["oc_iterations"] = len(hist)
+    summary["seconds_per_iteration"] = summary["oc_seconds"] / max(len(hist), 1)
     summary["final"] = hist[-1] if hist else None
     if args.fd and args.iters:
         t0 = time.perf_counter()
@@ -135,7 +154,7 @@ def main():
         summary["fd_final"] = {"max_rel_err": max(r["rel_err"] for r in res), "n": len(res),
                                "solver_max_rel_err": max(r["solver_rel_err"] for r in res),
                                "seconds": time.perf_counter() - t0}
-        print(json.dumps({"fd_iteration": args.iters, "results": res}), flush=True)
+        print(json.dumps({"fd_iteration": len(hist), "results": res}), flush=True)
     print(json.dumps({"summary": summary}), flush=True)
 
 

@@ -1,10 +1,16 @@
-"""Optimality-criteria topology-optimisation loop (Alg. 4 of the paper, with the
-density filter in place of the sensitivity filter) on the hexmg C ABI.
+"""Optimality-criteria topology-optimisation loop (Alg. 4 of the paper) on the
+hexmg C ABI, with either regularisation:
 
-Per iteration: rho~ = filter(x) -> c = Compliance(rho~) (MGPCG state solve) ->
-backward (adjoint sensitivity, Eq. 7, then the filter adjoint) -> OC update
-(Eqs. 8-9) with the filtered volume.  All arithmetic runs in the HIP library;
-autograd only chains the two hand-written adjoints.
+* filter="sensitivity" (the paper's, Eq. 3): c = Compliance(x) (MGPCG state
+  solve) -> backward (adjoint sensitivity, Eq. 7) -> filtered sensitivity ->
+  OC update (Eqs. 8-9) with V = mean(x);
+* filter="density": rho~ = filter(x) -> c = Compliance(rho~) -> backward
+  (adjoint sensitivity, then the filter adjoint) -> OC update with the
+  filtered volume.
+
+All arithmetic runs in the HIP library; autograd only chains the hand-written
+adjoints.  ``run(max_iters, tol)`` iterates until the largest design change
+drops below tol (Alg. 4 stops at 0.01).
 """
 from __future__ import annotations
 
@@ -29,30 +35,43 @@ class OCResult:
 
 class TopOpt:
     def __init__(self, nx, ny, nz, levels, f, volfrac, rmin=1.5, move=0.2, eta=0.5,
-                 precision=hexmg.MIXED, rtol=1e-6, maxit=500, x0=None, device="cuda", **grid_kw):
+                 precision=hexmg.MIXED, rtol=1e-6, maxit=500, x0=None, device="cuda", filter="density",
+                 gamma=1e-3, **grid_kw):
+        if filter not in ("density", "sensitivity"):
+            raise ValueError("filter must be 'density' or 'sensitivity'")
         self.shape = (nx, ny, nz)
         self.n = nx * ny * nz
         self.volfrac, self.rmin, self.move, self.eta = volfrac, rmin, move, eta
         self.rtol, self.maxit = rtol, maxit
+        self.filter, self.gamma = filter, gamma
         self.grid = hexmg.Grid(nx, ny, nz, levels, precision=precision, device=device, **grid_kw)
         self.f = f
         self.x = (torch.full((self.n,), float(volfrac), dtype=torch.float64, device=device)
                   if x0 is None else x0.clone())
-        # dV/dx of V = mean(rho~): the filter adjoint of 1/Ne
-        self.dv = hexmg.density_filter(nx, ny, nz, rmin, torch.full_like(self.x, 1.0 / self.n), adjoint=True)
+        if filter == "density":
+            # dV/dx of V = mean(rho~): the filter adjoint of 1/Ne
+            self.dv = hexmg.density_filter(nx, ny, nz, rmin, torch.full_like(self.x, 1.0 / self.n), adjoint=True)
+        else:
+            self.dv = torch.full_like(self.x, 1.0 / self.n)
         self.it = 0
 
     def objective(self, x):
-        """c(x) through the filter and the state solve; returns (c_total, rho~)."""
-        rho = DensityFilter.apply(x, self.shape, self.rmin)
+        """c(x) through the density filter (if any) and the state solve; returns
+        (c_total, physical densities)."""
+        rho = DensityFilter.apply(x, self.shape, self.rmin) if self.filter == "density" else x
         c = Compliance.apply(rho, self.grid, self.f, self.rtol, self.maxit)
         return c.sum(), rho
 
     def gradient(self, x):
+        """(c, dc/dx as used by the update, physical densities).  With the
+        sensitivity filter the returned derivative is the filtered one (Eq. 3)."""
         xr = x.detach().clone().requires_grad_(True)
         c, rho = self.objective(xr)
         c.backward()
-        return c.detach(), xr.grad.detach(), rho.detach()
+        g = xr.grad.detach()
+        if self.filter == "sensitivity":
+            g = hexmg.sensitivity_filter(*self.shape, self.rmin, x.detach(), g, gamma=self.gamma)
+        return c.detach(), g, rho.detach()
 
     def step(self) -> OCResult:
         c, dc, rho = self.gradient(self.x)
@@ -62,3 +81,16 @@ class TopOpt:
         self.it += 1
         info = self.grid.last_info[0]
         return OCResult(self.it, float(c), float(rho.mean()), change, lam, info["iterations"], info["rel_res_true"])
+
+    def run(self, max_iters, tol=0.01, callback=None):
+        """OC iterations until max |x_new - x| < tol or max_iters; returns the
+        list of OCResult."""
+        hist = []
+        for _ in range(max_iters):
+            r = self.step()
+            hist.append(r)
+            if callback is not None:
+                callback(r)
+            if r.change < tol:
+                break
+        return hist

@@ -1,4 +1,5 @@
-"""Pins of the oracle's density filter (Eqs. 4-5) and OC update (Eqs. 8-9)."""
+"""Pins of the oracle's density filter (Eqs. 4-5), sensitivity filter (Eq. 3)
+and OC update (Eqs. 8-9)."""
 import math
 
 import numpy as np
@@ -77,3 +78,42 @@ def test_oc_volume_and_bounds():
     assert np.all(xn <= np.minimum(1, x + 0.2) + 1e-15)
     # the filtered volume is linear in x: mean(rho~(z)) = dv_x . z
     assert vol(xn) == pytest.approx(float(dvx @ xn), rel=1e-13)
+
+
+def test_sensitivity_filter_brute_force():
+    """Eq. 3 by explicit loops over element centres, independent of the CSR matrix."""
+    nx, ny, nz, r, gamma = 3, 4, 2, 1.5, 1e-3
+    H, Hs = T.filter_matrix(nx, ny, nz, r)
+    n = nx * ny * nz
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.0, 1.0, n)
+    x[3] = 0.0  # below gamma: the denominator uses gamma
+    dc = -rng.uniform(0.1, 2.0, n)
+    out = T.sensitivity_filter(H, Hs, x, dc, gamma)
+    for e in range(n):
+        ce = (e % nx, (e // nx) % ny, e // (nx * ny))
+        num = den = 0.0
+        for i in range(n):
+            d = math.dist(ce, (i % nx, (i // nx) % ny, i // (nx * ny)))
+            if d <= r:
+                num += (r - d) * x[i] * dc[i]
+                den += r - d
+        assert out[e] == pytest.approx(num / (max(gamma, x[e]) * den), rel=1e-13)
+
+
+def test_sensitivity_filter_special_cases():
+    nx, ny, nz = 5, 4, 3
+    n = nx * ny * nz
+    H, Hs = T.filter_matrix(nx, ny, nz, 1.5)
+    # uniform design and sensitivity: the weighted mean of a constant
+    assert np.allclose(T.sensitivity_filter(H, Hs, np.full(n, 0.4), np.full(n, -3.0)), -3.0, rtol=1e-14)
+    # radius below one element: only the self weight, so dc~ = x dc / max(gamma, x)
+    H1, Hs1 = T.filter_matrix(nx, ny, nz, 0.9)
+    rng = np.random.default_rng(12)
+    x, dc = rng.uniform(0.01, 1.0, n), rng.standard_normal(n)
+    assert np.allclose(T.sensitivity_filter(H1, Hs1, x, dc), dc, rtol=1e-14)
+    # linear in dc
+    d2 = rng.standard_normal(n)
+    a = T.sensitivity_filter(H, Hs, x, dc + 2.0 * d2)
+    b = T.sensitivity_filter(H, Hs, x, dc) + 2.0 * T.sensitivity_filter(H, Hs, x, d2)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-14)
