@@ -12,6 +12,11 @@ as a sparse matrix so that it can be read against the text:
 * the coarse element stiffness is re-computed "on the fly" for an element of
   side h = 2^l, i.e. 2^l * K0 (3-D elasticity scales linearly with h);
 * a coarse DOF is fixed iff the coincident fine DOF is fixed;
+* ``coarse_operator="galerkin"`` replaces the re-discretized coarse operators
+  by the Galerkin products of Eq. 23, A_{l+1} = P~^T A_l P~ + (I - M_{l+1})
+  with P~ = M_l P M_{l+1} (prolongation that leaves fixed DOFs untouched on both
+  levels), so the coarse-grid correction is the A-orthogonal projection onto
+  the range of P~;
 * transfer: trilinear interpolation P (tensor product of 1-D linear
   interpolation) and restriction R = P^T (variational; the paper's 1/4 [1 2 1]
   stencil of Eq. 22 differs by a constant factor, which does not change the
@@ -67,7 +72,10 @@ class Hierarchy:
     """All levels of the assembled multigrid for one density field."""
 
     def __init__(self, nx, ny, nz, rho, node_mask, levels, E0=1.0, Emin=1e-9,
-                 p=3.0, nu=0.3, omega=0.6, sweeps=2, coarse_average="density"):
+                 p=3.0, nu=0.3, omega=0.6, sweeps=2, coarse_average="density",
+                 coarse_operator="rediscretize"):
+        if coarse_operator not in ("rediscretize", "galerkin"):
+            raise ValueError(coarse_operator)
         if levels < 1:
             raise ValueError("levels >= 1")
         for n in (nx, ny, nz):
@@ -105,6 +113,11 @@ class Hierarchy:
             self.free.append(free.astype(np.float64))
         for l in range(levels - 1):
             self.P.append(prolongation(*self.dims[l + 1]))
+        if coarse_operator == "galerkin":
+            for l in range(1, levels):
+                Pt = sp.diags(self.free[l - 1]) @ self.P[l - 1] @ sp.diags(self.free[l])
+                self.A[l] = (Pt.T @ self.A[l - 1] @ Pt + sp.diags(1.0 - self.free[l])).tocsr()
+                self.D[l] = self.A[l].diagonal().copy()
         self._coarse = sla.cho_factor(self.A[-1].toarray(), lower=True)
 
     # -- pieces of Alg. 3 --------------------------------------------------

@@ -117,3 +117,54 @@ def test_jacobi_smoother_reduces_energy_error():
         en = float(e @ (h.A[0] @ e))
         assert en < prev
         prev = en
+
+
+def test_galerkin_hierarchy_equals_rediscretized_for_uniform_density():
+    """Eq. 23 products with the supports: for a uniform density every Galerkin
+    coarse operator equals the re-discretized one (the face x = 0 is fixed, so the
+    masked prolongation is exercised)."""
+    g = W.Grid(8, 4, 4)
+    rho = np.full(g.n_elem, 0.45)
+    mask = W.fixed_mask_face_x0(g)
+    hr = mg.Hierarchy(8, 4, 4, rho, mask, 3)
+    hg = mg.Hierarchy(8, 4, 4, rho, mask, 3, coarse_operator="galerkin")
+    for l in range(3):
+        d = (hr.A[l] - hg.A[l]).toarray()
+        assert np.abs(d).max() < 1e-13 * abs(hr.A[l]).max(), l
+
+
+def test_galerkin_coarse_correction_is_a_projection():
+    """With Galerkin operators the two-grid coarse correction
+    C = I - P~ A_c^-1 P~^T A is an A-orthogonal projection on the free DOFs
+    (C^2 = C and A C symmetric); the re-discretized operator on a random field
+    is not, which shows the check can fail."""
+    g = W.Grid(8, 4, 4)
+    rho = W.random_field_density(g, seed=4, length_scale=2.0, lo=0.05)
+    mask = W.fixed_mask_face_x0(g)
+    rng = np.random.default_rng(9)
+    errs = {}
+    for op in ("galerkin", "rediscretize"):
+        h = mg.Hierarchy(8, 4, 4, rho, mask, 2, coarse_operator=op)
+        A, Ac = h.A[0].toarray(), h.A[1].toarray()
+        Pt = np.diag(h.free[0]) @ h.P[0].toarray() @ np.diag(h.free[1])
+        C = np.eye(A.shape[0]) - Pt @ np.linalg.solve(Ac, Pt.T @ A)
+        Mf = np.diag(h.free[0])
+        x = h.free[0] * rng.standard_normal(A.shape[0])
+        errs[op] = np.linalg.norm(Mf @ C @ (Mf @ C @ x) - Mf @ C @ x) / np.linalg.norm(x)
+        if op == "galerkin":
+            AC = Mf @ A @ C @ Mf
+            assert np.abs(AC - AC.T).max() < 1e-10 * np.abs(AC).max()
+    assert errs["galerkin"] < 1e-10
+    assert errs["rediscretize"] > 1e-3
+
+
+def test_galerkin_mgpcg_matches_direct():
+    g = W.Grid(16, 8, 8)
+    rho = W.random_field_density(g, seed=2, length_scale=3.0, lo=0.01)
+    mask = W.fixed_mask_face_x0(g)
+    f = W.cantilever_line_load(g)
+    free = fem.free_dof_mask(mask)
+    u_ref = fem.solve_direct(fem.assemble_stiffness(16, 8, 8, fem.simp_modulus(rho)), f, free)
+    h = mg.Hierarchy(16, 8, 8, rho, mask, 3, coarse_operator="galerkin")
+    u, its, rel, _ = mg.mgpcg(h, f, rtol=1e-10)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-8
