@@ -67,6 +67,10 @@ extern "C" {
 #define HEXMG_AVG_DENSITY 0 /* coarse rho = mean of the 8 children, then E(rho) (Sec. 4.2.2) */
 #define HEXMG_AVG_MODULUS 1 /* coarse E = mean of the 8 children's E */
 
+/* Coarse operators */
+#define HEXMG_COARSE_REDISCRETIZE 0 /* coarse element stiffness from the homogenized density (Sec. 4.2.2, default) */
+#define HEXMG_COARSE_GALERKIN 1     /* A_{l+1} = P^T A_l P with the supports (Eq. 23), stored as 27-point stencils */
+
 typedef struct hexmg_grid *hexmg_grid_t;
 
 typedef struct {
@@ -82,10 +86,15 @@ typedef struct {
   const uint8_t *fixed_mask; /* device, (nx+1)(ny+1)(nz+1) bytes; NULL = face x = 0 fixed.
                                 Copied at hexmg_grid_create; coarse masks are injected
                                 (coarse node fixed iff the coincident fine node is). */
+  int coarse_op;        /* HEXMG_COARSE_REDISCRETIZE | HEXMG_COARSE_GALERKIN.  Galerkin levels
+                           store 243 coefficients per node in both precisions (about
+                           2.9 kB per coarse node) and are applied as stencils; the
+                           cooperative coarse-cycle launch is not used with them. */
 } hexmg_grid_desc;
 
 /* Fill *desc with the defaults (E0 1, Emin 1e-9, nu 0.3, penal 3, FP64, 2 sweeps,
- * omega 0.6, density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0)
+ * omega 0.6, density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0,
+ * re-discretized coarse operators)
  * for the given grid.  Host only. */
 int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc *desc);
 

@@ -64,6 +64,8 @@ int validate(const hexmg_grid_desc* d) {
   if (d->max_nrhs < 1) return fail(HEXMG_ERR_INVALID, "max_nrhs must be >= 1");
   if (d->kernel != HEXMG_KERNEL_STREAM && d->kernel != HEXMG_KERNEL_GATHER && d->kernel != HEXMG_KERNEL_AUTO)
     return fail(HEXMG_ERR_INVALID, "bad kernel");
+  if (d->coarse_op != HEXMG_COARSE_REDISCRETIZE && d->coarse_op != HEXMG_COARSE_GALERKIN)
+    return fail(HEXMG_ERR_INVALID, "bad coarse_op");
   return 0;
 }
 
@@ -142,6 +144,16 @@ size_t carve(hexmg_grid* g, char* base) {
   g->active = c.take<int>(R);
   g->oc_partials = c.take<double>((size_t)kReduceBlocks * kOcProbes);
   g->oc_vol = c.take<double>(kOcProbes);
+  g->galerkin = g->desc.coarse_op == HEXMG_COARSE_GALERKIN && L > 1;
+  g->S64.assign(L, nullptr);
+  g->S32.assign(L, nullptr);
+  g->Gc = c.take<double>(8 * 576);
+  if (g->galerkin) {
+    for (int l = 1; l < L; ++l) {
+      g->S64[l] = c.take<double>(243ull * g->lv[l].nn);
+      g->S32[l] = c.take<float>(243ull * g->lv[l].nn);
+    }
+  }
   return c.off + 256;
 }
 
@@ -182,7 +194,14 @@ void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int le
   const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
   const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
   const Level& L = g->lv[level];
-  if (ch.kernel == HEXMG_KERNEL_GATHER) {
+  if (g->galerkin && level > 0) {
+    const T* S;
+    if constexpr (sizeof(T) == 4)
+      S = g->S32[level];
+    else
+      S = g->S64[level];
+    launch_stencil<T>(mode, L, S, u, f, wd, y, nrhs, act, s, t);
+  } else if (ch.kernel == HEXMG_KERNEL_GATHER) {
     launch_gather<T>(mode, L, Ke, E, u, f, wd, y, nrhs, act, s, t);
   } else {
     const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
@@ -233,7 +252,7 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_gr
 }
 
 int tune_kernels(hexmg_grid* g, hipStream_t s) {
-  for (int l = 0; l < g->L; ++l) {
+  for (int l = 0; l < (g->galerkin ? 1 : g->L); ++l) {
     if (int e = tune_level<double>(g, l, g->vu64[l], g->vf64[l], g->vt64[l], g->wd64[l], &g->choice64[l], s)) return e;
     if (int e = tune_level<float>(g, l, g->vu32[l], g->vf32[l], g->vt32[l], g->wd32[l], &g->choice32[l], s)) return e;
   }
@@ -393,7 +412,7 @@ int tune_tail(hexmg_grid* g, hipStream_t s) {
   tail = 0;
   tblocks = 0;
   const int maxb = coarse_cycle_max_blocks<T>();
-  if (g->L < 3 || maxb <= 0) return 0;
+  if (g->L < 3 || maxb <= 0 || g->galerkin) return 0;
   VView<T> v = [&] {
     if constexpr (sizeof(T) == 4)
       return view32(g);
@@ -582,6 +601,11 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   if (hipMemcpyAsync(g->Ke64, Ke, sizeof(Ke), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(g->Ke32, Kf, sizeof(Kf), hipMemcpyHostToDevice, s) != hipSuccess)
     return cleanup(fail(HEXMG_ERR_DEVICE, "copy of the element matrix failed"));
+  g->Gc_host.resize(8 * 576);
+  galerkin_child_matrices(Ke, g->Gc_host.data());
+  if (hipMemcpyAsync(g->Gc, g->Gc_host.data(), g->Gc_host.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return cleanup(fail(HEXMG_ERR_DEVICE, "copy of the Galerkin child matrices failed"));
   if (d->fixed_mask) {
     if (hipMemcpyAsync(g->mask[0], d->fixed_mask, g->lv[0].nn, hipMemcpyDeviceToDevice, s) != hipSuccess)
       return cleanup(fail(HEXMG_ERR_DEVICE, "copy of the support mask failed"));
@@ -624,10 +648,19 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     else
       launch_modulus_from_mean(g->lv[l - 1], g->lv[l], g->E64[l - 1], 2.0, g->E64[l], g->E32[l], s);
   }
-  for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], d.omega, g->wd64[l], g->wd32[l], s);
-  // Coarsest level: assemble, invert by Gauss-Jordan, symmetrize.
   const int nc = g->nc;
-  launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], s);
+  if (g->galerkin) {  // Eq. 23 products, level by level, as stencils
+    launch_galerkin_first(g->lv[0], g->lv[1], g->E64[0], g->Gc, g->Ke64, g->S64[1], g->S32[1], s);
+    for (int l = 1; l + 1 < g->L; ++l)
+      launch_galerkin_coarsen(g->lv[l], g->lv[l + 1], g->S64[l], g->S64[l + 1], g->S32[l + 1], s);
+    launch_diag(g->lv[0], g->Ke64, g->E64[0], d.omega, g->wd64[0], g->wd32[0], s);
+    for (int l = 1; l < g->L; ++l) launch_stencil_diag(g->lv[l], g->S64[l], d.omega, g->wd64[l], g->wd32[l], s);
+    launch_dense_from_stencil(g->lv[g->L - 1], g->S64[g->L - 1], g->Abuf[0], s);
+  } else {
+    for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], d.omega, g->wd64[l], g->wd32[l], s);
+    // Coarsest level: assemble, invert by Gauss-Jordan, symmetrize.
+    launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], s);
+  }
   double* inv = nullptr;
   launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, g->gjX, &inv, s);
   double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
@@ -1110,6 +1143,8 @@ int hexmg_set_coarse_cycle(hexmg_grid_t g, int dtype, int level, int blocks) {
   if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
   if (level != 0 && (level < 1 || level > g->L - 2))
     return fail(HEXMG_ERR_INVALID, "level must be 0 (off) or in [1, levels - 2]");
+  if (level != 0 && g->galerkin)
+    return fail(HEXMG_ERR_INVALID, "the cooperative coarse cycle is not available with Galerkin coarse operators");
   if (blocks < 0) return fail(HEXMG_ERR_INVALID, "blocks must be >= 0");
   int b = 0;
   if (level) {

@@ -156,6 +156,19 @@ void launch_oc_probe(long long n, const double* x, const double* dc, const doubl
 void launch_oc_apply(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
                      double lam_pow, double* xn, hipStream_t s);
 
+// Galerkin coarse operators (galerkin.hip): 27-point block stencils,
+// coefficient (9 o + 3 ci + cj) of node n at S[(9 o + 3 ci + cj) * nn + n].
+void launch_galerkin_first(const Level& F, const Level& C, const double* E, const double* G, const double* Ke,
+                           double* S64, float* S32, hipStream_t s);
+void launch_galerkin_coarsen(const Level& F, const Level& C, const double* Sf, double* S64, float* S32,
+                             hipStream_t s);
+template <typename T>
+void launch_stencil(int mode, const Level& L, const T* S, const T* u, const T* f, const T* wd, T* y, int nrhs,
+                    const int* act, hipStream_t s, const LaunchTimer& t = {});
+void launch_stencil_diag(const Level& L, const double* S, double omega, double* wd64, float* wd32, hipStream_t s);
+void launch_dense_from_stencil(const Level& C, const double* S, double* A, hipStream_t s);
+void galerkin_child_matrices(const double* Ke, double* G);  // host: 8 x 576
+
 // The coarse part of the V-cycle in one cooperative launch (coarse.hip):
 // levels, operators and vectors of one precision.  f[ls] holds the restricted
 // right-hand side of the first level ls of the launch and t[ls] its first
@@ -226,6 +239,13 @@ struct hexmg_grid {
   int nc;         // coarsest DOFs
   double* Ke64;   // 576
   float* Ke32;
+  // Galerkin coarse operators (desc.coarse_op == HEXMG_COARSE_GALERKIN):
+  // stencils of levels >= 1 in both precisions, and the 8 child matrices G_c
+  bool galerkin = false;
+  std::vector<double*> S64;
+  std::vector<float*> S32;
+  double* Gc = nullptr;
+  std::vector<double> Gc_host;
   hexmg::HaarCoef<double> hq64;
   hexmg::HaarCoef<float> hq32;
   // element-product kernel per level and precision ([level][0] binary64, [1] binary32)

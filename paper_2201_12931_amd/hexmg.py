@@ -23,6 +23,7 @@ FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 AVG_DENSITY, AVG_MODULUS = 0, 1
 KERNEL_STREAM, KERNEL_GATHER, KERNEL_AUTO = 0, 1, 2
+COARSE_REDISCRETIZE, COARSE_GALERKIN = 0, 1
 
 
 class HexmgError(RuntimeError):
@@ -39,7 +40,7 @@ class GridDesc(ctypes.Structure):
         ("penal", ctypes.c_double),
         ("precision", ctypes.c_int), ("smooth_sweeps", ctypes.c_int),
         ("omega", ctypes.c_double), ("coarse_avg", ctypes.c_int), ("max_nrhs", ctypes.c_int),
-        ("kernel", ctypes.c_int), ("fixed_mask", ctypes.c_void_p),
+        ("kernel", ctypes.c_int), ("fixed_mask", ctypes.c_void_p), ("coarse_op", ctypes.c_int),
     ]
 
 
