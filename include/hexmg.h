@@ -191,14 +191,40 @@ int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double 
 int hexmg_sensitivity_filter(int nx, int ny, int nz, double rmin, double gamma, const double *x,
                              const double *dc, double *out, void *stream);
 
+/* Self-weight of the design, the design-dependent gravity loading of the
+ * paper's foot-bridge example (Sec. 5): f = f_ext + f_g(rho) with, for every
+ * element of unit volume and unit mass density, the body force -gz rho_e
+ * along z shared equally by its eight nodes (the consistent load of the
+ * trilinear element).  rho is the density of the last hexmg_set_density.
+ * f_ext: device, N doubles, or NULL (zero); f: device, N doubles, not
+ * overlapping f_ext.  Asynchronous. */
+int hexmg_gravity_load(hexmg_grid_t grid, double gz, const double *f_ext, double *f, void *stream);
+
+/* Load part of the compliance derivative when f depends on the design:
+ * dc/drho_e = 2 u^T df/drho_e - u^T dK/drho_e u.  Adds
+ * weight * 2 * (-gz / 8) * (sum of u_z over the element's nodes) to dc
+ * (device, nx*ny*nz doubles; accumulates, so call it after
+ * hexmg_compliance_sensitivity).  u: device, N doubles.  Asynchronous. */
+int hexmg_gravity_sensitivity(hexmg_grid_t grid, const double *u, double gz, double weight, double *dc,
+                              void *stream);
+
+/* Passive regions (the paper's bridge examples): passive[e] = 1 sets x_e = 1
+ * (solid), 2 sets x_e = 0 (void), 0 leaves it (design).  n elements; passive,
+ * x: device.  Elements whose dv is 0 in hexmg_oc_update stay outside the
+ * volume constraint and keep their value, so passive elements are given
+ * dv = 0 there and this is applied to the result.  Asynchronous. */
+int hexmg_apply_passive(long long n, const uint8_t *passive, double *x, void *stream);
+
 /* S14: one optimality-criteria update (Eqs. 8-9) on the grid's elements:
  * x_new = clamp(x B^eta, max(0, x - move), min(1, x + move)),
  * B = -dc / (lambda dv), with lambda found by bisection in log space on
  * [1e-12, 1e12] (to a relative width of 1e-12) so that dv^T x_new = volfrac,
  * where dv = dV/dx (for the filtered volume V = mean(rho~) that is
  * H (1/(Ne Hs)), so dv^T x is exactly the filtered volume).  x, dc, dv:
- * device, Ne doubles (dc <= 0, dv > 0); x_new: device, Ne doubles, distinct
- * from the inputs.  lambda_host (host, may be NULL) receives lambda.
+ * device, Ne doubles (dc <= 0, dv >= 0; an element with dv = 0 is outside the
+ * volume constraint and keeps its x, e.g. a passive one); x_new: device, Ne
+ * doubles, distinct from the inputs.  lambda_host (host, may be NULL)
+ * receives lambda.
  * Synchronises the stream once per bisection pass (32 multipliers per pass). */
 int hexmg_oc_update(hexmg_grid_t grid, const double *x, const double *dc, const double *dv, double volfrac,
                     double move, double eta, double *x_new, double *lambda_host, void *stream);

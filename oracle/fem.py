@@ -10,6 +10,8 @@ Follows Sec. 2 of the paper:
 * Eq. 7: dc/drho_e = -u_e^T (p rho_e^(p-1) (K0 - K_min)) u_e, with u* = u because
   the compliance is self-adjoint; in our reading that is
   -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e.
+* Self-weight (the foot-bridge example's gravity loading): a load that depends
+  on the design, f(rho), adds 2 u^T df/drho_e to the derivative.
 
 Supports are imposed by elimination: fixed DOFs are removed from the system and
 carry u = 0.  For operator-level comparisons the same supports are written as
@@ -140,3 +142,25 @@ def apply_constrained_at_nodes(nx, ny, nz, E, node_mask, u, nodes, nu=0.3, h=1.0
             d = 3 * n + c
             out[t, c] = acc[c] if free[d] else u[d]
     return out
+
+
+def gravity_load(nx, ny, nz, rho, g=1.0) -> np.ndarray:
+    """Self-weight of the design (the gravity loading of the paper's foot-bridge
+    example): element e of unit volume and unit mass density carries the body
+    force -g rho_e along z.  For the trilinear element each shape function
+    integrates to 1/8 of the element volume, so each of its eight nodes takes
+    -g rho_e / 8."""
+    rho = np.asarray(rho, dtype=np.float64)
+    f = np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1))
+    nodes = element_nodes(nx, ny, nz)
+    np.add.at(f, 3 * nodes.reshape(-1) + 2, np.repeat(-g * rho / 8.0, 8))
+    return f
+
+
+def gravity_sensitivity(nx, ny, nz, u, g=1.0) -> np.ndarray:
+    """Load part of dc/drho_e for c = f(rho)^T u with K u = f(rho):
+    dc/drho_e = 2 u^T df/drho_e - u^T dK/drho_e u; this returns the first term,
+    2 (-g / 8) (sum of u_z over the element's nodes)."""
+    u = np.asarray(u, dtype=np.float64)
+    uz = u[3 * element_nodes(nx, ny, nz) + 2]
+    return 2.0 * (-g / 8.0) * uz.sum(axis=1)

@@ -6,8 +6,11 @@
   is the hand-written adjoint sensitivity of Eq. 7 with u* = u (the compliance
   is self-adjoint, so no second solve), weighted by the incoming gradient per
   load case.
+* ``SelfWeightCompliance``: as ``Compliance`` for one load case whose load
+  includes the self-weight of the design, f = f_ext + f_g(rho); the derivative
+  gains the load term 2 u^T df/drho.
 
-Both run entirely in the HIP library; tensors only carry device memory.
+All run entirely in the HIP library; tensors only carry device memory.
 """
 from __future__ import annotations
 
@@ -57,3 +60,33 @@ class Compliance(torch.autograd.Function):
         dc = torch.empty_like(rho)
         grid.compliance_sensitivity(f, u, dc=dc, weights=w)
         return dc, None, None, None, None
+
+
+class SelfWeightCompliance(torch.autograd.Function):
+    """c = SelfWeightCompliance.apply(rho, grid, f_ext, gz, rtol, maxit): one load
+    case, f = f_ext + self-weight of rho (gravity gz along -z)."""
+
+    @staticmethod
+    def forward(ctx, rho, grid, f_ext, gz, rtol=1e-6, maxit=500):
+        rho = rho.detach().contiguous()
+        grid.set_density(rho)
+        f = grid.gravity_load(gz, f_ext)
+        u = torch.empty_like(f)
+        code, info = grid.solve(f, u, rtol=rtol, maxit=maxit)
+        c = grid.compliance_sensitivity(f, u)
+        ctx.grid, ctx.version, ctx.gz = grid, grid.density_version, gz
+        ctx.save_for_backward(rho, f, u)
+        grid.last_info = info
+        return torch.as_tensor(c[0], dtype=torch.float64, device=rho.device)
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        rho, f, u = ctx.saved_tensors
+        grid = ctx.grid
+        if grid.density_version != ctx.version:
+            grid.set_density(rho)
+        w = float(grad_c.detach().double().cpu())
+        dc = torch.empty_like(rho)
+        grid.compliance_sensitivity(f, u, dc=dc, weights=np.array([w]))
+        grid.gravity_sensitivity(u, ctx.gz, dc, weight=w)
+        return dc, None, None, None, None, None

@@ -1049,6 +1049,32 @@ int hexmg_sensitivity_filter(int nx, int ny, int nz, double rmin, double gamma, 
   return 0;
 }
 
+int hexmg_gravity_load(hexmg_grid_t g, double gz, const double* f_ext, double* f, void* stream) {
+  if (!g || !f) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (f == f_ext) return fail(HEXMG_ERR_INVALID, "f must not overlap f_ext");
+  if (!std::isfinite(gz)) return fail(HEXMG_ERR_INVALID, "g must be finite");
+  if (!g->density_set) return fail(HEXMG_ERR_INVALID, "hexmg_set_density has not succeeded");
+  launch_gravity_load(g->lv[0], g->rho[0], gz, f_ext, f, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_gravity_sensitivity(hexmg_grid_t g, const double* u, double gz, double weight, double* dc, void* stream) {
+  if (!g || !u || !dc) return fail(HEXMG_ERR_INVALID, "null argument");
+  if (!std::isfinite(gz) || !std::isfinite(weight)) return fail(HEXMG_ERR_INVALID, "g and weight must be finite");
+  launch_gravity_sensitivity(g->lv[0], u, 2.0 * weight * (-gz / 8.0), dc, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int hexmg_apply_passive(long long n, const uint8_t* passive, double* x, void* stream) {
+  if (n < 0 || (n > 0 && (!passive || !x))) return fail(HEXMG_ERR_INVALID, "null argument or negative size");
+  if (n == 0) return 0;
+  launch_apply_passive(n, passive, x, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int hexmg_oc_update(hexmg_grid_t g, const double* x, const double* dc, const double* dv, double volfrac,
                     double move, double eta, double* x_new, double* lambda_host, void* stream) {
   if (!g || !x || !dc || !dv || !x_new) return fail(HEXMG_ERR_INVALID, "null argument");

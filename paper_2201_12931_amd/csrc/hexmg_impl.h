@@ -148,6 +148,10 @@ void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const doubl
                    hipStream_t s);
 void launch_sens_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,
                         double* out, hipStream_t s);
+void launch_gravity_load(const Level& L, const double* rho, double g, const double* f_ext, double* f,
+                         hipStream_t s);
+void launch_gravity_sensitivity(const Level& L, const double* u, double coef, double* dc, hipStream_t s);
+void launch_apply_passive(long long n, const uint8_t* passive, double* x, hipStream_t s);
 struct OcProbes {
   double v[kOcProbes];  // lambda_p^(-eta)
 };

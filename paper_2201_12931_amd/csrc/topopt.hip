@@ -86,6 +86,47 @@ __global__ void k_sens_filter(int nx, int ny, int nz, double rmin, int R, double
   out[me] = s / (fmax(gamma, x[me]) * ws);
 }
 
+// Self-weight: f = f_ext - (g / 8) sum_{e adjacent} rho_e along z (each of an
+// element's eight nodes takes an eighth of its weight).  f_ext may be null.
+__global__ void k_gravity_load(Level L, const double* __restrict__ rho, double g, const double* __restrict__ f_ext,
+                               double* __restrict__ f) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= L.nn) return;
+  const int i = n % L.nxn, t = n / L.nxn, j = t % L.nyn, k = t / L.nyn;
+  double s = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int ei = i - (a & 1), ej = j - ((a >> 1) & 1), ek = k - (a >> 2);
+    if (ei < 0 || ei >= L.nx || ej < 0 || ej >= L.ny || ek < 0 || ek >= L.nz) continue;
+    s += rho[ei + L.nx * (ej + L.ny * ek)];
+  }
+  const long long b = 3ll * n;
+  f[b] = f_ext ? f_ext[b] : 0.0;
+  f[b + 1] = f_ext ? f_ext[b + 1] : 0.0;
+  f[b + 2] = (f_ext ? f_ext[b + 2] : 0.0) - 0.125 * g * s;
+}
+
+// dc_e += coef * sum of u_z over the element's nodes (coef = 2 w (-g / 8))
+__global__ void k_gravity_sensitivity(Level L, const double* __restrict__ u, double coef, double* __restrict__ dc) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= L.ne) return;
+  const int i = e % L.nx, t = e / L.nx, j = t % L.ny, k = t / L.ny;
+  double s = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int m = (i + (a & 1)) + L.nxn * ((j + ((a >> 1) & 1)) + L.nyn * (k + (a >> 2)));
+    s += u[3ll * m + 2];
+  }
+  dc[e] += coef * s;
+}
+
+// passive elements: 1 = solid (x = 1), 2 = void (x = 0); others unchanged
+__global__ void k_apply_passive(long long n, const uint8_t* __restrict__ passive, double* __restrict__ x) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const int p = passive[e];
+  if (p == 1) x[e] = 1.0;
+  else if (p == 2) x[e] = 0.0;
+}
+
 // Volume at kOcProbes multipliers: partial[block][p] = sum_e dv_e x_new_e(lambda_p)
 __global__ __launch_bounds__(kBlock) void k_oc_probe(long long n, const double* __restrict__ x,
                                                      const double* __restrict__ dc, const double* __restrict__ dv,
@@ -97,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_oc_probe(long long n, const double* 
   for (int p = 0; p < kOcProbes; ++p) acc[p] = 0.0;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
     const double xe = x[e], ve = dv[e];
+    if (ve == 0.0) continue;  // outside the volume constraint (passive)
     const double B = -dc[e] / ve;
     const double se = xe * pow(B > 0.0 ? B : 0.0, eta);
     const double lo = fmax(0.0, xe - move), hi = fmin(1.0, xe + move);
@@ -133,6 +175,10 @@ __global__ void k_oc_apply(long long n, const double* __restrict__ x, const doub
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n) return;
   const double xe = x[e];
+  if (dv[e] == 0.0) {  // outside the volume constraint: left to the caller (passive)
+    xn[e] = xe;
+    return;
+  }
   const double B = -dc[e] / dv[e];
   const double se = xe * pow(B > 0.0 ? B : 0.0, eta);
   xn[e] = fmin(fmin(1.0, xe + move), fmax(fmax(0.0, xe - move), se * lam_pow));
@@ -158,6 +204,19 @@ void launch_sens_filter(int nx, int ny, int nz, double rmin, double gamma, const
   const int R = (int)std::ceil(rmin) - 1;
   const int bx = 64;
   k_sens_filter<<<dim3((nx + bx - 1) / bx, ny, nz), bx, 0, s>>>(nx, ny, nz, rmin, R, gamma, x, dc, out);
+}
+
+void launch_gravity_load(const Level& L, const double* rho, double g, const double* f_ext, double* f,
+                         hipStream_t s) {
+  k_gravity_load<<<(L.nn + kBlock - 1) / kBlock, kBlock, 0, s>>>(L, rho, g, f_ext, f);
+}
+
+void launch_gravity_sensitivity(const Level& L, const double* u, double coef, double* dc, hipStream_t s) {
+  k_gravity_sensitivity<<<(L.ne + kBlock - 1) / kBlock, kBlock, 0, s>>>(L, u, coef, dc);
+}
+
+void launch_apply_passive(long long n, const uint8_t* passive, double* x, hipStream_t s) {
+  k_apply_passive<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, passive, x);
 }
 
 void launch_oc_probe(long long n, const double* x, const double* dc, const double* dv, double eta, double move,

@@ -81,6 +81,9 @@ def lib() -> ctypes.CDLL:
             "hexmg_element_matrix": (i, [d, vp]),
             "hexmg_filter": (i, [i, i, i, d, i, vp, vp, vp, vp]),
             "hexmg_sensitivity_filter": (i, [i, i, i, d, d, vp, vp, vp, vp]),
+            "hexmg_gravity_load": (i, [vp, d, vp, vp, vp]),
+            "hexmg_gravity_sensitivity": (i, [vp, vp, d, d, vp, vp]),
+            "hexmg_apply_passive": (i, [ctypes.c_longlong, vp, vp, vp]),
             "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), vp]),
             "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_set_kernel_choice": (i, [vp, i, i, i, i, i]),
@@ -187,6 +190,17 @@ def sensitivity_filter(nx, ny, nz, rmin, x, dc, out=None, gamma=1e-3, stream=Non
                                           _dev(dc, torch.float64, n, "dc"), _dev(out, torch.float64, n, "out"),
                                           _stream(stream)))
     return out
+
+
+def apply_passive(passive, x, stream=None):
+    """x_e = 1 where passive_e == 1 (solid), 0 where passive_e == 2 (void); in place."""
+    import torch
+
+    if passive.dtype != torch.uint8 or passive.numel() != x.numel() or not passive.is_contiguous():
+        raise ValueError("passive must be a contiguous uint8 tensor with one entry per element")
+    _check(lib().hexmg_apply_passive(x.numel(), ctypes.c_void_p(passive.data_ptr()),
+                                     _dev(x, torch.float64, name="x"), _stream(stream)))
+    return x
 
 
 def batch_solve(grids, fs, us, rtol=1e-6, maxit=500, stream=None, check=True):
@@ -321,6 +335,26 @@ class Grid:
 
     def set_kernel_choice(self, level, dtype, kernel, zchunk=4, shape=0):
         _check(lib().hexmg_set_kernel_choice(self.handle, level, dtype, kernel, zchunk, shape))
+
+    def gravity_load(self, gz, f_ext=None, f=None, stream=None):
+        """f = f_ext + self-weight of the last set density (-gz rho_e / 8 per node along z)."""
+        import torch
+
+        if f is None:
+            f = torch.empty(self.n_dof, dtype=torch.float64, device=self.workspace.device)
+        _check(lib().hexmg_gravity_load(self.handle, float(gz),
+                                        None if f_ext is None else _dev(f_ext, torch.float64, self.n_dof, "f_ext"),
+                                        _dev(f, torch.float64, self.n_dof, "f"), _stream(stream)))
+        return f
+
+    def gravity_sensitivity(self, u, gz, dc, weight=1.0, stream=None):
+        """dc += weight * 2 u^T df/drho (the load part of the compliance derivative)."""
+        import torch
+
+        _check(lib().hexmg_gravity_sensitivity(self.handle, _dev(u, torch.float64, self.n_dof, "u"), float(gz),
+                                               float(weight), _dev(dc, torch.float64, self.n_elem, "dc"),
+                                               _stream(stream)))
+        return dc
 
     def coarse_cycle_choice(self, dtype=F32):
         """(first level of the cooperative coarse-cycle launch or 0, workgroups)."""

@@ -8,7 +8,10 @@ hexmg C ABI, with either regularisation:
   (adjoint sensitivity, then the filter adjoint) -> OC update with the
   filtered volume.
 
-All arithmetic runs in the HIP library; autograd only chains the hand-written
+Passive regions (1 solid, 2 void per element; sensitivity filter) keep their
+value and stay out of the volume constraint; ``gravity`` adds the self-weight
+of the design to the single load case (its derivative included).  All
+arithmetic runs in the HIP library; autograd only chains the hand-written
 adjoints.  ``run(max_iters, tol)`` iterates until the largest design change
 drops below tol (Alg. 4 stops at 0.01).
 """
@@ -19,7 +22,7 @@ import dataclasses
 import torch
 
 from . import hexmg
-from .autograd import Compliance, DensityFilter
+from .autograd import Compliance, DensityFilter, SelfWeightCompliance
 
 
 @dataclasses.dataclass
@@ -36,9 +39,14 @@ class OCResult:
 class TopOpt:
     def __init__(self, nx, ny, nz, levels, f, volfrac, rmin=1.5, move=0.2, eta=0.5,
                  precision=hexmg.MIXED, rtol=1e-6, maxit=500, x0=None, device="cuda", filter="density",
-                 gamma=1e-3, **grid_kw):
+                 gamma=1e-3, passive=None, gravity=0.0, **grid_kw):
         if filter not in ("density", "sensitivity"):
             raise ValueError("filter must be 'density' or 'sensitivity'")
+        if passive is not None and filter != "sensitivity":
+            raise ValueError("passive regions are supported with the sensitivity filter")
+        if gravity and (f.dim() != 1):
+            raise ValueError("self-weight loading takes one load case")
+        self.passive, self.gravity = passive, float(gravity)
         self.shape = (nx, ny, nz)
         self.n = nx * ny * nz
         self.volfrac, self.rmin, self.move, self.eta = volfrac, rmin, move, eta
@@ -51,15 +59,23 @@ class TopOpt:
         if filter == "density":
             # dV/dx of V = mean(rho~): the filter adjoint of 1/Ne
             self.dv = hexmg.density_filter(nx, ny, nz, rmin, torch.full_like(self.x, 1.0 / self.n), adjoint=True)
-        else:
+        elif passive is None:
             self.dv = torch.full_like(self.x, 1.0 / self.n)
+        else:
+            # V = mean of x over the design (non-passive) elements; passive ones keep their value
+            active = (passive == 0).to(torch.float64)
+            self.dv = active / active.sum()
+            hexmg.apply_passive(passive, self.x)
         self.it = 0
 
     def objective(self, x):
         """c(x) through the density filter (if any) and the state solve; returns
         (c_total, physical densities)."""
         rho = DensityFilter.apply(x, self.shape, self.rmin) if self.filter == "density" else x
-        c = Compliance.apply(rho, self.grid, self.f, self.rtol, self.maxit)
+        if self.gravity:
+            c = SelfWeightCompliance.apply(rho, self.grid, self.f, self.gravity, self.rtol, self.maxit)
+        else:
+            c = Compliance.apply(rho, self.grid, self.f, self.rtol, self.maxit)
         return c.sum(), rho
 
     def gradient(self, x):
@@ -76,11 +92,14 @@ class TopOpt:
     def step(self) -> OCResult:
         c, dc, rho = self.gradient(self.x)
         x_new, lam = self.grid.oc_update(self.x, dc, self.dv, self.volfrac, self.move, self.eta)
+        if self.passive is not None:
+            hexmg.apply_passive(self.passive, x_new)
         change = float((x_new - self.x).abs().max())
         self.x = x_new
         self.it += 1
         info = self.grid.last_info[0]
-        return OCResult(self.it, float(c), float(rho.mean()), change, lam, info["iterations"], info["rel_res_true"])
+        vol = float(rho.mean()) if self.filter == "density" else float((self.dv * rho).sum())
+        return OCResult(self.it, float(c), vol, change, lam, info["iterations"], info["rel_res_true"])
 
     def run(self, max_iters, tol=0.01, callback=None):
         """OC iterations until max |x_new - x| < tol or max_iters; returns the

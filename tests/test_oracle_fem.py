@@ -169,3 +169,52 @@ def test_line_load_total():
     f = W.cantilever_line_load(g)
     assert f.sum() == pytest.approx(-1.0, rel=1e-15)
     assert np.count_nonzero(f) == 17
+
+
+def test_gravity_consistent_load_is_an_eighth_per_node():
+    """The consistent nodal load of a constant body force on the trilinear
+    element is the integral of each shape function: 2x2x2 Gauss quadrature of
+    N_a = prod(1 - t or t) over the unit cube gives 1/8 for every corner."""
+    gp = [0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)]
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+        s = 0.0
+        for x in gp:
+            for y in gp:
+                for z in gp:
+                    s += 0.125 * (x if ax else 1 - x) * (y if ay else 1 - y) * (z if az else 1 - z)
+        assert s == pytest.approx(0.125, rel=1e-14)
+    g = W.Grid(5, 3, 4)
+    rho = W.iid_uniform_density(g, seed=2, lo=0.0)
+    f = fem.gravity_load(5, 3, 4, rho, g=9.81)
+    assert f[2::3].sum() == pytest.approx(-9.81 * rho.sum(), rel=1e-13)
+    assert np.all(f[0::3] == 0) and np.all(f[1::3] == 0)
+    fu = fem.gravity_load(5, 3, 4, np.full(g.n_elem, 0.5), g=2.0)
+    interior = 2 + 6 * (1 + 4 * 2)  # node (2, 1, 2): eight adjacent elements
+    assert fu[3 * interior + 2] == pytest.approx(-2.0 * 0.5, rel=1e-15)
+
+
+def test_self_weight_compliance_gradient_finite_differences():
+    """c(rho) = f(rho)^T u(rho) with a design-dependent load: the adjoint
+    derivative (stiffness part + 2 u^T df/drho) against central differences of
+    direct solves."""
+    nx, ny, nz = 4, 2, 2
+    g = W.Grid(nx, ny, nz)
+    rho = W.iid_uniform_density(g, seed=3, lo=0.3)
+    free = fem.free_dof_mask(W.fixed_mask_face_x0(g))
+    f_ext = W.cantilever_line_load(g)
+
+    def comp(r):
+        f = f_ext + fem.gravity_load(nx, ny, nz, r, g=0.7)
+        u = fem.solve_direct(fem.assemble_stiffness(nx, ny, nz, fem.simp_modulus(r)), f, free)
+        return fem.compliance(f * free, u), u
+
+    c0, u = comp(rho)
+    dc = fem.sensitivity(nx, ny, nz, rho, u) + fem.gravity_sensitivity(nx, ny, nz, u, g=0.7)
+    h = 1e-6
+    for e in range(g.n_elem):
+        rp, rm = rho.copy(), rho.copy()
+        rp[e] += h
+        rm[e] -= h
+        fd = (comp(rp)[0] - comp(rm)[0]) / (2 * h)
+        assert fd == pytest.approx(dc[e], rel=1e-6, abs=1e-9 * abs(dc).max()), e
