@@ -355,6 +355,15 @@ CoarseCycle<T> make_cycle(hexmg_grid* g) {
   return a;
 }
 
+// Orders stream s after the coarsest inverse of the last hexmg_set_density
+// (formed on the auxiliary stream); a no-op once s has waited.
+void wait_coarse(hexmg_grid* g, hipStream_t s) {
+  if (!g->coarse_pending || (g->coarse_waited_valid && g->coarse_waited == s)) return;
+  (void)hipStreamWaitEvent(s, g->ev_coarse, 0);
+  g->coarse_waited = s;
+  g->coarse_waited_valid = true;
+}
+
 // out = V_l(f) from a zero initial guess.  The first sweep writes the level's
 // scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
 // in `out` without a copy.  f and out must not overlap.  With first_done the
@@ -365,6 +374,7 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
                   bool first_done = false) {
   const Level& L = g->lv[l];
   if (l == g->L - 1) {
+    wait_coarse(g, s);
     launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, nrhs, act, s);
     return;
   }
@@ -386,6 +396,7 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   const int blocks = sizeof(T) == 4 ? g->tail_blocks32 : g->tail_blocks64;
   bool done = false;
   if (fuse && tail == l + 1) {  // the rest of the cycle as one cooperative launch
+    wait_coarse(g, s);
     done = launch_coarse_cycle<T>(make_cycle<T>(g), l + 1, nrhs, act, blocks, s) == hipSuccess;
     if (!done) {
       (void)hipGetLastError();
@@ -447,6 +458,7 @@ int tune_tail(hexmg_grid* g, hipStream_t s) {
       prev = b;
       bool ok = true;
       float ms = 0.f;
+      wait_coarse(g, s);
       if (int e = time3([&] { ok = ok && launch_coarse_cycle<T>(cyc, ls, 1, nullptr, b, s) == hipSuccess; }, &ms))
         return e;
       if (!ok) {
@@ -623,6 +635,9 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
 int hexmg_grid_destroy(hexmg_grid_t g) {
   if (!g) return 0;
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
+  if (g->aux_stream) (void)hipStreamDestroy(g->aux_stream);
+  for (hipEvent_t e : {g->ev_fork, g->ev_coarse, g->ev_flag})
+    if (e) (void)hipEventDestroy(e);
   for (auto& r : g->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -638,8 +653,19 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   g->last_stream = s;
   const hexmg_grid_desc& d = g->desc;
+  if (!g->aux_stream) {
+    if (hipStreamCreateWithFlags(&g->aux_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_coarse, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_flag, hipEventDisableTiming) != hipSuccess)
+      return fail(HEXMG_ERR_DEVICE, "stream or event creation failed");
+  }
+  // the previous coarsest inverse may still be in flight on the auxiliary stream
+  if (g->coarse_pending) HIP_TRY(hipStreamWaitEvent(s, g->ev_coarse, 0));
   launch_simp(g->lv[0].ne, rho, d.E0, d.Emin, d.penal, 1.0, g->E64[0], g->E32[0], g->rho[0], g->flags, s);
   launch_or_flags(kReduceBlocks, g->flags, g->flags + kReduceBlocks, s);
+  HIP_TRY(hipMemcpyAsync(g->host_scalars, g->flags + kReduceBlocks, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(g->ev_flag, s));
   for (int l = 1; l < g->L; ++l) {
     launch_homogenize(g->lv[l - 1], g->lv[l], g->rho[l - 1], g->rho[l], s);
     if (d.coarse_avg == HEXMG_AVG_DENSITY)
@@ -653,23 +679,34 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     launch_galerkin_first(g->lv[0], g->lv[1], g->E64[0], g->Gc, g->Ke64, g->S64[1], g->S32[1], s);
     for (int l = 1; l + 1 < g->L; ++l)
       launch_galerkin_coarsen(g->lv[l], g->lv[l + 1], g->S64[l], g->S64[l + 1], g->S32[l + 1], s);
+  }
+  // Coarsest level on the auxiliary stream: assemble (or take the stencil),
+  // invert by Gauss-Jordan, symmetrize.  Everything it reads is final here.
+  HIP_TRY(hipEventRecord(g->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(g->aux_stream, g->ev_fork, 0));
+  hipStream_t a = g->aux_stream;
+  if (g->galerkin)
+    launch_dense_from_stencil(g->lv[g->L - 1], g->S64[g->L - 1], g->Abuf[0], a);
+  else
+    launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], a);
+  double* inv = nullptr;
+  launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, g->gjX, &inv, a);
+  double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
+  launch_symmetrize(nc, inv, other, a);
+  HIP_TRY(hipEventRecord(g->ev_coarse, a));
+  g->Ainv = other;
+  g->coarse_pending = true;
+  g->coarse_waited_valid = false;
+  if (g->galerkin) {
     launch_diag(g->lv[0], g->Ke64, g->E64[0], d.omega, g->wd64[0], g->wd32[0], s);
     for (int l = 1; l < g->L; ++l) launch_stencil_diag(g->lv[l], g->S64[l], d.omega, g->wd64[l], g->wd32[l], s);
-    launch_dense_from_stencil(g->lv[g->L - 1], g->S64[g->L - 1], g->Abuf[0], s);
   } else {
     for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], d.omega, g->wd64[l], g->wd32[l], s);
-    // Coarsest level: assemble, invert by Gauss-Jordan, symmetrize.
-    launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], s);
   }
-  double* inv = nullptr;
-  launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, g->gjX, &inv, s);
-  double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
-  launch_symmetrize(nc, inv, other, s);
-  g->Ainv = other;
   HIP_TRY(hipGetLastError());
+  // validity of rho: wait only for the flag, not for the set-up queued behind it
   int bad = 0;
-  HIP_TRY(hipMemcpyAsync(g->host_scalars, g->flags + kReduceBlocks, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipEventSynchronize(g->ev_flag));
   std::memcpy(&bad, g->host_scalars, sizeof(int));
   if (bad) {
     g->density_set = false;

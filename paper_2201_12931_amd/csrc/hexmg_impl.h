@@ -274,6 +274,14 @@ struct hexmg_grid {
   bool density_set;
   hipStream_t last_stream;
   hipStream_t own_stream = nullptr;  // created on first use by a batched solve
+  // The coarsest inverse is formed on aux_stream, concurrently with the rest of
+  // hexmg_set_density and the first steps of the next solve; the first use of
+  // it on a stream waits for ev_coarse (coarse_waited: the stream that has).
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_coarse = nullptr, ev_flag = nullptr;
+  hipStream_t coarse_waited = nullptr;
+  bool coarse_waited_valid = false;  // coarse_waited names a stream (the null stream is one)
+  bool coarse_pending = false;
   // profiling
   bool profile;
   // tag: the CG iteration a launch belongs to (0: not part of one); launches of
