@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--ku-reps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run 3 device copies of this many MiB (calibration for HBM byte counters)")
+    ap.add_argument("--coarse-cycle", default="", metavar="LEVEL:BLOCKS",
+                    help="pin the cooperative coarse-cycle launch (0:0 = off) instead of the timed choice")
     ap.add_argument("--l0-choice", default="", metavar="KIND:ZCHUNK:SHAPE",
                     help="pin the level-0 binary32 kernel (KIND stream|gather) instead of the timed choice, "
                          "e.g. for counter runs whose timings are perturbed by the profiler")
@@ -146,6 +148,10 @@ def main():
         return code, info[0], c[0]
 
     mixed.set_density(rho_d)  # first success times the kernel variants
+    if args.coarse_cycle:
+        lv, nb = (int(v) for v in args.coarse_cycle.split(":"))
+        for dt in (hexmg.F32, hexmg.F64):
+            mixed.set_coarse_cycle(dt, lv, nb)
     if args.l0_choice:
         kind, zc, shape = args.l0_choice.split(":")
         mixed.set_kernel_choice(0, hexmg.F32, hexmg.KERNEL_STREAM if kind == "stream" else hexmg.KERNEL_GATHER,
