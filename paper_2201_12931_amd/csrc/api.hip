@@ -129,7 +129,6 @@ size_t carve(hexmg_grid* g, char* base) {
   g->Abuf[0] = c.take<double>(nc * nc);
   g->Abuf[1] = c.take<double>(nc * nc);
   g->gjD = c.take<double>(kGJBlock * kGJBlock);
-  g->gjX = c.take<double>(kGJBlock * nc);
   g->Ke64 = c.take<double>(576);
   g->Ke32 = c.take<float>(576);
   const size_t N0 = 3ull * g->lv[0].nn;
@@ -690,7 +689,7 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
   else
     launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], a);
   double* inv = nullptr;
-  launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, g->gjX, &inv, a);
+  launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, &inv, a);
   double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
   launch_symmetrize(nc, inv, other, a);
   HIP_TRY(hipEventRecord(g->ev_coarse, a));

@@ -141,7 +141,7 @@ void launch_symmetrize(int n, const double* A, double* B, hipStream_t s);
 // In-place-style blocked Gauss-Jordan inverse of the n x n SPD matrix in A
 // (B is the ping-pong buffer, D kGJBlock^2 and X kGJBlock*n scratch); *result
 // receives the buffer holding the inverse.
-void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double** result, hipStream_t s);
+void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, hipStream_t s);
 
 // Density filter and optimality criteria (topopt.hip)
 void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out, double* tmp,
@@ -238,7 +238,6 @@ struct hexmg_grid {
   std::vector<float*> vf32, vu32, vt32, vr32;
   double* Abuf[2];  // coarsest operator / Gauss-Jordan ping-pong
   double* gjD;      // kGJBlock^2
-  double* gjX;      // kGJBlock * n_c
   double* Ainv;     // points at the buffer holding the symmetrized inverse
   int nc;         // coarsest DOFs
   double* Ke64;   // 576

@@ -305,65 +305,56 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
   }
 }
 
-// grid ceil(n / 64): X[r][j] = sum_q D[r][q] A[k0+q][j] for the block's 64
-// columns (X[r][k0+c] = D[r][c] inside the pivot block).  Lane = column, wave w
-// rows 16w .. 16w+15; the column of A_K* is held in registers, D in LDS.
-__global__ __launch_bounds__(kBlock) void k_gj_row_panel(int n, int k0, int nb, const double* __restrict__ A,
-                                                         const double* __restrict__ D, double* __restrict__ X) {
-  __shared__ double sD[kGJBlock][kGJBlock];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + lane;
-  for (int t = threadIdx.x; t < kGJBlock * kGJBlock; t += kBlock) {
-    const int r = t >> 6, q = t & 63;
-    sD[r][q] = (r < nb && q < nb) ? D[r * nb + q] : 0.0;
-  }
-  double a[kGJBlock];
-#pragma unroll
-  for (int q = 0; q < kGJBlock; ++q) a[q] = (q < nb && j < n) ? A[(long long)(k0 + q) * n + j] : 0.0;
-  __syncthreads();
-  const bool inK = j >= k0 && j < k0 + nb;
-#pragma unroll 4
-  for (int rr = 0; rr < 16; ++rr) {
-    const int r = 16 * w + rr;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < kGJBlock; ++q) s += sD[r][q] * a[q];
-    if (r < nb && j < n) X[(long long)r * n + j] = inK ? sD[r][j - k0] : s;
-  }
-}
-
-// grid (ceil(n / 64), ceil(n / 64)): 64x64 tile of
-//   B_ij = X[i-k0][j]                                   (i in K)
-//   B_ij = (j in K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]  (otherwise)
-// Lane = column j (X column in registers), wave w rows 16w .. 16w+15 of the
-// tile (A_IK rows from LDS).
-__global__ __launch_bounds__(kBlock) void k_gj_update(int n, int k0, int nb, const double* __restrict__ A,
-                                                      const double* __restrict__ X, double* __restrict__ B) {
-  __shared__ double sA[kGJBlock][kGJBlock];
+// Row panel and update in one launch, grid (ceil(n / 64), ceil(n / 64)): the
+// block of tile (I, J) first forms its own 64 columns of the row panel,
+// X_J = D A_KJ (X_K = D), in LDS -- the ceil(n/64)-fold recomputation costs
+// 64^3 multiply-adds per tile, far less than a launch -- then
+//   B_ij = X[i-k0][j]                                      (i in K)
+//   B_ij = (j in K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]    (otherwise).
+// Lane = column j, wave w rows 16w .. 16w+15 of the tile.
+__global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int k0, int nb, const double* __restrict__ A,
+                                                            const double* __restrict__ D,
+                                                            double* __restrict__ B) {
+  __shared__ double sD[kGJBlock][kGJBlock];   // D (zero-padded)
+  __shared__ double sX[kGJBlock][kGJBlock];   // A_KJ, then X_J
+  __shared__ double sA[kGJBlock][kGJBlock];   // A_IK
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane, i0 = blockIdx.y * 64;
   for (int t = threadIdx.x; t < kGJBlock * kGJBlock; t += kBlock) {
     const int r = t >> 6, q = t & 63;
+    const int jj = blockIdx.x * 64 + q;
+    sD[r][q] = (r < nb && q < nb) ? D[r * nb + q] : 0.0;
+    sX[r][q] = (r < nb && jj < n) ? A[(long long)(k0 + r) * n + jj] : 0.0;
     sA[r][q] = (i0 + r < n && q < nb) ? A[(long long)(i0 + r) * n + k0 + q] : 0.0;
   }
-  double x[kGJBlock];
+  __syncthreads();
+  const bool jK = j >= k0 && j < k0 + nb;
+  double x[16];
 #pragma unroll
-  for (int q = 0; q < kGJBlock; ++q) x[q] = (q < nb && j < n) ? X[(long long)q * n + j] : 0.0;
+  for (int rr = 0; rr < 16; ++rr) {
+    const int r = 16 * w + rr;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGJBlock; ++q) acc += sD[r][q] * sX[q][lane];
+    x[rr] = jK ? sD[r][j - k0] : acc;
+  }
+  __syncthreads();  // every thread is done reading A_KJ
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) sX[16 * w + rr][lane] = x[rr];
   __syncthreads();
   if (j >= n) return;
-  const bool jK = j >= k0 && j < k0 + nb;
 #pragma unroll 4
   for (int rr = 0; rr < 16; ++rr) {
     const int r = 16 * w + rr, i = i0 + r;
     if (i >= n) break;
     double v;
     if (i >= k0 && i < k0 + nb) {
-      v = X[(long long)(i - k0) * n + j];
+      v = sX[i - k0][lane];
     } else {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kGJBlock; ++q) s += sA[r][q] * x[q];
-      v = (jK ? 0.0 : A[(long long)i * n + j]) - s;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < kGJBlock; ++q) acc += sA[r][q] * sX[q][lane];
+      v = (jK ? 0.0 : A[(long long)i * n + j]) - acc;
     }
     B[(long long)i * n + j] = v;
   }
@@ -676,15 +667,14 @@ void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, d
   const int N = 3 * C.nn;
   k_coarse_assemble<<<dim3(blocks_for(N), N), kBlock, 0, s>>>(C, Ke, E, A);
 }
-void launch_gj_blocked(int n, double* A, double* B, double* D, double* X, double** result, hipStream_t s) {
+void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, hipStream_t s) {
   double* buf[2] = {A, B};
   int cur = 0;
   for (int k0 = 0; k0 < n; k0 += kGJBlock) {
     const int nb = (n - k0) < kGJBlock ? (n - k0) : kGJBlock;
     const int t = (n + 63) / 64;
     k_gj_block_inv<<<1, kBlock, 0, s>>>(n, k0, nb, buf[cur], D);
-    k_gj_row_panel<<<t, kBlock, 0, s>>>(n, k0, nb, buf[cur], D, X);
-    k_gj_update<<<dim3(t, t), kBlock, 0, s>>>(n, k0, nb, buf[cur], X, buf[1 - cur]);
+    k_gj_panel_update<<<dim3(t, t), kBlock, 0, s>>>(n, k0, nb, buf[cur], D, buf[1 - cur]);
     cur = 1 - cur;
   }
   *result = buf[cur];
