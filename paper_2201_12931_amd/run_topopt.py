@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--coarse-avg", choices=["density", "modulus"], default="density")
     ap.add_argument("--filter", choices=["density", "sensitivity"], default="density")
     ap.add_argument("--coarse-op", choices=["rediscretize", "galerkin"], default="rediscretize")
+    ap.add_argument("--omega", type=float, default=0.6, help="Jacobi damping of the V-cycle smoother")
     ap.add_argument("--until", type=float, default=0.0,
                     help="stop once the largest design change is below this (Alg. 4 uses 0.01); 0 = run --iters")
     args = ap.parse_args()
@@ -108,11 +109,13 @@ def main():
                  precision=hexmg.FP64 if args.fp64 else hexmg.MIXED,
                  coarse_avg=hexmg.AVG_DENSITY if args.coarse_avg == "density" else hexmg.AVG_MODULUS,
                  filter=args.filter,
-                 coarse_op=hexmg.COARSE_GALERKIN if args.coarse_op == "galerkin" else hexmg.COARSE_REDISCRETIZE)
+                 coarse_op=hexmg.COARSE_GALERKIN if args.coarse_op == "galerkin" else hexmg.COARSE_REDISCRETIZE,
+                 omega=args.omega)
     summary = {"grid": [args.nx, args.ny, args.nz], "elements": g.n_elem, "dofs": g.n_dof,
                "levels": args.levels, "volfrac": args.volfrac, "rmin": args.rmin, "rtol": args.rtol,
                "coarse_avg": args.coarse_avg, "precision": "fp64" if args.fp64 else "mixed",
-               "filter": args.filter, "until": args.until, "coarse_op": args.coarse_op}
+               "filter": args.filter, "until": args.until, "coarse_op": args.coarse_op,
+               "omega": args.omega}
     rng = np.random.Generator(np.random.PCG64(args.fd_seed))
 
     def fd_elements():
