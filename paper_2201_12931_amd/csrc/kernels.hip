@@ -307,26 +307,28 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
 
 // Row panel and update in one launch, grid (ceil(n / 64), ceil(n / 64)): the
 // block of tile (I, J) first forms its own 64 columns of the row panel,
-// X_J = D A_KJ (X_K = D), in LDS -- the ceil(n/64)-fold recomputation costs
-// 64^3 multiply-adds per tile, far less than a launch -- then
+// X_J = D A_KJ (X_K = D) -- the ceil(n/64)-fold recomputation costs 64^3
+// multiply-adds per tile, far less than a launch -- then
 //   B_ij = X[i-k0][j]                                      (i in K)
 //   B_ij = (j in K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]    (otherwise).
-// Lane = column j, wave w rows 16w .. 16w+15 of the tile.
+// Lane = column j, wave w rows 16w .. 16w+15 of the tile; the column operand
+// of each product is held in registers and the row operand is read from LDS
+// as a broadcast.
 __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int k0, int nb, const double* __restrict__ A,
                                                             const double* __restrict__ D,
                                                             double* __restrict__ B) {
-  __shared__ double sD[kGJBlock][kGJBlock];   // D (zero-padded)
-  __shared__ double sX[kGJBlock][kGJBlock];   // A_KJ, then X_J
-  __shared__ double sA[kGJBlock][kGJBlock];   // A_IK
+  __shared__ double sD[kGJBlock][kGJBlock];  // D (zero-padded), then X_J
+  __shared__ double sA[kGJBlock][kGJBlock];  // A_IK
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane, i0 = blockIdx.y * 64;
   for (int t = threadIdx.x; t < kGJBlock * kGJBlock; t += kBlock) {
     const int r = t >> 6, q = t & 63;
-    const int jj = blockIdx.x * 64 + q;
     sD[r][q] = (r < nb && q < nb) ? D[r * nb + q] : 0.0;
-    sX[r][q] = (r < nb && jj < n) ? A[(long long)(k0 + r) * n + jj] : 0.0;
     sA[r][q] = (i0 + r < n && q < nb) ? A[(long long)(i0 + r) * n + k0 + q] : 0.0;
   }
+  double col[kGJBlock];  // column j of A_KJ, then of X_J
+#pragma unroll
+  for (int q = 0; q < kGJBlock; ++q) col[q] = (q < nb && j < n) ? A[(long long)(k0 + q) * n + j] : 0.0;
   __syncthreads();
   const bool jK = j >= k0 && j < k0 + nb;
   double x[16];
@@ -334,26 +336,28 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int k0, int n
   for (int rr = 0; rr < 16; ++rr) {
     const int r = 16 * w + rr;
     double acc = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < kGJBlock; ++q) acc += sD[r][q] * sX[q][lane];
+#pragma unroll
+    for (int q = 0; q < kGJBlock; ++q) acc += sD[r][q] * col[q];
     x[rr] = jK ? sD[r][j - k0] : acc;
   }
-  __syncthreads();  // every thread is done reading A_KJ
+  __syncthreads();  // D no longer needed: its buffer takes X_J
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) sX[16 * w + rr][lane] = x[rr];
+  for (int rr = 0; rr < 16; ++rr) sD[16 * w + rr][lane] = x[rr];
   __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kGJBlock; ++q) col[q] = sD[q][lane];
   if (j >= n) return;
-#pragma unroll 4
+#pragma unroll 2
   for (int rr = 0; rr < 16; ++rr) {
     const int r = 16 * w + rr, i = i0 + r;
     if (i >= n) break;
     double v;
     if (i >= k0 && i < k0 + nb) {
-      v = sX[i - k0][lane];
+      v = sD[i - k0][lane];
     } else {
       double acc = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < kGJBlock; ++q) acc += sA[r][q] * sX[q][lane];
+#pragma unroll
+      for (int q = 0; q < kGJBlock; ++q) acc += sA[r][q] * col[q];
       v = (jK ? 0.0 : A[(long long)i * n + j]) - acc;
     }
     B[(long long)i * n + j] = v;
