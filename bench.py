@@ -38,6 +38,8 @@ def smooth_bytes_per_launch(g) -> float:
 # device copy of known size), keyed by workload, kernel choice and a digest of
 # the kernel source they were taken on: any change to the kernel voids them.
 TRAFFIC = {
+    # profiles/stream_smooth_f32_L0_cantilever_128x64x64_rf_traffic.md
+    ("cantilever_128x64x64_rf", "stream", 4, 1, "439f5b43171d28ca"): 46209135.0,
 }
 
 
