@@ -233,16 +233,18 @@ int hexmg_oc_update(hexmg_grid_t grid, const double *x, const double *dc, const 
  * for Poisson ratio nu, written to Ke_host.  Host only; needs no GPU. */
 int hexmg_element_matrix(double nu, double *Ke_host);
 
-/* The element-product kernel used on `level` for dtype (HEXMG_F64/F32):
- * *kernel = HEXMG_KERNEL_STREAM or HEXMG_KERNEL_GATHER and, for the streaming
- * kernel, the planes per z-chunk and the tile shape index (rows per thread /
- * waves per workgroup; any output pointer may be NULL).  With
- * HEXMG_KERNEL_AUTO the choice is made by timing the candidates (node-gather;
- * every streaming shape with 2..64 planes per chunk) on the grid's stream
- * during the first successful hexmg_set_density. */
+/* The element-product kernel of the damped-Jacobi sweep on `level` for dtype
+ * (HEXMG_F64/F32): *kernel = HEXMG_KERNEL_STREAM or HEXMG_KERNEL_GATHER and,
+ * for the streaming kernel, the planes per z-chunk and the tile shape index
+ * (rows per thread / waves per workgroup; any output pointer may be NULL).
+ * With HEXMG_KERNEL_AUTO the choice is made by timing the candidates
+ * (node-gather; every streaming shape with 2..64 planes per chunk) on the
+ * grid's stream during the first successful hexmg_set_density, separately
+ * for K u, the sweep and the residual. */
 int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int *kernel, int *zchunk, int *shape);
 
-/* Overrides the element-product kernel of `level` for dtype: kernel
+/* Overrides the element-product kernel of `level` for dtype (all three
+ * modes): kernel
  * HEXMG_KERNEL_STREAM (zchunk >= 1 planes per chunk, shape 0 .. number of
  * shapes - 1) or HEXMG_KERNEL_GATHER.  Later automatic tuning does not undo it.
  * Returns -1 for an unknown kernel, shape or level. */

@@ -208,12 +208,13 @@ void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int le
   }
 }
 
-// Times the candidate kernels of one level in one precision (a damped-Jacobi
-// sweep on zero vectors, the level's own scratch buffers) and returns the
-// fastest.  The streaming kernel is kept unless the node-gather is more than
-// 5% faster.
+// Times the candidate kernels of one level in one precision in each of the
+// three modes (K u, damped-Jacobi sweep, residual; zero vectors, the level's
+// own scratch buffers) and keeps the fastest per mode.  The streaming kernel
+// is kept unless the node-gather is more than 5% faster.
 template <typename T>
-int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_grid::Choice* out, hipStream_t s) {
+int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::array<hexmg_grid::Choice, 3>* out,
+               hipStream_t s) {
   const Level& L = g->lv[level];
   const size_t bytes = 3ull * L.nn * sizeof(T);
   HIP_TRY(hipMemsetAsync(u, 0, bytes, s));
@@ -227,26 +228,28 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, hexmg_gr
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  float best_stream = 1e30f, best_gather = 1e30f;
-  hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4, 0};
-  for (const auto& c : cand) {
-    launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, 1, s);
-    HIP_TRY(hipEventRecord(e0, s));
-    for (int rep = 0; rep < 3; ++rep) launch_choice<T>(g, c, kSmooth, level, u, f, wd, y, 1, s);
-    HIP_TRY(hipEventRecord(e1, s));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (c.kernel == HEXMG_KERNEL_GATHER) {
-      best_gather = ms;
-    } else if (ms < best_stream) {
-      best_stream = ms;
-      bs = c;
+  for (int mode = 0; mode < 3; ++mode) {
+    float best_stream = 1e30f, best_gather = 1e30f;
+    hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4, 0};
+    for (const auto& c : cand) {
+      launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 3; ++rep) launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (c.kernel == HEXMG_KERNEL_GATHER) {
+        best_gather = ms;
+      } else if (ms < best_stream) {
+        best_stream = ms;
+        bs = c;
+      }
     }
+    (*out)[mode] = (best_gather < 0.95f * best_stream) ? hexmg_grid::Choice{HEXMG_KERNEL_GATHER, 0, 0} : bs;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  *out = (best_gather < 0.95f * best_stream) ? hexmg_grid::Choice{HEXMG_KERNEL_GATHER, 0, 0} : bs;
   return 0;
 }
 
@@ -271,7 +274,8 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
   }
   LaunchTimer t;
   if (a && b) t = LaunchTimer{a, b};
-  launch_choice<T>(g, f32 ? g->choice32[level] : g->choice64[level], mode, level, u, f, wd, y, nrhs, s, maskin, act,
+  launch_choice<T>(g, (f32 ? g->choice32[level] : g->choice64[level])[mode], mode, level, u, f, wd, y, nrhs, s, maskin,
+                   act,
                    t);
   if (a && b) g->recs.push_back({family_of(mode, f32), a, b, g->prof_tag});
 }
@@ -367,10 +371,12 @@ void wait_coarse(hexmg_grid* g, hipStream_t s) {
 // scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
 // in `out` without a copy.  f and out must not overlap.  With first_done the
 // caller has already written the first sweep (omega D^-1 f) into the scratch
-// vector.  act: per right-hand side skip flags (may be null).
+// vector.  act: per right-hand side skip flags (may be null).  maskin: f may be
+// non-zero at fixed DOFs, so this level's element products mask their input
+// (the deeper levels' right-hand sides come out of the masked restriction).
 template <typename T>
 void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrhs, const int* act, hipStream_t s,
-                  bool first_done = false) {
+                  bool first_done = false, bool maskin = false) {
   const Level& L = g->lv[l];
   if (l == g->L - 1) {
     wait_coarse(g, s);
@@ -383,10 +389,10 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   int cur = 0;
   if (!first_done) launch_jacobi_first<T>(N, v.wd[l], f, buf[0], nrhs, act, s);
   for (int it = 1; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, false, act);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act);
     cur = 1 - cur;
   }
-  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], nrhs, s, false, act);
+  gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], nrhs, s, maskin, act);
   // the next level's first sweep is formed inside the restriction (not on the coarsest level)
   const bool fuse = l + 1 < g->L - 1;
   launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], nrhs, act, s, fuse ? v.wd[l + 1] : nullptr,
@@ -405,7 +411,7 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   if (!done) vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, act, s, fuse);
   launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, act, s);
   for (int it = 0; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, false, act);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act);
     cur = 1 - cur;
   }
 }
@@ -566,15 +572,17 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   carve(g, static_cast<char*>(workspace));
   for (int l = 0; l < g->L; ++l) g->lv[l].mask = g->mask[l];
   g->tuned = d->kernel != HEXMG_KERNEL_AUTO;
-  g->choice64.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4, 1});
-  g->choice32.assign(g->L, hexmg_grid::Choice{HEXMG_KERNEL_STREAM, 4, 1});
+  g->choice64.assign(g->L, {});
+  g->choice32.assign(g->L, {});
   for (int l = 0; l < g->L; ++l) {
-    if (d->kernel == HEXMG_KERNEL_GATHER) {
-      g->choice64[l] = {HEXMG_KERNEL_GATHER, 0, 0};
-      g->choice32[l] = {HEXMG_KERNEL_GATHER, 0, 0};
-    } else {
-      g->choice64[l].zchunk = stream_zchunk(g->lv[l], false, 1);
-      g->choice32[l].zchunk = stream_zchunk(g->lv[l], true, 1);
+    for (int m = 0; m < 3; ++m) {
+      if (d->kernel == HEXMG_KERNEL_GATHER) {
+        g->choice64[l][m] = {HEXMG_KERNEL_GATHER, 0, 0};
+        g->choice32[l][m] = {HEXMG_KERNEL_GATHER, 0, 0};
+      } else {
+        g->choice64[l][m] = {HEXMG_KERNEL_STREAM, stream_zchunk(g->lv[l], false, 1), 1};
+        g->choice32[l][m] = {HEXMG_KERNEL_STREAM, stream_zchunk(g->lv[l], true, 1), 1};
+      }
     }
   }
   g->density_set = false;
@@ -754,10 +762,10 @@ int hexmg_vcycle(hexmg_grid_t g, int dtype, const void* r, void* z, int nrhs, vo
     const int nb = (nrhs - k) < g->desc.max_nrhs ? (nrhs - k) : g->desc.max_nrhs;
     if (dtype == HEXMG_F64) {
       VView<double> v = view64(g);
-      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, nb, nullptr, s);
+      vcycle_level<double>(g, v, 0, (const double*)r + k * N, (double*)z + k * N, nb, nullptr, s, false, true);
     } else {
       VView<float> v = view32(g);
-      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, nb, nullptr, s);
+      vcycle_level<float>(g, v, 0, (const float*)r + k * N, (float*)z + k * N, nb, nullptr, s, false, true);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -1167,7 +1175,7 @@ int hexmg_kernel_choice(hexmg_grid_t g, int level, int dtype, int* kernel, int* 
   if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
   if (level < 0 || level >= g->L) return fail(HEXMG_ERR_INVALID, "bad level");
   if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
-  const hexmg_grid::Choice& c = dtype == HEXMG_F64 ? g->choice64[level] : g->choice32[level];
+  const hexmg_grid::Choice& c = (dtype == HEXMG_F64 ? g->choice64[level] : g->choice32[level])[kSmooth];
   if (kernel) *kernel = c.kernel;
   if (zchunk) *zchunk = c.zchunk;
   if (shape) *shape = c.shape;
@@ -1187,7 +1195,7 @@ int hexmg_set_kernel_choice(hexmg_grid_t g, int level, int dtype, int kernel, in
   } else {
     return fail(HEXMG_ERR_INVALID, "bad kernel");
   }
-  (dtype == HEXMG_F64 ? g->choice64 : g->choice32)[level] = c;
+  (dtype == HEXMG_F64 ? g->choice64 : g->choice32)[level].fill(c);
   g->tuned = true;
   return 0;
 }

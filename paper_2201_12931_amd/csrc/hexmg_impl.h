@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -253,7 +254,8 @@ struct hexmg_grid {
   hexmg::HaarCoef<float> hq32;
   // element-product kernel per level and precision ([level][0] binary64, [1] binary32)
   struct Choice { int kernel; int zchunk; int shape; };
-  std::vector<Choice> choice64, choice32;
+  // [level][mode]: the element-product kernel per mode (K u, sweep, residual)
+  std::vector<std::array<Choice, 3>> choice64, choice32;
   // first level of the cooperative coarse-cycle launch per precision (0: every
   // level launched step by step) and its workgroup count
   int tail64 = 0, tail32 = 0, tail_blocks64 = 0, tail_blocks32 = 0;

@@ -97,7 +97,10 @@ __device__ inline void block_product(const HaarCoef<T>& q, T E, const T (&v)[8][
   for (int c = 0; c < 3; ++c) t[0][c] = T(0);
 }
 
-template <typename T, int MODE, int R, int W, int MINW>
+// MASKIN: the input u may be non-zero at fixed DOFs (public K u and V-cycle
+// entry) and is masked on load; without it (every vector inside the solver is
+// zero there) only the outputs use the support bits.
+template <typename T, int MODE, int R, int W, int MINW, bool MASKIN>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     const bool pin = kk >= 0 && kk < L.nzn;
 #pragma unroll
     for (int r = 0; r <= R; ++r) {
-      const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * kk;
       const bool ok = pin && row_in[r];
+      const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * kk;
       m[r] = ok ? (int)L.mask[n] : 7;
       u[r][0] = ok ? ug[3 * n] : T(0);
       u[r][1] = ok ? ug[3 * n + 1] : T(0);
@@ -199,8 +202,8 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     if (MODE != kApply) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1);
         const bool ok = out_plane && row_out[r];
+        const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           fo[r][c] = ok ? fg[3 * n + c] : T(0);
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 #pragma unroll
     for (int r = 0; r <= R; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ue[r][c] = ((mc[r] >> c) & 1) ? T(0) : uc[r][c];
+      for (int c = 0; c < 3; ++c) ue[r][c] = (MASKIN && ((mc[r] >> c) & 1)) ? T(0) : uc[r][c];
     // x-edge modes of row r: s = u(i+1) + u(i), d = u(i+1) - u(i)
     auto xedge = [&](int r, T (&xe)[2][3]) {
 #pragma unroll
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     // node update of plane kk-1 for row r
     auto finish = [&](int r, const T (&Ku)[3]) {
       if (!(out_plane && row_out[r])) return;
-      const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1);
+      T* yp = yg + 3 * ((long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1));
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T Au = ((mo[r] >> c) & 1) ? uo[r][c] : Ku[c];
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
           v = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
         else
           v = fo[r][c] - Au;
-        yg[3 * n + c] = v;
+        yp[c] = v;
       }
     };
     T xa[2][3], xb[2][3];
@@ -362,20 +365,33 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
   }
 }
 
+template <typename T, int R, int W, int MINW, bool MASKIN>
+void launch_stream_mode(int mode, dim3 grid, dim3 block, const Level& L, const HaarCoef<T>& q, const T* E,
+                        const T* u, const T* f, const T* wd, T* y, int zchunk, int nchunks, const int* act,
+                        hipStream_t s, const LaunchTimer& t) {
+  if (mode == kApply)
+    launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks,
+                 act);
+  else if (mode == kSmooth)
+    launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks,
+                 act);
+  else
+    launch_timed(k_stream<T, kResidual, R, W, MINW, MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
+                 nchunks, act);
+}
+
 template <typename T, int R, int W, int MINW>
-void launch_stream_impl(int mode, const Level& L, const HaarCoef<T>& q, const T* E, const T* u, const T* f,
-                        const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
+void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
+                        const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
                         const LaunchTimer& t) {
   constexpr int kOutRows = W * R - 2;
   const int nchunks = (L.nzn + zchunk - 1) / zchunk;
   dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
   dim3 block(64 * W);
-  if (mode == kApply)
-    launch_timed(k_stream<T, kApply, R, W, MINW>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks, act);
-  else if (mode == kSmooth)
-    launch_timed(k_stream<T, kSmooth, R, W, MINW>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks, act);
+  if (maskin)
+    launch_stream_mode<T, R, W, MINW, true>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
   else
-    launch_timed(k_stream<T, kResidual, R, W, MINW>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks, act);
+    launch_stream_mode<T, R, W, MINW, false>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
 }
 
 }  // namespace
@@ -394,19 +410,18 @@ template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
                    const LaunchTimer& t) {
-  (void)maskin;  // inputs are always masked on load
   if constexpr (sizeof(T) == 4) {
     if (shape == 0)
-      launch_stream_impl<T, 2, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 2, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else if (shape == 1)
-      launch_stream_impl<T, 3, 4, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 3, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else
-      launch_stream_impl<T, 4, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 4, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
   } else {
     if (shape == 0)
-      launch_stream_impl<T, 1, 8, 2>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 1, 8, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else
-      launch_stream_impl<T, 2, 4, 1>(mode, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 2, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
   }
 }
 template void launch_stream<float>(int, bool, int, const Level&, const HaarCoef<float>&, const float*,
