@@ -132,7 +132,6 @@ void launch_to64_dot(long long n, const float* u32, const double* r, double* z, 
                      const int* act, hipStream_t s);
 void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s);
 void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s);
-void launch_f32_to_f64(long long n, const float* a, double* b, int nrhs, const int* act, hipStream_t s);
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);
 void launch_fill(long long n, double v, double* x, hipStream_t s);
 

@@ -537,14 +537,6 @@ __global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* _
   if (i < n) b[off + i] = (float)a[off + i];
 }
 
-__global__ void k_f32_to_f64(long long n, const float* __restrict__ a, double* __restrict__ b,
-                             const int* __restrict__ act) {
-  if (act && !act[blockIdx.y]) return;
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  const long long off = n * blockIdx.y;
-  if (i < n) b[off + i] = (double)a[off + i];
-}
-
 __global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b,
                       double* __restrict__ c) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -725,9 +717,6 @@ void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipS
 }
 void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s) {
   k_f64_to_f32<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, a, b, act);
-}
-void launch_f32_to_f64(long long n, const float* a, double* b, int nrhs, const int* act, hipStream_t s) {
-  k_f32_to_f64<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, a, b, act);
 }
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s) {
   k_sub<<<blocks_for(n), kBlock, 0, s>>>(n, a, b, c);
