@@ -397,11 +397,13 @@ void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>
 }  // namespace
 
 // Shapes (rows per thread R, waves per workgroup W, minimum waves per SIMD the
-// register allocation targets).  binary32: (2,4,3) (3,4,2) (4,4,1);
-// binary64: (1,8,3) (2,8,1).  All fit without spilling to memory.
-int stream_shapes(bool f32) { return f32 ? 3 : 2; }
+// register allocation targets).  binary32: (2,4,2) (3,4,2) (4,4,1) (3,8,1)
+// (2,8,1); binary64: (1,8,2) (2,4,1) (taller binary64 tiles spill).  A tile computes W*R element
+// rows for W*R-2 output node rows, so the taller tiles repeat less work at
+// their edges.  All fit without spilling to memory.
+int stream_shapes(bool f32) { return f32 ? 5 : 2; }
 int stream_out_rows(bool f32, int shape) {
-  static const int r32[3] = {4 * 2 - 2, 4 * 3 - 2, 4 * 4 - 2};
+  static const int r32[5] = {4 * 2 - 2, 4 * 3 - 2, 4 * 4 - 2, 8 * 3 - 2, 8 * 2 - 2};
   static const int r64[2] = {8 * 1 - 2, 4 * 2 - 2};
   return f32 ? r32[shape] : r64[shape];
 }
@@ -415,8 +417,12 @@ void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarC
       launch_stream_impl<T, 2, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
     else if (shape == 1)
       launch_stream_impl<T, 3, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
-    else
+    else if (shape == 2)
       launch_stream_impl<T, 4, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+    else if (shape == 3)
+      launch_stream_impl<T, 3, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+    else
+      launch_stream_impl<T, 2, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
   } else {
     if (shape == 0)
       launch_stream_impl<T, 1, 8, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
