@@ -1,0 +1,232 @@
+"""Parity at the full workload sizes, in the launch configuration the bench uses
+(grids created with the defaults, kernels chosen by the autotuner), on outputs
+the oracle computes one by one:
+
+* K u in binary64 and binary32 at sampled nodes -- tile edges in x (62-column
+  tiles), the first and last rows and planes, the fixed face and random
+  interior nodes -- against the oracle's node-by-node product;
+* the mixed-precision solve: the residual f - A u recomputed by the oracle at
+  the sampled nodes from the solver's u (each component is bounded by the
+  2-norm the solver reports), the reported true residual below rtol, and the
+  compliance equal to f^T u;
+* the adjoint sensitivity at sampled elements against the oracle's formula
+  on the same u;
+* at 256x128x128, one optimality-criteria step: the density filter at
+  sampled elements by its definition, the OC update at sampled elements from
+  the returned multiplier, and the volume constraint;
+* the batched workload: every right-hand side of every grid.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import element, fem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def sample_nodes(g: W.Grid, n_random=120, seed=0):
+    """Nodes on the x tile edges, the boundary rows/planes and at random."""
+    rng = np.random.default_rng(seed)
+    xs = sorted({0, 1, 2, 60, 61, 62, 63, 123, 124, g.nx // 2, g.nx - 1, g.nx} & set(range(g.nx + 1)))
+    ys = sorted({0, 1, g.ny // 2, g.ny - 1, g.ny} & set(range(g.ny + 1)))
+    zs = sorted({0, 1, 4, 5, g.nz // 2, g.nz - 1, g.nz} & set(range(g.nz + 1)))
+    pts = [(i, j, k) for i in xs for j in ys[:: max(1, len(ys) // 3)] for k in zs[:: max(1, len(zs) // 3)]]
+    pts += [tuple(int(v) for v in rng.integers(0, (g.nx + 1, g.ny + 1, g.nz + 1))) for _ in range(n_random)]
+    return np.unique(np.array([g.node(i, j, k) for i, j, k in pts], dtype=np.int64))
+
+
+def sample_elements(g: W.Grid, n=200, seed=1):
+    rng = np.random.default_rng(seed)
+    corners = [0, g.nx - 1, g.nx * (g.ny - 1), g.n_elem - 1]
+    return np.unique(np.concatenate([corners, rng.integers(0, g.n_elem, n)]))
+
+
+def element_sensitivity(g, rho, u, elems, p=3.0, E0=1.0, Emin=1e-9):
+    """Eq. 7 element by element: -p rho^(p-1) (E0 - Emin) u_e^T K0 u_e, and
+    the size of the terms it sums, p rho^(p-1) (E0 - Emin) |u_e|^2 lambda_max(K0),
+    against which rounding is measured (near-rigid element motions cancel)."""
+    Ke = element.hex8_stiffness(0.3)
+    lmax = float(np.linalg.eigvalsh(Ke)[-1])
+    out, scale = [], []
+    for e in elems:
+        i, j, k = e % g.nx, (e // g.nx) % g.ny, e // (g.nx * g.ny)
+        dofs = []
+        for a in range(8):
+            n = g.node(i + (a & 1), j + ((a >> 1) & 1), k + (a >> 2))
+            dofs += [3 * n, 3 * n + 1, 3 * n + 2]
+        ue = u[dofs]
+        f = p * rho[e] ** (p - 1.0) * (E0 - Emin)
+        out.append(-f * float(ue @ Ke @ ue))
+        scale.append(f * float(ue @ ue) * lmax)
+    return np.array(out), np.array(scale)
+
+
+def check_solve(g, rho, mask, f, u, info, rtol, nodes):
+    """Sampled residual, reported true residual, compliance consistency."""
+    free = fem.free_dof_mask(mask)
+    Mf = f * free
+    fn = float(np.linalg.norm(Mf))
+    Au = fem.apply_constrained_at_nodes(g.nx, g.ny, g.nz, fem.simp_modulus(rho), mask, u, nodes)
+    r = Mf.reshape(-1, 3)[nodes] - Au
+    assert info["rel_res_true"] <= rtol
+    assert np.abs(r).max() <= info["rel_res_true"] * fn * (1 + 1e-6) + 1e-14 * fn
+    assert info["compliance"] == pytest.approx(float(f @ u), rel=1e-12)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    _gpu()
+    g, rho, f, mask, spec = W.workload("cantilever_128x64x64_rf")
+    from paper_2201_12931_amd import hexmg
+
+    grid = hexmg.Grid(g.nx, g.ny, g.nz, spec["levels"], precision=hexmg.MIXED)
+    grid.set_density(gpu(rho))
+    return g, rho, f, mask, spec, grid
+
+
+def test_fullsize_128x64x64_apply(c1):
+    print("case full-size K u 128x64x64", flush=True)
+    g, rho, f, mask, spec, grid = c1
+    nodes = sample_nodes(g)
+    u = W.random_vector(g.n_dof, seed=51)
+    ref = fem.apply_constrained_at_nodes(g.nx, g.ny, g.nz, fem.simp_modulus(rho), mask, u, nodes)
+    y64 = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+    grid.apply_K(gpu(u), y64)
+    y = y64.cpu().numpy().reshape(-1, 3)[nodes]
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    y32 = torch.empty(g.n_dof, dtype=torch.float32, device="cuda")
+    grid.apply_K(gpu(u.astype(np.float32)), y32)
+    y = y32.cpu().numpy().reshape(-1, 3)[nodes]
+    assert np.abs(y - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_fullsize_128x64x64_solve_and_sensitivity(c1):
+    print("case full-size solve 128x64x64", flush=True)
+    g, rho, f, mask, spec, grid = c1
+    u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+    code, info = grid.solve(gpu(f), u, rtol=spec["rtol"])
+    assert code == 0
+    un = u.cpu().numpy()
+    check_solve(g, rho, mask, f, un, info[0], spec["rtol"], sample_nodes(g, seed=3))
+    dc = torch.empty(g.n_elem, dtype=torch.float64, device="cuda")
+    grid.compliance_sensitivity(gpu(f), u, dc)
+    elems = sample_elements(g)
+    ref, scale = element_sensitivity(g, rho, un, elems)
+    assert np.all(np.abs(dc.cpu().numpy()[elems] - ref) <= 1e-13 * scale + 1e-300)
+
+
+def test_fullsize_batched_192x96x96_and_uneven_grids():
+    """The batched workload: 8 point-load cases in lockstep on 192x96x96 plus
+    16 uneven cantilevers, advanced together; every right-hand side checked."""
+    from paper_2201_12931_amd import hexmg
+    from paper_2201_12931_amd.run_batch import UNEVEN_NX, levels_for
+
+    _gpu()
+    print("case full-size batched workload", flush=True)
+    g, rho, F, mask, spec = W.workload("batched_192x96x96_8rhs")
+    problems = [(g, spec["levels"], rho, F)]
+    for k, nx in enumerate(UNEVEN_NX):
+        gk = W.Grid(nx, nx // 2, nx // 2)
+        problems.append((gk, levels_for(nx // 2), W.random_field_density(gk, seed=300 + k, lo=0.01),
+                         W.cantilever_line_load(gk)[None, :]))
+    grids, fs, us = [], [], []
+    for gk, L, rk, fk in problems:
+        grid = hexmg.Grid(gk.nx, gk.ny, gk.nz, L, precision=hexmg.MIXED, max_nrhs=fk.shape[0])
+        grid.set_density(gpu(rk))
+        grids.append(grid)
+        fs.append(gpu(fk))
+        us.append(torch.empty_like(fs[-1]))
+    code, infos = hexmg.batch_solve(grids, fs, us, rtol=1e-6)
+    assert code == 0
+    for (gk, L, rk, fk), u, info in zip(problems, us, infos):
+        mk = W.fixed_mask_face_x0(gk)
+        un = u.cpu().numpy()
+        nodes = sample_nodes(gk, n_random=40, seed=gk.nx)
+        for r in range(fk.shape[0]):
+            check_solve(gk, rk, mk, fk[r], un[r], info[r], 1e-6, nodes)
+
+
+def test_fullsize_256x128x128_oc_step():
+    """One optimisation step at 256x128x128 (density filter, volume 0.12):
+    filter, sensitivity chain and OC update checked at sampled elements."""
+    from paper_2201_12931_amd import hexmg
+    from paper_2201_12931_amd.topopt import TopOpt
+
+    _gpu()
+    print("case full-size OC step 256x128x128", flush=True)
+    g = W.Grid(256, 128, 128)
+    f = W.cantilever_line_load(g)
+    opt = TopOpt(256, 128, 128, 6, gpu(f), volfrac=0.12)
+    rng = np.random.default_rng(7)
+    opt.x = gpu(rng.uniform(0.05, 0.4, g.n_elem))  # a non-uniform design
+    x = opt.x.cpu().numpy()
+    c, dc, rho = opt.gradient(opt.x)
+    elems = sample_elements(g, n=150, seed=8)
+    rmin, R = 1.5, 1
+    rho_n = rho.cpu().numpy()
+    for e in elems:  # Eqs. 4-5 by definition
+        i, j, k = e % g.nx, (e // g.nx) % g.ny, e // (g.nx * g.ny)
+        s = ws = 0.0
+        for dk in range(-R, R + 1):
+            for dj in range(-R, R + 1):
+                for di in range(-R, R + 1):
+                    ii, jj, kk = i + di, j + dj, k + dk
+                    if not (0 <= ii < g.nx and 0 <= jj < g.ny and 0 <= kk < g.nz):
+                        continue
+                    w = rmin - math.sqrt(di * di + dj * dj + dk * dk)
+                    if w > 0:
+                        s += w * x[ii + g.nx * (jj + g.ny * kk)]
+                        ws += w
+        assert rho_n[e] == pytest.approx(s / ws, rel=1e-13)
+    x_new, lam = opt.grid.oc_update(opt.x, dc, opt.dv, 0.12, 0.2, 0.5)
+    xn, dcn, dvn = x_new.cpu().numpy(), dc.cpu().numpy(), opt.dv.cpu().numpy()
+    B = np.maximum(-dcn[elems] / (lam * dvn[elems]), 0.0)
+    ref = np.clip(x[elems] * np.sqrt(B), np.maximum(0, x[elems] - 0.2), np.minimum(1, x[elems] + 0.2))
+    assert np.abs(xn[elems] - ref).max() < 1e-10
+    assert float(dvn @ xn) == pytest.approx(0.12, rel=1e-9)
+
+
+def test_fullsize_768x384x384():
+    """113 M elements: K u in binary32 at sampled nodes, the mixed solve
+    (sampled residual), and the sensitivity at sampled elements."""
+    from paper_2201_12931_amd import hexmg
+
+    _gpu()
+    print("case full-size 768x384x384", flush=True)
+    g, rho, f, mask, spec = W.workload("cantilever_768x384x384_rf")
+    grid = hexmg.Grid(g.nx, g.ny, g.nz, spec["levels"], precision=hexmg.MIXED)
+    grid.set_density(gpu(rho))
+    E = fem.simp_modulus(rho)
+    nodes = sample_nodes(g, n_random=80, seed=9)
+    u32 = torch.randn(g.n_dof, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    y32 = torch.empty_like(u32)
+    grid.apply_K(u32, y32)
+    un = u32.cpu().numpy().astype(np.float64)
+    ref = fem.apply_constrained_at_nodes(g.nx, g.ny, g.nz, E, mask, un, nodes)
+    y = y32.cpu().numpy().reshape(-1, 3)[nodes]
+    assert np.abs(y - ref).max() <= 1e-5 * np.abs(ref).max()
+    del u32, y32, un
+    fd = gpu(f)
+    u = torch.empty_like(fd)
+    code, info = grid.solve(fd, u, rtol=spec["rtol"])
+    assert code == 0
+    un = u.cpu().numpy()
+    check_solve(g, rho, mask, f, un, info[0], spec["rtol"], nodes)
+    dc = torch.empty(g.n_elem, dtype=torch.float64, device="cuda")
+    grid.compliance_sensitivity(fd, u, dc)
+    elems = sample_elements(g, n=100, seed=10)
+    refs, scale = element_sensitivity(g, rho, un, elems)
+    assert np.all(np.abs(dc.cpu().numpy()[elems] - refs) <= 1e-13 * scale + 1e-300)
