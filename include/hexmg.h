@@ -74,7 +74,8 @@ extern "C" {
 typedef struct hexmg_grid *hexmg_grid_t;
 
 typedef struct {
-  int nx, ny, nz;       /* elements per axis; each divisible by 2^(levels-1) */
+  int nx, ny, nz;       /* elements per axis; each divisible by 2^(levels-1);
+                           3 (nx+1)(ny+1)(nz+1) < 2^31 and 24 (nx+1)(ny+1) < 2^31 */
   int levels;           /* multigrid levels, >= 1; level 0 is the given grid */
   double E0, Emin, nu, penal; /* 1, 1e-9, 0.3, 3 in the paper's examples */
   int precision;        /* HEXMG_FP64 | HEXMG_MIXED */

@@ -50,6 +50,8 @@ int validate(const hexmg_grid_desc* d) {
     return fail(HEXMG_ERR_INVALID, "grid dimensions must be divisible by 2^(levels-1)");
   const long long nn = (long long)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
   if (3 * nn >= (1ll << 31)) return fail(HEXMG_ERR_INVALID, "grid too large (3*nodes must be < 2^31)");
+  if (24ll * (d->nx + 1) * (d->ny + 1) >= (1ll << 31))
+    return fail(HEXMG_ERR_INVALID, "xy plane too large (24*(nx+1)*(ny+1) must be < 2^31)");
   const long long nnc = (long long)(d->nx / q + 1) * (d->ny / q + 1) * (d->nz / q + 1);
   if (3 * nnc > 6144) return fail(HEXMG_ERR_INVALID, "coarsest level too large for the dense solve (> 6144 DOFs); add levels");
   if (!(d->Emin > 0.0) || !(d->E0 > d->Emin) || !std::isfinite(d->E0))

@@ -8,9 +8,11 @@
 // where H is the 8x8 tensor product of the per-axis [[1,1],[-1,1]] maps.
 // The sums and differences are shared between neighbouring elements: the
 // x-stage (per node) is shared by the 4 elements around an x-edge, the y-stage
-// (per xy-face) by the 2 elements above and below it; only the z-stage, the
-// block product and their adjoints are per element.  This takes K u from
-// 576 FMA per node (dense 24x24 rows) to ~150 VALU operations per node.
+// (per xy-face) by the 2 elements above and below it, and so are their
+// adjoints (the two elements' contributions to a face are summed in the face's
+// modes before the y and x adjoints); only the z-stage, the block product and
+// the z adjoint are per element.  This takes K u from 576 FMA per node (dense
+// 24x24 rows) to about 150 VALU operations per node.
 //
 // Mapping.  A wave owns 64 consecutive node columns in x (lane = column) and R
 // consecutive node rows in y (held in registers); a workgroup stacks W waves in
@@ -19,8 +21,9 @@
 // same thread, and the only cross-wave dependency (the adjoint contribution of
 // a wave's last face row to the next wave's first node row) goes through LDS,
 // double-buffered by plane parity, with one barrier per plane.  Each tile reads
-// a one-node halo on every side and writes the interior: 62 columns x (W*R-2)
-// rows x its z-chunk.  Every output is written exactly once: no atomics.
+// a one-node halo on every side and writes the nodes whose elements it holds
+// on both sides: 62 columns x (W*R-1) rows x its z-chunk.  Every output is
+// written exactly once: no atomics.
 //
 // Out-of-domain nodes read as 0 and out-of-domain elements have modulus 0, so
 // the boundary needs no special case.  Fixed DOFs read as 0 and return u.
@@ -97,6 +100,62 @@ __device__ inline void block_product(const HaarCoef<T>& q, T E, const T (&v)[8][
   for (int c = 0; c < 3; ++c) t[0][c] = T(0);
 }
 
+// Buffer-resource access.  Every load and store of the kernel goes through a
+// raw buffer resource that spans one z-plane of one array; the per-lane byte
+// offset inside the plane is fixed for the whole z-march and only the plane
+// base (a uniform value) moves.  An offset at or past the resource's size reads
+// as 0 and drops the store, which is how nodes and elements outside the domain
+// (or outside the tile's output window) are handled: kOutside is such an
+// offset for every resource, and a resource of size 0 disables a whole plane.
+constexpr int kRsrcWord3 = 0x00020000;      // raw buffer, 32-bit dwords
+constexpr int kOutside = (int)0x80000000;   // planes are < 2 GiB
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+typedef unsigned u32x3 __attribute__((__vector_size__(3 * sizeof(unsigned))));
+
+__device__ inline Rsrc plane_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, kRsrcWord3);
+}
+__device__ inline void load3(Rsrc r, int off, float (&v)[3]) {
+  const u32x3 x = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+  v[0] = __uint_as_float(x[0]);
+  v[1] = __uint_as_float(x[1]);
+  v[2] = __uint_as_float(x[2]);
+}
+__device__ inline void load3(Rsrc r, int off, double (&v)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * c, 0, 0);
+    v[c] = __longlong_as_double((long long)(((unsigned long long)x[1] << 32) | x[0]));
+  }
+}
+__device__ inline float load1(Rsrc r, int off, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline double load1(Rsrc r, int off, double) {
+  const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __longlong_as_double((long long)(((unsigned long long)x[1] << 32) | x[0]));
+}
+__device__ inline void store3(Rsrc r, int off, const float (&v)[3]) {
+  const u32x3 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
+  __builtin_amdgcn_raw_buffer_store_b96(x, r, off, 0, 0);
+}
+__device__ inline void store3(Rsrc r, int off, const double (&v)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v[c]);
+    const u32x2 x = {(unsigned)(b & 0xffffffffull), (unsigned)(b >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, off + 8 * c, 0, 0);
+  }
+}
+
+// bit c of m set ? a : b, as a bit-field select.
+__device__ inline float select_bit(int m, int c, float a, float b) {
+  const int sel = (m << (31 - c)) >> 31;
+  return __int_as_float((sel & __float_as_int(a)) | (~sel & __float_as_int(b)));
+}
+__device__ inline double select_bit(int m, int c, double a, double b) { return ((m >> c) & 1) ? a : b; }
+
 // MASKIN: the input u may be non-zero at fixed DOFs (public K u and V-cycle
 // entry) and is masked on load; without it (every vector inside the solver is
 // zero there) only the outputs use the support bits.
@@ -114,7 +173,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
   }
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  constexpr int kOutRows = W * R - 2;
+  constexpr int kOutRows = W * R - 1;
   const int i = blockIdx.x * 62 - 1 + lane;           // node column of this lane
   const int jt0 = blockIdx.y * kOutRows - 1;          // first (halo) row of the tile
   const int j0 = jt0 + w * R;                         // first row of this wave
@@ -125,60 +184,67 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
   const bool col_elem = i >= 0 && i < L.nx;
   const long long plane = (long long)L.nxn * L.nyn;
   const long long eplane = (long long)L.nx * L.ny;
-
-  __shared__ T xch[2][W][6][64];  // [parity][wave][bottom xyz, top xyz][lane]
+  const int vbytes = (int)(3 * plane * (long long)sizeof(T));   // one plane of a nodal vector
+  const int ebytes = (int)(eplane * (long long)sizeof(T));      // one layer of moduli
+  const int mbytes = (int)plane;                                 // one plane of support bits
 
   // Row r of this wave is node row j0 + r; rows 0..R are read, rows 0..R-1 own
   // element rows and (when inside the tile's output window) output rows.
-  bool row_in[R + 1], row_elem[R], row_out[R];
+  // Byte offsets inside a plane; kOutside where the row is not read / written.
+  int offu[R + 1], offm[R + 1], offe[R], offo[R], offmo[R];
 #pragma unroll
   for (int r = 0; r <= R; ++r) {
     const int jr = j0 + r;
-    row_in[r] = col_in && jr >= 0 && jr < L.nyn;
+    const int n = i + L.nxn * jr;
+    const bool in = col_in && jr >= 0 && jr < L.nyn;
+    offu[r] = in ? n * (3 * (int)sizeof(T)) : kOutside;
+    offm[r] = in ? n : kOutside;
     if (r < R) {
-      row_elem[r] = col_elem && jr >= 0 && jr < L.ny;
+      offe[r] = (col_elem && jr >= 0 && jr < L.ny) ? (i + L.nx * jr) * (int)sizeof(T) : kOutside;
       const int rt = w * R + r;
-      row_out[r] = lane_out && rt >= 1 && rt <= kOutRows && jr < L.nyn;
+      const bool out = lane_out && rt >= 1 && rt <= kOutRows && jr < L.nyn;
+      offo[r] = out ? offu[r] : kOutside;
+      offmo[r] = out ? n : kOutside;
     }
   }
 
-  // Software pipeline: the raw u and support bits of plane kk+1 and the moduli
-  // of element layer kk are requested while plane kk is being processed.
+  // Software pipeline: the raw u (and, with MASKIN, the support bits) of plane
+  // kk+1 and the moduli of element layer kk are requested while plane kk is
+  // being processed.
   T un[R + 1][3], uc[R + 1][3], uo[R][3];
-  int mn[R + 1], mc[R + 1], mo[R];
+  int mn[R + 1], mc[R + 1];
   T En[R], Ec[R];
+  __shared__ T xch[2][W][3][64];  // [parity][wave][xyz][lane]: node values for the next wave
   auto load_plane = [&](int kk, T (&u)[R + 1][3], int (&m)[R + 1]) {
     const bool pin = kk >= 0 && kk < L.nzn;
+    const Rsrc ru = plane_rsrc(ug + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
 #pragma unroll
-    for (int r = 0; r <= R; ++r) {
-      const bool ok = pin && row_in[r];
-      const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * kk;
-      m[r] = ok ? (int)L.mask[n] : 7;
-      u[r][0] = ok ? ug[3 * n] : T(0);
-      u[r][1] = ok ? ug[3 * n + 1] : T(0);
-      u[r][2] = ok ? ug[3 * n + 2] : T(0);
+    for (int r = 0; r <= R; ++r) load3(ru, offu[r], u[r]);
+    if (MASKIN) {
+      const Rsrc rm = plane_rsrc(L.mask + plane * (pin ? kk : 0), pin ? mbytes : 0);
+#pragma unroll
+      for (int r = 0; r <= R; ++r) m[r] = __builtin_amdgcn_raw_buffer_load_b8(rm, offm[r], 0, 0);
     }
   };
   auto load_layer = [&](int ke, T (&E)[R]) {
     const bool lin = ke >= 0 && ke < L.nz;
+    const Rsrc re = plane_rsrc(Eg + eplane * (lin ? ke : 0), lin ? ebytes : 0);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const long long e = (long long)i + (long long)L.nx * (j0 + r) + eplane * ke;
-      E[r] = (lin && row_elem[r]) ? Eg[e] : T(0);
-    }
+    for (int r = 0; r < R; ++r) E[r] = load1(re, offe[r], T(0));
   };
 
-  T Fp[R][4][3];   // face modes of the previous plane
-  T Yp[R][3];      // pending node sums of the previous plane
+  T Fp[R][4][3];   // face modes of the previous plane (forward transform)
+  T Tp[R][4][3];   // top-face modes of the previous element layer (adjoint)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    mo[r] = 7;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      Yp[r][c] = T(0);
       uo[r][c] = T(0);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) Fp[r][m][c] = T(0);
+      for (int m = 0; m < 4; ++m) {
+        Fp[r][m][c] = T(0);
+        Tp[r][m][c] = T(0);
+      }
     }
   }
   load_plane(kc0 - 1, un, mn);
@@ -188,7 +254,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     // rotate the pipeline and request the next plane / layer
 #pragma unroll
     for (int r = 0; r <= R; ++r) {
-      mc[r] = mn[r];
+      if (MASKIN) mc[r] = mn[r];
 #pragma unroll
       for (int c = 0; c < 3; ++c) uc[r][c] = un[r][c];
     }
@@ -196,60 +262,71 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     for (int r = 0; r < R; ++r) Ec[r] = En[r];
     load_plane(kk + 1, un, mn);
     load_layer(kk, En);
-    // f and omega/D of plane kk-1 for this iteration's epilogue
-    T fo[R][3], wo[R][3];
+    // support bits, f and omega/D of plane kk-1 for this iteration's epilogue
     const bool out_plane = kk - 1 >= kc0;
-    if (MODE != kApply) {
+    const long long po = plane * (out_plane ? kk - 1 : 0);
+    const Rsrc ry = plane_rsrc(yg + 3 * po, out_plane ? vbytes : 0);
+    int mo[R];
+    T fo[R][3], wo[R][3];
+    {
+      const Rsrc rm = plane_rsrc(L.mask + po, out_plane ? mbytes : 0);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const bool ok = out_plane && row_out[r];
-        const long long n = (long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          fo[r][c] = ok ? fg[3 * n + c] : T(0);
-          wo[r][c] = (MODE == kSmooth && ok) ? wg[3 * n + c] : T(0);
-        }
-      }
+      for (int r = 0; r < R; ++r) mo[r] = __builtin_amdgcn_raw_buffer_load_b8(rm, offmo[r], 0, 0);
     }
-    // masked u of plane kk (fixed and outside DOFs read as 0)
+    if (MODE != kApply) {
+      const Rsrc rf = plane_rsrc(fg + 3 * po, out_plane ? vbytes : 0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) load3(rf, offo[r], fo[r]);
+    }
+    if (MODE == kSmooth) {
+      const Rsrc rw = plane_rsrc(wg + 3 * po, out_plane ? vbytes : 0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) load3(rw, offo[r], wo[r]);
+    }
+    // u of plane kk (fixed DOFs masked when the input may be non-zero there)
     T ue[R + 1][3];
 #pragma unroll
     for (int r = 0; r <= R; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ue[r][c] = (MASKIN && ((mc[r] >> c) & 1)) ? T(0) : uc[r][c];
-    // x-edge modes of row r: s = u(i+1) + u(i), d = u(i+1) - u(i)
+      for (int c = 0; c < 3; ++c) ue[r][c] = MASKIN ? select_bit(mc[r], c, T(0), uc[r][c]) : uc[r][c];
+    // x-edge modes of row r: s = u(i+1) + u(i), d = u(i+1) - u(i).  The
+    // difference is formed as -(u(i) - u(i+1)) so that both shifts fold into
+    // their additions (lane 63 reads 0 from its missing neighbour).
     auto xedge = [&](int r, T (&xe)[2][3]) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T nx_ = lane_next(ue[r][c]);
-        xe[0][c] = nx_ + ue[r][c];
-        xe[1][c] = nx_ - ue[r][c];
+        xe[0][c] = lane_next(ue[r][c]) + ue[r][c];
+        xe[1][c] = -(ue[r][c] - lane_next(ue[r][c]));
       }
+    };
+    // x adjoint of an edge row: node i takes the "0" end of edge i and the
+    // "1" end of edge i-1.
+    auto xadjoint = [&](const T (&e)[2][3], T (&nv)[3]) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nv[c] = (e[0][c] - e[1][c]) + lane_prev(e[0][c] + e[1][c]);
     };
     // node update of plane kk-1 for row r
     auto finish = [&](int r, const T (&Ku)[3]) {
-      if (!(out_plane && row_out[r])) return;
-      T* yp = yg + 3 * ((long long)i + (long long)L.nxn * (j0 + r) + plane * (kk - 1));
+      T v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T Au = ((mo[r] >> c) & 1) ? uo[r][c] : Ku[c];
-        T v;
+        const T Au = select_bit(mo[r], c, uo[r][c], Ku[c]);
         if (MODE == kApply)
-          v = Au;
+          v[c] = Au;
         else if (MODE == kSmooth)
-          v = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
+          v[c] = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
         else
-          v = fo[r][c] - Au;
-        yp[c] = v;
+          v[c] = fo[r][c] - Au;
       }
+      store3(ry, offo[r], v);
     };
     T xa[2][3], xb[2][3];
     xedge(0, xa);
 
     if (kk >= kc0) {
       // ---- element layer kk-1 (between planes kk-1 and kk) -----------------
-      T carry_b[2][3], carry_t[2][3];    // "1"-end edge contributions to row r+1
-      T x0b[2][3], x0t[2][3];            // row 0 edge sums awaiting the previous wave
+      T carry[2][3];   // "1"-end contributions of the face row above to edge row r+1
+      T e0row[2][3];   // edge row 0 ("0" ends only) awaiting the previous wave
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         T (&xlo)[2][3] = (r & 1) ? xb : xa;
@@ -273,70 +350,51 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
         }
         T t[8][3];
         block_product<T>(q, Ec[r], v, t);
-        // z adjoint: bottom face (plane kk-1) = t_s - t_d, top face (plane kk) = t_s + t_d;
-        // y adjoint: edge row r ("0" end) = G_s - G_d, edge row r+1 ("1" end) = G_s + G_d.
-        T eb0[2][3], et0[2][3];
+        // z adjoint: bottom face (plane kk-1) = t_lo - t_hi, top face (plane kk)
+        // = t_lo + t_hi.  The bottom face joins the top face of the layer below
+        // (same xy face), and the y adjoint is applied once to their sum:
+        // edge row r ("0" end) = F_s - F_d, edge row r+1 ("1" end) = F_s + F_d.
+        T e[2][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
 #pragma unroll
           for (int xm = 0; xm < 2; ++xm) {
-            const T bs = t[xm][c] - t[xm + 4][c], bd = t[xm + 2][c] - t[xm + 6][c];
-            const T ts = t[xm][c] + t[xm + 4][c], td = t[xm + 2][c] + t[xm + 6][c];
-            eb0[xm][c] = bs - bd;
-            et0[xm][c] = ts - td;
-            if (r > 0) {
-              eb0[xm][c] += carry_b[xm][c];
-              et0[xm][c] += carry_t[xm][c];
-            }
-            carry_b[xm][c] = bs + bd;
-            carry_t[xm][c] = ts + td;
+            const T Fs = Tp[r][xm][c] + (t[xm][c] - t[xm + 4][c]);
+            const T Fd = Tp[r][xm + 2][c] + (t[xm + 2][c] - t[xm + 6][c]);
+            Tp[r][xm][c] = t[xm][c] + t[xm + 4][c];
+            Tp[r][xm + 2][c] = t[xm + 2][c] + t[xm + 6][c];
+            e[xm][c] = (r > 0) ? carry[xm][c] + (Fs - Fd) : Fs - Fd;
+            carry[xm][c] = Fs + Fd;
           }
         }
         if (r == 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int xm = 0; xm < 2; ++xm) {
-              x0b[xm][c] = eb0[xm][c];
-              x0t[xm][c] = et0[xm][c];
-            }
+            for (int xm = 0; xm < 2; ++xm) e0row[xm][c] = e[xm][c];
         } else {
-          // edge row r complete: x adjoint gives the node sums of row r
           T Ku[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const T bs = eb0[0][c], bd = eb0[1][c], ts = et0[0][c], td = et0[1][c];
-            Ku[c] = Yp[r][c] + (bs - bd) + lane_prev(bs + bd);
-            Yp[r][c] = (ts - td) + lane_prev(ts + td);
-          }
+          xadjoint(e, Ku);
           finish(r, Ku);
         }
       }
-      // The last face row's "1"-end edge contributions belong to the next
-      // wave's first node row: apply the x adjoint here and hand over the node
-      // values through LDS.
+      // The last face row's "1"-end contributions belong to the next wave's
+      // first node row: apply the x adjoint here and hand the node values over
+      // through LDS.
       T(*slot)[64] = xch[kk & 1][w];
+      {
+        T nv[3];
+        xadjoint(carry, nv);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T bs = carry_b[0][c], bd = carry_b[1][c], ts = carry_t[0][c], td = carry_t[1][c];
-        slot[c][lane] = (bs - bd) + lane_prev(bs + bd);
-        slot[3 + c][lane] = (ts - td) + lane_prev(ts + td);
+        for (int c = 0; c < 3; ++c) slot[c][lane] = nv[c];
       }
       __syncthreads();
       T Ku[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T bs = x0b[0][c], bd = x0b[1][c], ts = x0t[0][c], td = x0t[1][c];
-        Ku[c] = Yp[0][c] + (bs - bd) + lane_prev(bs + bd);
-        Yp[0][c] = (ts - td) + lane_prev(ts + td);
-      }
+      xadjoint(e0row, Ku);
       if (w > 0) {
         T(*prev)[64] = xch[kk & 1][w - 1];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          Ku[c] += prev[c][lane];
-          Yp[0][c] += prev[3 + c][lane];
-        }
+        for (int c = 0; c < 3; ++c) Ku[c] += prev[c][lane];
       }
       finish(0, Ku);
     } else {
@@ -357,11 +415,9 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     }
     // plane kk becomes the previous plane
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      mo[r] = mc[r];
+    for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) uo[r][c] = uc[r][c];
-    }
   }
 }
 
@@ -384,7 +440,7 @@ template <typename T, int R, int W, int MINW>
 void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                         const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
                         const LaunchTimer& t) {
-  constexpr int kOutRows = W * R - 2;
+  constexpr int kOutRows = W * R - 1;
   const int nchunks = (L.nzn + zchunk - 1) / zchunk;
   dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
   dim3 block(64 * W);
@@ -398,13 +454,13 @@ void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>
 
 // Shapes (rows per thread R, waves per workgroup W, minimum waves per SIMD the
 // register allocation targets).  binary32: (2,4,2) (3,4,2) (4,4,1) (3,8,1)
-// (2,8,1); binary64: (1,8,2) (2,4,1) (taller binary64 tiles spill).  A tile computes W*R element
-// rows for W*R-2 output node rows, so the taller tiles repeat less work at
-// their edges.  All fit without spilling to memory.
+// (2,8,1); binary64: (1,8,2) (2,4,1) (taller binary64 tiles spill).  A tile
+// computes W*R element rows for W*R-1 output node rows, so the taller tiles
+// repeat less work at their edges.  All fit without spilling to memory.
 int stream_shapes(bool f32) { return f32 ? 5 : 2; }
 int stream_out_rows(bool f32, int shape) {
-  static const int r32[5] = {4 * 2 - 2, 4 * 3 - 2, 4 * 4 - 2, 8 * 3 - 2, 8 * 2 - 2};
-  static const int r64[2] = {8 * 1 - 2, 4 * 2 - 2};
+  static const int r32[5] = {4 * 2 - 1, 4 * 3 - 1, 4 * 4 - 1, 8 * 3 - 1, 8 * 2 - 1};
+  static const int r64[2] = {8 * 1 - 1, 4 * 2 - 1};
   return f32 ? r32[shape] : r64[shape];
 }
 
