@@ -224,7 +224,7 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
   const bool f32 = sizeof(T) == 4;
   std::vector<hexmg_grid::Choice> cand;
   for (int sh = 0; sh < stream_shapes(f32); ++sh)
-    for (int zc : {2, 4, 8, 16, 32, 64})
+    for (int zc : {1, 2, 4, 8, 16, 32, 64})
       if (zc <= L.nzn || zc == 2) cand.push_back({HEXMG_KERNEL_STREAM, zc, sh});
   cand.push_back({HEXMG_KERNEL_GATHER, 0, 0});
   hipEvent_t e0, e1;

@@ -159,7 +159,8 @@ __device__ inline double select_bit(int m, int c, double a, double b) { return (
 // MASKIN: the input u may be non-zero at fixed DOFs (public K u and V-cycle
 // entry) and is masked on load; without it (every vector inside the solver is
 // zero there) only the outputs use the support bits.
-template <typename T, int MODE, int R, int W, int MINW, bool MASKIN>
+// PRE > 0: zchunk is PRE and all inputs of the workgroup are requested up front.
+template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
@@ -215,8 +216,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
   int mn[R + 1], mc[R + 1];
   T En[R], Ec[R];
   __shared__ T xch[2][W][3][64];  // [parity][wave][xyz][lane]: node values for the next wave
+  // Only planes kc0-1..kc1 and element layers kc0-1..kc1-1 are needed; the
+  // pipeline's requests outside them are given empty resources (no traffic).
   auto load_plane = [&](int kk, T (&u)[R + 1][3], int (&m)[R + 1]) {
-    const bool pin = kk >= 0 && kk < L.nzn;
+    const bool pin = kk >= 0 && kk < L.nzn && kk <= kc1;
     const Rsrc ru = plane_rsrc(ug + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
 #pragma unroll
     for (int r = 0; r <= R; ++r) load3(ru, offu[r], u[r]);
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     }
   };
   auto load_layer = [&](int ke, T (&E)[R]) {
-    const bool lin = ke >= 0 && ke < L.nz;
+    const bool lin = ke >= 0 && ke < L.nz && ke >= kc0 - 1 && ke < kc1;
     const Rsrc re = plane_rsrc(Eg + eplane * (lin ? ke : 0), lin ? ebytes : 0);
 #pragma unroll
     for (int r = 0; r < R; ++r) E[r] = load1(re, offe[r], T(0));
@@ -247,27 +250,11 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       }
     }
   }
-  load_plane(kc0 - 1, un, mn);
-  load_layer(kc0 - 2, En);
-
-  for (int kk = kc0 - 1; kk <= kc1; ++kk) {
-    // rotate the pipeline and request the next plane / layer
-#pragma unroll
-    for (int r = 0; r <= R; ++r) {
-      if (MASKIN) mc[r] = mn[r];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) uc[r][c] = un[r][c];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) Ec[r] = En[r];
-    load_plane(kk + 1, un, mn);
-    load_layer(kk, En);
-    // support bits, f and omega/D of plane kk-1 for this iteration's epilogue
-    const bool out_plane = kk - 1 >= kc0;
+  // Inputs of the epilogue of iteration kk (output plane kk-1): support bits,
+  // f and omega/D.
+  auto load_out = [&](int kk, int (&mo)[R], T (&fo)[R][3], T (&wo)[R][3]) {
+    const bool out_plane = kk - 1 >= kc0 && kk - 1 < kc1;
     const long long po = plane * (out_plane ? kk - 1 : 0);
-    const Rsrc ry = plane_rsrc(yg + 3 * po, out_plane ? vbytes : 0);
-    int mo[R];
-    T fo[R][3], wo[R][3];
     {
       const Rsrc rm = plane_rsrc(L.mask + po, out_plane ? mbytes : 0);
 #pragma unroll
@@ -283,6 +270,14 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 #pragma unroll
       for (int r = 0; r < R; ++r) load3(rw, offo[r], wo[r]);
     }
+  };
+
+  // Iteration kk: x and y stages of plane kk; for kk >= kc0 also element layer
+  // kk-1 and the output of plane kk-1.
+  auto body = [&](int kk, const T (&uc)[R + 1][3], const int (&mc)[R + 1], const T (&Ec)[R], const int (&mo)[R],
+                  const T (&fo)[R][3], const T (&wo)[R][3]) {
+    const bool out_plane = kk - 1 >= kc0 && kk - 1 < kc1;
+    const Rsrc ry = plane_rsrc(yg + 3 * plane * (out_plane ? kk - 1 : 0), out_plane ? vbytes : 0);
     // u of plane kk (fixed DOFs masked when the input may be non-zero there)
     T ue[R + 1][3];
 #pragma unroll
@@ -418,21 +413,64 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) uo[r][c] = uc[r][c];
+  };
+
+  if constexpr (PRE > 0) {
+    // zchunk == PRE output planes per workgroup (the library launches PRE = 1
+    // for a z-chunk of one plane): every input is requested before any
+    // arithmetic, so the workgroup waits on memory once.
+    constexpr int Z = PRE;
+    T up[Z + 2][R + 1][3], Ep[Z + 2][R];
+    int mp[Z + 2][R + 1], mo[Z][R];
+    T fo[Z][R][3], wo[Z][R][3];
+#pragma unroll
+    for (int t = 0; t < Z + 2; ++t) load_plane(kc0 - 1 + t, up[t], mp[t]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) Ep[0][r] = T(0);
+#pragma unroll
+    for (int t = 1; t < Z + 2; ++t) load_layer(kc0 - 2 + t, Ep[t]);
+#pragma unroll
+    for (int o = 0; o < Z; ++o) load_out(kc0 + 1 + o, mo[o], fo[o], wo[o]);
+#pragma unroll
+    for (int t = 0; t < Z + 2; ++t) {
+      const int kk = kc0 - 1 + t, o = t >= 2 ? t - 2 : 0;
+      if (kk <= kc1) body(kk, up[t], mp[t], Ep[t], mo[o], fo[o], wo[o]);
+    }
+  } else {
+    load_plane(kc0 - 1, un, mn);
+    load_layer(kc0 - 2, En);
+    for (int kk = kc0 - 1; kk <= kc1; ++kk) {
+      // rotate the pipeline and request the next plane / layer
+#pragma unroll
+      for (int r = 0; r <= R; ++r) {
+        if (MASKIN) mc[r] = mn[r];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uc[r][c] = un[r][c];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) Ec[r] = En[r];
+      load_plane(kk + 1, un, mn);
+      load_layer(kk, En);
+      int mo[R];
+      T fo[R][3], wo[R][3];
+      load_out(kk, mo, fo, wo);
+      body(kk, uc, mc, Ec, mo, fo, wo);
+    }
   }
 }
 
-template <typename T, int R, int W, int MINW, bool MASKIN>
+template <typename T, int R, int W, int MINW, bool MASKIN, int PRE>
 void launch_stream_mode(int mode, dim3 grid, dim3 block, const Level& L, const HaarCoef<T>& q, const T* E,
                         const T* u, const T* f, const T* wd, T* y, int zchunk, int nchunks, const int* act,
                         hipStream_t s, const LaunchTimer& t) {
   if (mode == kApply)
-    launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks,
-                 act);
+    launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
+                 nchunks, act);
   else if (mode == kSmooth)
-    launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk, nchunks,
-                 act);
+    launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
+                 nchunks, act);
   else
-    launch_timed(k_stream<T, kResidual, R, W, MINW, MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
+    launch_timed(k_stream<T, kResidual, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
                  nchunks, act);
 }
 
@@ -444,10 +482,15 @@ void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>
   const int nchunks = (L.nzn + zchunk - 1) / zchunk;
   dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
   dim3 block(64 * W);
-  if (maskin)
-    launch_stream_mode<T, R, W, MINW, true>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+  // a z-chunk of one plane takes the preloaded form
+  if (maskin && zchunk == 1)
+    launch_stream_mode<T, R, W, MINW, true, 1>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+  else if (maskin)
+    launch_stream_mode<T, R, W, MINW, true, 0>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+  else if (zchunk == 1)
+    launch_stream_mode<T, R, W, MINW, false, 1>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
   else
-    launch_stream_mode<T, R, W, MINW, false>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+    launch_stream_mode<T, R, W, MINW, false, 0>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
 }
 
 }  // namespace
