@@ -255,113 +255,160 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
 //   B_K* = X,  B_IK = -A_IK D,  B_IJ = A_IJ - A_IK X_J,
 // which is nb scalar Gauss-Jordan steps applied at once.  A is read, B written.
 // The SPD coarse matrix (identity rows at fixed DOFs) needs no pivoting.
+//
+// Both kernels hold a 64x64 tile in registers, 16 elements per thread:
+// thread t = 16 ty + tx owns rows ty + 16 rr and columns tx + 16 cc
+// (rr, cc = 0..3), so that the 16 lanes of a row read consecutive words.
 
-__device__ inline double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// Inverse of the diagonal block by one workgroup of four waves: lane j holds
-// column j, wave w rows w, w+4, ..., w+60, all in registers.  Step k: the wave
-// owning row k publishes it through LDS (double-buffered: one barrier per
-// step); every wave reads the pivot column of its own rows from lane k.
-// Rows and columns beyond nb are padded with the identity.
+// Inverse of the diagonal block, written transposed (DT[j*64+i] = D_ij) for
+// the panel kernel.  Step k: the owners of row k and of column k publish them
+// through LDS (double-buffered: one barrier per step); then every element
+// takes a_ij <- a_ij - c_i r_j with r_j = a_kj / a_kk and c_i = a_ik, where the
+// pivot row and column are first cleared and c_k = -1, r_k = 1/a_kk, which
+// leaves 1/a_kk at (k,k), r_j on row k and -c_i/a_kk on column k.  Rows and
+// columns beyond nb are padded with the identity.
 __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
-                                                         double* __restrict__ D) {
-  static_assert(kGJBlock == 64 && kBlock == 256, "one lane per column, four waves");
-  __shared__ double prow[2][kGJBlock];
-  const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double v[16];
+                                                         double* __restrict__ DT) {
+  static_assert(kGJBlock == 64 && kBlock == 256, "16x16 threads of 4x4 micro-tiles");
+  __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double a[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = w + 4 * q;
-    v[q] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-  }
+  for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-  for (int kq = 0; kq < 16; ++kq) {
-#pragma unroll
-    for (int kr = 0; kr < 4; ++kr) {
-      const int k = 4 * kq + kr;
-      double* pr = prow[k & 1];
-      if (w == kr) pr[j] = v[kq];
-      __syncthreads();
-      const double p = 1.0 / pr[k];
-      const bool colk = j == k;
-      const double rj = colk ? p : pr[j] * p;  // new pivot row
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const double c = readlane_f64(v[q], k);  // old a_ik
-        v[q] = (colk ? 0.0 : v[q]) - c * rj;
-      }
-      if (w == kr) v[kq] = rj;
+    for (int cc = 0; cc < 4; ++cc) {
+      const int i = ty + 16 * rr, j = tx + 16 * cc;
+      a[rr][cc] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
     }
-  }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = w + 4 * q;
-    if (i < nb && j < nb) D[i * nb + j] = v[q];
-  }
+  for (int ks = 0; ks < 4; ++ks)  // slot of row / column k in the owners' registers
+#pragma unroll 2
+    for (int kb = 0; kb < 16; ++kb) {  // owner index (ty of row k, tx of column k)
+      const int k = 16 * ks + kb, par = kb & 1;
+      if (ty == kb) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) prow[par][tx + 16 * cc] = a[ks][cc];
+      }
+      if (tx == kb) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) pcol[par][ty + 16 * rr] = a[rr][ks];
+      }
+      __syncthreads();
+      const double p = 1.0 / prow[par][k];
+      double r[4], c[4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) r[cc] = prow[par][tx + 16 * cc] * p;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) c[rr] = pcol[par][ty + 16 * rr];
+      if (tx == kb) {
+        r[ks] = p;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) a[rr][ks] = 0.0;
+      }
+      if (ty == kb) {
+        c[ks] = -1.0;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) a[ks][cc] = 0.0;
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) a[rr][cc] = fma(-c[rr], r[cc], a[rr][cc]);
+    }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) DT[(tx + 16 * cc) * kGJBlock + ty + 16 * rr] = a[rr][cc];
 }
 
-// Row panel and update in one launch, grid (ceil(n / 64), ceil(n / 64)): the
-// block of tile (I, J) first forms its own 64 columns of the row panel,
-// X_J = D A_KJ (X_K = D) -- the ceil(n/64)-fold recomputation costs 64^3
-// multiply-adds per tile, far less than a launch -- then
-//   B_ij = X[i-k0][j]                                      (i in K)
-//   B_ij = (j in K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]    (otherwise).
-// Lane = column j, wave w rows 16w .. 16w+15 of the tile; the column operand
-// of each product is held in registers and the row operand is read from LDS
-// as a broadcast.
-__global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int k0, int nb, const double* __restrict__ A,
-                                                            const double* __restrict__ D,
+// Row panel and update in one launch, grid (ceil(n / 64), ceil(n / 64)) of
+// 64x64 tiles (J, I).  The block of tile (I, J) first forms its own 64 columns
+// of the row panel, X_J = D A_KJ (X_K = D, from A_KK taken as the identity) --
+// the ceil(n/64)-fold recomputation costs 64^3 multiply-adds per tile, less
+// than a launch -- then
+//   B_ij = X[i-k0][j]                                          (I = K)
+//   B_ij = (J = K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]        (otherwise).
+// Both products read their operands from LDS, D^T / A_IK^T on the left (rows
+// q, padded against bank conflicts) and A_KJ / X_J on the right.
+__global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int nb, const double* __restrict__ A,
+                                                            const double* __restrict__ DT,
                                                             double* __restrict__ B) {
-  __shared__ double sD[kGJBlock][kGJBlock];  // D (zero-padded), then X_J
-  __shared__ double sA[kGJBlock][kGJBlock];  // A_IK
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + lane, i0 = blockIdx.y * 64;
-  for (int t = threadIdx.x; t < kGJBlock * kGJBlock; t += kBlock) {
-    const int r = t >> 6, q = t & 63;
-    sD[r][q] = (r < nb && q < nb) ? D[r * nb + q] : 0.0;
-    sA[r][q] = (i0 + r < n && q < nb) ? A[(long long)(i0 + r) * n + k0 + q] : 0.0;
+  constexpr int P = kGJBlock + 1;
+  __shared__ double sL[kGJBlock][P];  // D^T, then A_IK^T
+  __shared__ double sR[kGJBlock][P];  // A_KJ (identity for J = K), then X_J
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int k0 = kb * kGJBlock, I = blockIdx.y, J = blockIdx.x;
+  const int i0 = I * kGJBlock, j0 = J * kGJBlock;
+  for (int e = threadIdx.x; e < kGJBlock * kGJBlock; e += kBlock) {
+    const int r = e >> 6, c = e & 63;
+    sL[r][c] = (r < nb && c < nb) ? DT[r * kGJBlock + c] : 0.0;
+    double v = 0.0;
+    if (r < nb && j0 + c < n) v = (J == kb) ? (r == c ? 1.0 : 0.0) : A[(long long)(k0 + r) * n + j0 + c];
+    sR[r][c] = v;
   }
-  double col[kGJBlock];  // column j of A_KJ, then of X_J
-#pragma unroll
-  for (int q = 0; q < kGJBlock; ++q) col[q] = (q < nb && j < n) ? A[(long long)(k0 + q) * n + j] : 0.0;
   __syncthreads();
-  const bool jK = j >= k0 && j < k0 + nb;
-  double x[16];
+  double x[4][4] = {};
+#pragma unroll 4
+  for (int q = 0; q < kGJBlock; ++q) {
+    double l[4], rr_[4];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    const int r = 16 * w + rr;
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < kGJBlock; ++q) acc += sD[r][q] * col[q];
-    x[rr] = jK ? sD[r][j - k0] : acc;
-  }
-  __syncthreads();  // D no longer needed: its buffer takes X_J
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) sD[16 * w + rr][lane] = x[rr];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kGJBlock; ++q) col[q] = sD[q][lane];
-  if (j >= n) return;
-#pragma unroll 2
-  for (int rr = 0; rr < 16; ++rr) {
-    const int r = 16 * w + rr, i = i0 + r;
-    if (i >= n) break;
-    double v;
-    if (i >= k0 && i < k0 + nb) {
-      v = sD[i - k0][lane];
-    } else {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < kGJBlock; ++q) acc += sA[r][q] * col[q];
-      v = (jK ? 0.0 : A[(long long)i * n + j]) - acc;
+    for (int m = 0; m < 4; ++m) {
+      l[m] = sL[q][ty + 16 * m];
+      rr_[m] = sR[q][tx + 16 * m];
     }
-    B[(long long)i * n + j] = v;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) x[rr][cc] = fma(l[rr], rr_[cc], x[rr][cc]);
   }
+  if (I == kb) {  // rows of the pivot block: B_K* = X
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
+        if (i < n && j < n) B[(long long)i * n + j] = x[rr][cc];
+      }
+    return;  // uniform per block
+  }
+  __syncthreads();  // every read of sL and sR is done
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) sR[ty + 16 * rr][tx + 16 * cc] = x[rr][cc];
+  for (int e = threadIdx.x; e < kGJBlock * kGJBlock; e += kBlock) {
+    const int r = e >> 6, c = e & 63;  // A[i0 + r][k0 + c] -> sL[c][r]
+    sL[c][r] = (i0 + r < n && c < nb) ? A[(long long)(i0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  double y[4][4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
+      y[rr][cc] = (J != kb && i < n && j < n) ? A[(long long)i * n + j] : 0.0;
+    }
+#pragma unroll 4
+  for (int q = 0; q < kGJBlock; ++q) {
+    double l[4], xr[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      l[m] = sL[q][ty + 16 * m];
+      xr[m] = sR[q][tx + 16 * m];
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) y[rr][cc] = fma(-l[rr], xr[cc], y[rr][cc]);
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
+      if (i < n && j < n) B[(long long)i * n + j] = y[rr][cc];
+    }
 }
 
 __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __restrict__ B) {
@@ -670,7 +717,7 @@ void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, 
     const int nb = (n - k0) < kGJBlock ? (n - k0) : kGJBlock;
     const int t = (n + 63) / 64;
     k_gj_block_inv<<<1, kBlock, 0, s>>>(n, k0, nb, buf[cur], D);
-    k_gj_panel_update<<<dim3(t, t), kBlock, 0, s>>>(n, k0, nb, buf[cur], D, buf[1 - cur]);
+    k_gj_panel_update<<<dim3(t, t), kBlock, 0, s>>>(n, k0 / kGJBlock, nb, buf[cur], D, buf[1 - cur]);
     cur = 1 - cur;
   }
   *result = buf[cur];
