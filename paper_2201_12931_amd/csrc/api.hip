@@ -138,7 +138,7 @@ size_t carve(hexmg_grid* g, char* base) {
   g->z = c.take<double>(N0 * R);
   g->p = c.take<double>(N0 * R);
   g->q = c.take<double>(N0 * R);
-  g->partials = c.take<double>(kReduceBlocks * R);
+  g->partials = c.take<double>((size_t)kMaxDotParts * R);  // >= kReduceBlocks
   g->partials2 = c.take<double>(kReduceBlocks * R);
   g->scalars = c.take<double>(kScalars * R);
   g->flags = c.take<int>(kReduceBlocks + 1);
@@ -190,7 +190,7 @@ int stream_zchunk(const Level& L, bool f32, int shape) {
 template <typename T>
 void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
                    const T* wd, T* y, int nrhs, hipStream_t s, bool maskin = false, const int* act = nullptr,
-                   const LaunchTimer& t = {}) {
+                   const LaunchTimer& t = {}, double* dotp = nullptr) {
   const bool f32 = sizeof(T) == 4;
   const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
   const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
@@ -206,7 +206,7 @@ void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int le
     launch_gather<T>(mode, L, Ke, E, u, f, wd, y, nrhs, act, s, t);
   } else {
     const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
-    launch_stream<T>(mode, maskin, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, nrhs, act, s, t);
+    launch_stream<T>(mode, maskin, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, nrhs, act, s, t, dotp);
   }
 }
 
@@ -266,7 +266,7 @@ int tune_kernels(hexmg_grid* g, hipStream_t s) {
 
 template <typename T>
 void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T* wd, T* y, int nrhs,
-            hipStream_t s, bool maskin = false, const int* act = nullptr) {
+            hipStream_t s, bool maskin = false, const int* act = nullptr, double* dotp = nullptr) {
   const bool f32 = sizeof(T) == 4;
   hipEvent_t a = nullptr, b = nullptr;
   const bool prof = g->profile && level == 0;
@@ -277,8 +277,7 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
   LaunchTimer t;
   if (a && b) t = LaunchTimer{a, b};
   launch_choice<T>(g, (f32 ? g->choice32[level] : g->choice64[level])[mode], mode, level, u, f, wd, y, nrhs, s, maskin,
-                   act,
-                   t);
+                   act, t, dotp);
   if (a && b) g->recs.push_back({family_of(mode, f32), a, b, g->prof_tag});
 }
 
@@ -817,8 +816,11 @@ struct PcgRun {
   long long N() const { return 3ll * g->lv[0].nn; }
   double* slot(int k) const { return g->host_ring + (size_t)(k % 3) * kScalars * g->desc.max_nrhs; }
   hipEvent_t wait_event() const { return ev[(phase == kFinish ? final_slot : target) % 3]; }
-  int post(int k) {
-    HIP_TRY(hipMemcpyAsync(slot(k), g->scalars, (size_t)kScalars * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  // the scalars of slot k reach the host by a copy (final phase) or, for a CG
+  // iteration, written by the iteration's last kernel itself
+  int post(int k, bool copy) {
+    if (copy)
+      HIP_TRY(hipMemcpyAsync(slot(k), g->scalars, (size_t)kScalars * nb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ev[k % 3], s));
     return 0;
   }
@@ -826,12 +828,23 @@ struct PcgRun {
   int issue_iteration(int k) {
     double* sc = g->scalars;
     g->prof_tag = k;
-    gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active);
-    launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
-    launch_update_xr(N(), g->partials, sc, g->active, g->p, g->q, u, g->r, g->partials2, (k - 1) & 1, nb, s);
-    launch_rr_check(g->partials2, sc, g->active, nb, s);
+    // q = A p, with p . q formed inside the streaming kernel when it is the
+    // level-0 choice and its workgroups are few enough; else a separate pass
+    const hexmg_grid::Choice& ch = g->choice64[0][kApply];
+    int npq = 0;
+    if (ch.kernel == HEXMG_KERNEL_STREAM) {
+      const int nbk = stream_blocks(g->lv[0], false, ch.shape, ch.zchunk);
+      if (nbk <= kMaxDotParts) npq = nbk;
+    }
+    gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active, npq ? g->partials : nullptr);
+    if (!npq) {
+      launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
+      npq = kReduceBlocks;
+    }
+    launch_update_xr(N(), g->partials, npq, sc, g->active, g->p, g->q, u, g->r, g->partials2, (k - 1) & 1, nb, s);
+    launch_rr_check(g->partials2, sc, g->active, slot(k), nb, s);
     issued = k;
-    return post(k);
+    return post(k, false);
   }
   // z = M^{-1} r, beta, p = z + beta p (after iteration k), then iteration k+1
   int issue_next() {
@@ -873,7 +886,7 @@ struct PcgRun {
     dot(g, N(), f, u, sc + kTmp2, nb, s);
     final_slot = read + 2;  // a slot no result in flight is written to
     phase = kFinish;
-    return post(final_slot);
+    return post(final_slot, true);
   }
   int advance() {
     if (phase == kIterate) {

@@ -61,10 +61,17 @@ void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s
     kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
 }
 
+// dotp (K u only, may be null): one partial of u . (A u) per workgroup, per
+// right-hand side stream_blocks(...) of them, right-hand side r at
+// dotp + r * stream_blocks(...).
 template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
-                   const LaunchTimer& t = {});
+                   const LaunchTimer& t = {}, double* dotp = nullptr);
+// workgroups of one right-hand side's launch of the streaming kernel
+int stream_blocks(const Level& L, bool f32, int shape, int zchunk);
+// most partials a fused dot product may leave per right-hand side
+constexpr int kMaxDotParts = 8192;
 
 constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
 constexpr int kOcProbes = 32;       // Lagrange multipliers evaluated per OC pass
@@ -119,11 +126,15 @@ void launch_reduce_final(const double* partials, double* out, int stride, int nr
 // CG steps with the scalars computed on the device (see ScalarSlot):
 // init: active = (ff > 0), its = 0, stop = rtol^2 ff (rtol2 <= 0: never)
 void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s);
-// alpha = rz[parity] / (sum of pq partials); x += alpha p; r -= alpha q; rr partials
-void launch_update_xr(long long n, const double* pq_partials, double* sc, const int* active, const double* p,
-                      const double* q, double* x, double* r, double* rr_partials, int parity, int nrhs, hipStream_t s);
-// rr = sum of partials; its += 1; convergence / breakdown clears active
-void launch_rr_check(const double* rr_partials, double* sc, int* active, int nrhs, hipStream_t s);
+// alpha = rz[parity] / (sum of the npq pq partials of a right-hand side, which
+// are also npq apart); x += alpha p; r -= alpha q; rr partials
+void launch_update_xr(long long n, const double* pq_partials, int npq, double* sc, const int* active,
+                      const double* p, const double* q, double* x, double* r, double* rr_partials, int parity,
+                      int nrhs, hipStream_t s);
+// rr = sum of partials; its += 1; convergence / breakdown clears active; the
+// scalars of every right-hand side are written to host_slot (pinned host memory)
+void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
+                     hipStream_t s);
 // rz_new = sum of rz partials; beta = rz_new / rz[parity]; p = z + beta p; rz[1-parity] = rz_new
 void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const double* z,
                      double* p, int parity, int nrhs, hipStream_t s);

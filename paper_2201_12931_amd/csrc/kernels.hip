@@ -468,9 +468,11 @@ __global__ void k_pcg_init(double rtol2, double* __restrict__ sc, int* __restric
   s[kPq] = 0.0;
 }
 
-// grid (kReduceBlocks, nrhs).  Every block sums the same pq partials in the
-// same order, so all blocks use the identical alpha.
-__global__ void k_update_xr(long long n, const double* __restrict__ pq_partials, double* __restrict__ sc,
+// grid (kReduceBlocks, nrhs).  alpha = rz / pq with pq the sum of npq partials
+// per right-hand side; every block sums the same partials in the same order,
+// so all blocks use the identical alpha.  x += alpha p, r -= alpha q, and the
+// partials of ||r||^2.
+__global__ void k_update_xr(long long n, const double* __restrict__ pq_partials, int npq, double* __restrict__ sc,
                             const int* __restrict__ active, const double* __restrict__ p,
                             const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
                             double* __restrict__ rr_partials, int parity) {
@@ -480,7 +482,9 @@ __global__ void k_update_xr(long long n, const double* __restrict__ pq_partials,
     if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
     return;
   }
-  const double pq = sum_partials(pq_partials + (long long)kReduceBlocks * rhs);
+  double pqs = 0.0;
+  for (int i = threadIdx.x; i < npq; i += kBlock) pqs += pq_partials[(long long)npq * rhs + i];
+  const double pq = block_sum_all(pqs);
   double* s = sc + kScalars * rhs;
   const double alpha = s[kRz0 + parity] / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -507,25 +511,39 @@ __global__ void k_update_xr(long long n, const double* __restrict__ pq_partials,
   if (threadIdx.x == 0) rr_partials[blockIdx.x] = acc;
 }
 
-// one block per right-hand side: ||r||^2, iteration count, convergence test
+// One block per right-hand side: ||r||^2, iteration count, convergence and
+// breakdown test; then the scalars are written to host_slot (pinned host
+// memory, kScalars per right-hand side), where the host reads them without a
+// copy.  A right-hand side that has stopped only republishes its scalars.
 __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __restrict__ sc,
-                           int* __restrict__ active) {
+                           int* __restrict__ active, double* __restrict__ host_slot) {
   const int rhs = blockIdx.x;
   const double rr = sum_partials(rr_partials + (long long)kReduceBlocks * rhs);
-  if (threadIdx.x != 0 || !active[rhs]) return;
+  if (threadIdx.x != 0) return;
   double* s = sc + kScalars * rhs;
-  s[kRr] = rr;
-  s[kIts] += 1.0;
-  const bool finite = rr == rr && rr < 1e308;
-  if (!(s[kPq] > 0.0 && s[kPq] < 1e308) || !finite) {
-    active[rhs] = 0;
-    s[kActive] = 0.0;
-    s[kStatus] = -5.0;
-  } else if (rr <= s[kStop]) {
-    active[rhs] = 0;
-    s[kActive] = 0.0;
-    s[kStatus] = 0.0;
+  double v[kScalars];
+#pragma unroll
+  for (int j = 0; j < kScalars; ++j) v[j] = s[j];
+  if (active[rhs]) {
+    v[kRr] = rr;
+    v[kIts] += 1.0;
+    const bool finite = rr == rr && rr < 1e308;
+    int act = 1;
+    if (!(v[kPq] > 0.0 && v[kPq] < 1e308) || !finite) {
+      act = 0;
+      v[kStatus] = -5.0;
+    } else if (rr <= v[kStop]) {
+      act = 0;
+      v[kStatus] = 0.0;
+    }
+    v[kActive] = act;
+    active[rhs] = act;
+#pragma unroll
+    for (int j = 0; j < kScalars; ++j) s[j] = v[j];
   }
+#pragma unroll
+  for (int j = 0; j < kScalars; ++j) host_slot[kScalars * rhs + j] = v[j];
+  __threadfence_system();
 }
 
 // grid (kReduceBlocks, nrhs): beta from the rz partials, p = z + beta p
@@ -743,13 +761,16 @@ void launch_reduce_final(const double* partials, double* out, int stride, int nr
 void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s) {
   k_pcg_init<<<1, ((nrhs + 63) / 64) * 64, 0, s>>>(rtol2, sc, active, nrhs);
 }
-void launch_update_xr(long long n, const double* pq_partials, double* sc, const int* active, const double* p,
-                      const double* q, double* x, double* r, double* rr_partials, int parity, int nrhs, hipStream_t s) {
-  k_update_xr<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, sc, active, p, q, x, r, rr_partials,
+void launch_update_xr(long long n, const double* pq_partials, int npq, double* sc, const int* active,
+                      const double* p, const double* q, double* x, double* r, double* rr_partials, int parity,
+                      int nrhs, hipStream_t s) {
+  k_update_xr<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, npq, sc, active, p, q, x, r, rr_partials,
                                                            parity);
 }
-void launch_rr_check(const double* rr_partials, double* sc, int* active, int nrhs, hipStream_t s) {
-  k_rr_check<<<nrhs, kBlock, 0, s>>>(rr_partials, sc, active);
+
+void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
+                     hipStream_t s) {
+  k_rr_check<<<nrhs, kBlock, 0, s>>>(rr_partials, sc, active, host_slot);
 }
 void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const double* z,
                      double* p, int parity, int nrhs, hipStream_t s) {

@@ -164,7 +164,8 @@ template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
-                                                      int nchunks, const int* __restrict__ act) {
+                                                      int nchunks, const int* __restrict__ act,
+                                                      double* __restrict__ dotp) {
   if (act && !act[blockIdx.z / nchunks]) return;  // right-hand side already converged (uniform per block)
   {  // blockIdx.z = z-chunk + nchunks * right-hand side; vectors are [nrhs][3 nn]
     const long long off = 3ll * L.nn * (blockIdx.z / nchunks);
@@ -250,6 +251,9 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       }
     }
   }
+  // With dotp (K u only): this thread's share of u . (A u) over its outputs.
+  double dot = 0.0;
+
   // Inputs of the epilogue of iteration kk (output plane kk-1): support bits,
   // f and omega/D.
   auto load_out = [&](int kk, int (&mo)[R], T (&fo)[R][3], T (&wo)[R][3]) {
@@ -306,9 +310,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T Au = select_bit(mo[r], c, uo[r][c], Ku[c]);
-        if (MODE == kApply)
+        if (MODE == kApply) {
           v[c] = Au;
-        else if (MODE == kSmooth)
+          if (dotp && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;
+        } else if (MODE == kSmooth)
           v[c] = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
         else
           v[c] = fo[r][c] - Au;
@@ -457,40 +462,59 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       body(kk, uc, mc, Ec, mo, fo, wo);
     }
   }
+  if (MODE == kApply && dotp) {  // one partial per workgroup, in a fixed order
+    __shared__ double wsum[W];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
+    if (lane == 0) wsum[w] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) t += wsum[k];
+      const int parts = gridDim.x * gridDim.y * nchunks;
+      const int rhs = blockIdx.z / nchunks;
+      dotp[(long long)parts * rhs + blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * (blockIdx.z % nchunks))] = t;
+    }
+  }
 }
 
 template <typename T, int R, int W, int MINW, bool MASKIN, int PRE>
 void launch_stream_mode(int mode, dim3 grid, dim3 block, const Level& L, const HaarCoef<T>& q, const T* E,
                         const T* u, const T* f, const T* wd, T* y, int zchunk, int nchunks, const int* act,
-                        hipStream_t s, const LaunchTimer& t) {
+                        double* dotp, hipStream_t s, const LaunchTimer& t) {
   if (mode == kApply)
     launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
-                 nchunks, act);
+                 nchunks, act, dotp);
   else if (mode == kSmooth)
     launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
-                 nchunks, act);
+                 nchunks, act, dotp);
   else
     launch_timed(k_stream<T, kResidual, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
-                 nchunks, act);
+                 nchunks, act, dotp);
 }
 
 template <typename T, int R, int W, int MINW>
 void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
-                        const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
-                        const LaunchTimer& t) {
+                        const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, double* dotp,
+                        hipStream_t s, const LaunchTimer& t) {
   constexpr int kOutRows = W * R - 1;
   const int nchunks = (L.nzn + zchunk - 1) / zchunk;
   dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
   dim3 block(64 * W);
   // a z-chunk of one plane takes the preloaded form
   if (maskin && zchunk == 1)
-    launch_stream_mode<T, R, W, MINW, true, 1>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+    launch_stream_mode<T, R, W, MINW, true, 1>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, dotp,
+                                               s, t);
   else if (maskin)
-    launch_stream_mode<T, R, W, MINW, true, 0>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+    launch_stream_mode<T, R, W, MINW, true, 0>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, dotp,
+                                               s, t);
   else if (zchunk == 1)
-    launch_stream_mode<T, R, W, MINW, false, 1>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+    launch_stream_mode<T, R, W, MINW, false, 1>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, dotp,
+                                                s, t);
   else
-    launch_stream_mode<T, R, W, MINW, false, 0>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, s, t);
+    launch_stream_mode<T, R, W, MINW, false, 0>(mode, grid, block, L, q, E, u, f, wd, y, zchunk, nchunks, act, dotp,
+                                                s, t);
 }
 
 }  // namespace
@@ -510,30 +534,35 @@ int stream_out_rows(bool f32, int shape) {
 template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
-                   const LaunchTimer& t) {
+                   const LaunchTimer& t, double* dotp) {
   if constexpr (sizeof(T) == 4) {
     if (shape == 0)
-      launch_stream_impl<T, 2, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 2, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
     else if (shape == 1)
-      launch_stream_impl<T, 3, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 3, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
     else if (shape == 2)
-      launch_stream_impl<T, 4, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 4, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
     else if (shape == 3)
-      launch_stream_impl<T, 3, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 3, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
     else
-      launch_stream_impl<T, 2, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 2, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
   } else {
     if (shape == 0)
-      launch_stream_impl<T, 1, 8, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 1, 8, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
     else
-      launch_stream_impl<T, 2, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, s, t);
+      launch_stream_impl<T, 2, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
   }
 }
 template void launch_stream<float>(int, bool, int, const Level&, const HaarCoef<float>&, const float*,
                                    const float*, const float*, const float*, float*, int, int, const int*,
-                                   hipStream_t, const LaunchTimer&);
+                                   hipStream_t, const LaunchTimer&, double*);
 template void launch_stream<double>(int, bool, int, const Level&, const HaarCoef<double>&, const double*,
                                     const double*, const double*, const double*, double*, int, int, const int*,
-                                    hipStream_t, const LaunchTimer&);
+                                    hipStream_t, const LaunchTimer&, double*);
+
+int stream_blocks(const Level& L, bool f32, int shape, int zchunk) {
+  const int rows = stream_out_rows(f32, shape);
+  return ((L.nxn + 61) / 62) * ((L.nyn + rows - 1) / rows) * ((L.nzn + zchunk - 1) / zchunk);
+}
 
 }  // namespace hexmg
