@@ -339,12 +339,23 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int k0 = kb * kGJBlock, I = blockIdx.y, J = blockIdx.x;
   const int i0 = I * kGJBlock, j0 = J * kGJBlock;
-  for (int e = threadIdx.x; e < kGJBlock * kGJBlock; e += kBlock) {
-    const int r = e >> 6, c = e & 63;
-    sL[r][c] = (r < nb && c < nb) ? DT[r * kGJBlock + c] : 0.0;
-    double v = 0.0;
-    if (r < nb && j0 + c < n) v = (J == kb) ? (r == c ? 1.0 : 0.0) : A[(long long)(k0 + r) * n + j0 + c];
-    sR[r][c] = v;
+  // every global load of a stage is issued before the first LDS store
+  constexpr int kPer = kGJBlock * kGJBlock / kBlock;  // 16 elements per thread
+  {
+    double vl[kPer], vr[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + kBlock * m, r = e >> 6, c = e & 63;
+      vl[m] = (r < nb && c < nb) ? DT[r * kGJBlock + c] : 0.0;
+      vr[m] = (r < nb && j0 + c < n) ? ((J == kb) ? (r == c ? 1.0 : 0.0) : A[(long long)(k0 + r) * n + j0 + c])
+                                     : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + kBlock * m, r = e >> 6, c = e & 63;
+      sL[r][c] = vl[m];
+      sR[r][c] = vr[m];
+    }
   }
   __syncthreads();
   double x[4][4] = {};
@@ -376,19 +387,28 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
   for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) sR[ty + 16 * rr][tx + 16 * cc] = x[rr][cc];
-  for (int e = threadIdx.x; e < kGJBlock * kGJBlock; e += kBlock) {
-    const int r = e >> 6, c = e & 63;  // A[i0 + r][k0 + c] -> sL[c][r]
-    sL[c][r] = (i0 + r < n && c < nb) ? A[(long long)(i0 + r) * n + k0 + c] : 0.0;
+  double y[4][4];
+  {
+    double va[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + kBlock * m, r = e >> 6, c = e & 63;  // A[i0 + r][k0 + c] -> sL[c][r]
+      va[m] = (i0 + r < n && c < nb) ? A[(long long)(i0 + r) * n + k0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
+        y[rr][cc] = (J != kb && i < n && j < n) ? A[(long long)i * n + j] : 0.0;
+      }
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + kBlock * m, r = e >> 6, c = e & 63;
+      sL[c][r] = va[m];
+    }
   }
   __syncthreads();
-  double y[4][4];
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
-      y[rr][cc] = (J != kb && i < n && j < n) ? A[(long long)i * n + j] : 0.0;
-    }
 #pragma unroll 4
   for (int q = 0; q < kGJBlock; ++q) {
     double l[4], xr[4];
@@ -437,6 +457,7 @@ __global__ void k_dot_partial(long long n, const double* __restrict__ x, const d
     return;
   }
   double s = 0.0;
+#pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
     s += x[i] * y[i];
   s = block_sum(s);
@@ -501,6 +522,7 @@ __global__ void k_update_xr(long long n, const double* __restrict__ pq_partials,
   x += off;
   r += off;
   double acc = 0.0;
+#pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
@@ -562,6 +584,7 @@ __global__ void k_update_p(long long n, const double* __restrict__ rz_partials, 
   const long long off = n * rhs;
   z += off;
   p += off;
+#pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
     p[i] = z[i] + beta * p[i];
 }
@@ -577,6 +600,7 @@ __global__ void k_to64_dot(long long n, const float* __restrict__ u32, const dou
   }
   const long long off = n * rhs;
   double acc = 0.0;
+#pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     const double zi = (double)u32[off + i];
     z[off + i] = zi;

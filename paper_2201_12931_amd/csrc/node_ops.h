@@ -98,25 +98,31 @@ __device__ inline void restrict_node(const Level& F, const Level& C, const T* __
                                      const T* __restrict__ wdc, T* __restrict__ tc, int m) {
   int I, J, K;
   node_coords(C, m, I, J, K);
-  T s0 = 0, s1 = 0, s2 = 0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int kk = 2 * K + dz;
-    if (kk < 0 || kk >= F.nzn) continue;
-    const T wz = dz ? T(0.5) : T(1);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int jj = 2 * J + dy;
-      if (jj < 0 || jj >= F.nyn) continue;
-      const T wy = dy ? T(0.5) : T(1);
+  // all 27 neighbours are requested at once: out-of-range ones read a clamped
+  // in-range node with weight 0
+  T v[27][3], w[27];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int ii = 2 * I + dx;
-        if (ii < 0 || ii >= F.nxn) continue;
-        const T w = (dx ? T(0.5) : T(1)) * wy * wz;
-        const T* rn = r + 3ll * (ii + F.nxn * (jj + F.nyn * kk));
-        s0 += w * rn[0];
-        s1 += w * rn[1];
-        s2 += w * rn[2];
+        const int q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+        const int ii = 2 * I + dx, jj = 2 * J + dy, kk = 2 * K + dz;
+        const bool in = ii >= 0 && ii < F.nxn && jj >= 0 && jj < F.nyn && kk >= 0 && kk < F.nzn;
+        const int ic = min(max(ii, 0), F.nxn - 1), jc = min(max(jj, 0), F.nyn - 1), kc = min(max(kk, 0), F.nzn - 1);
+        const T* rn = r + 3ll * (ic + F.nxn * (jc + F.nyn * kc));
+        w[q] = in ? (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1)) : T(0);
+        v[q][0] = rn[0];
+        v[q][1] = rn[1];
+        v[q][2] = rn[2];
       }
-    }
+  T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    s0 += w[q] * v[q][0];
+    s1 += w[q] * v[q][1];
+    s2 += w[q] * v[q][2];
   }
   const int mk = C.mask[m];
   const T f0 = (mk & 1) ? T(0) : s0, f1 = (mk & 2) ? T(0) : s1, f2 = (mk & 4) ? T(0) : s2;
@@ -130,24 +136,41 @@ __device__ inline void restrict_node(const Level& F, const Level& C, const T* __
   }
 }
 
-// Fine correction at fine node n: u += M P e_c (trilinear interpolation).
+// Fine correction at fine node n: u += M P e_c (trilinear interpolation).  The
+// eight surrounding coarse nodes are requested at once (weight 0, index
+// clamped, where an axis coordinate is even and only one coarse node counts).
 template <typename T>
 __device__ inline void prolong_node(const Level& F, const Level& C, const T* __restrict__ ec, T* __restrict__ u,
                                     int n) {
   int i, j, k;
   node_coords(F, n, i, j, k);
-  T s0 = 0, s1 = 0, s2 = 0;
   const int oz = k & 1, oy = j & 1, ox = i & 1;
-  const T wz = oz ? T(0.5) : T(1), wy = oy ? T(0.5) : T(1), wx = ox ? T(0.5) : T(1);
-  for (int cz = 0; cz <= oz; ++cz)
-    for (int cy = 0; cy <= oy; ++cy)
-      for (int cx = 0; cx <= ox; ++cx) {
-        const int m = ((i >> 1) + cx) + C.nxn * (((j >> 1) + cy) + C.nyn * ((k >> 1) + cz));
-        const T w = wx * wy * wz;
-        s0 += w * ec[3ll * m];
-        s1 += w * ec[3ll * m + 1];
-        s2 += w * ec[3ll * m + 2];
+  T v[8][3], w[8];
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const int q = cx + 2 * cy + 4 * cz;
+        const T wx = ox ? T(0.5) : (cx ? T(0) : T(1));
+        const T wy = oy ? T(0.5) : (cy ? T(0) : T(1));
+        const T wz = oz ? T(0.5) : (cz ? T(0) : T(1));
+        const int I = min((i >> 1) + cx, C.nxn - 1), J = min((j >> 1) + cy, C.nyn - 1),
+                  K = min((k >> 1) + cz, C.nzn - 1);
+        const T* e = ec + 3ll * (I + C.nxn * (J + C.nyn * K));
+        w[q] = wx * wy * wz;
+        v[q][0] = e[0];
+        v[q][1] = e[1];
+        v[q][2] = e[2];
       }
+  T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    s0 += w[q] * v[q][0];
+    s1 += w[q] * v[q][1];
+    s2 += w[q] * v[q][2];
+  }
   const int mk = F.mask[n];
   if (!(mk & 1)) u[3ll * n] += s0;
   if (!(mk & 2)) u[3ll * n + 1] += s1;
