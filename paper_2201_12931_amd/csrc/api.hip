@@ -130,7 +130,7 @@ size_t carve(hexmg_grid* g, char* base) {
   g->nc = (int)nc;
   g->Abuf[0] = c.take<double>(nc * nc);
   g->Abuf[1] = c.take<double>(nc * nc);
-  g->gjD = c.take<double>(kGJBlock * kGJBlock);
+  g->gjD = c.take<double>(2 * kGJBlock * kGJBlock);
   g->Ke64 = c.take<double>(576);
   g->Ke32 = c.take<float>(576);
   const size_t N0 = 3ull * g->lv[0].nn;
@@ -233,10 +233,13 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
   for (int mode = 0; mode < 3; ++mode) {
     float best_stream = 1e30f, best_gather = 1e30f;
     hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4, 0};
+    // small levels run for a few microseconds per launch: more repetitions
+    // keep the timer's noise below the differences between candidates
+    const int reps = L.ne < 100000 ? 12 : 3;
     for (const auto& c : cand) {
       launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
       HIP_TRY(hipEventRecord(e0, s));
-      for (int rep = 0; rep < 3; ++rep) launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
+      for (int rep = 0; rep < reps; ++rep) launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;

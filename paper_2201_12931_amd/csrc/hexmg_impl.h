@@ -149,9 +149,9 @@ void launch_fill(long long n, double v, double* x, hipStream_t s);
 void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
                         double coef, double pm1, int accumulate, double* dc, hipStream_t s);
 void launch_symmetrize(int n, const double* A, double* B, hipStream_t s);
-// In-place-style blocked Gauss-Jordan inverse of the n x n SPD matrix in A
-// (B is the ping-pong buffer, D kGJBlock^2 and X kGJBlock*n scratch); *result
-// receives the buffer holding the inverse.
+// Blocked Gauss-Jordan inverse of the n x n SPD matrix in A (B is the
+// ping-pong buffer, D 2 kGJBlock^2 scratch for the pivot-block inverses);
+// *result receives the buffer holding the inverse.  1 + ceil(n/64) launches.
 void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, hipStream_t s);
 
 // Density filter and optimality criteria (topopt.hip)

@@ -267,19 +267,12 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
 // pivot row and column are first cleared and c_k = -1, r_k = 1/a_kk, which
 // leaves 1/a_kk at (k,k), r_j on row k and -c_i/a_kk on column k.  Rows and
 // columns beyond nb are padded with the identity.
-__global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
-                                                         double* __restrict__ DT) {
-  static_assert(kGJBlock == 64 && kBlock == 256, "16x16 threads of 4x4 micro-tiles");
-  __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
+// In-place inverse of the 64x64 tile held in a (padded with the identity
+// beyond its nb x nb block), by the block's 256 threads; written transposed to
+// DT (DT[j*64+i] = D_ij).  prow / pcol: the block's LDS exchange buffers.
+__device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][kGJBlock], double (&pcol)[2][kGJBlock],
+                                     double* __restrict__ DT) {
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double a[4][4];
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int i = ty + 16 * rr, j = tx + 16 * cc;
-      a[rr][cc] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-    }
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks)  // slot of row / column k in the owners' registers
 #pragma unroll 2
@@ -294,21 +287,25 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
         for (int rr = 0; rr < 4; ++rr) pcol[par][ty + 16 * rr] = a[rr][ks];
       }
       __syncthreads();
-      const double p = 1.0 / prow[par][k];
+      // 1/a_kk: hardware reciprocal and two Newton steps (each squares the
+      // relative error), shorter than the IEEE division sequence on this
+      // latency-bound chain
+      const double akk = prow[par][k];
+      double p = __builtin_amdgcn_rcp(akk);
+      p = fma(p, fma(-akk, p, 1.0), p);
+      p = fma(p, fma(-akk, p, 1.0), p);
       double r[4], c[4];
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) r[cc] = prow[par][tx + 16 * cc] * p;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) c[rr] = pcol[par][ty + 16 * rr];
-      if (tx == kb) {
-        r[ks] = p;
+      const bool colk = tx == kb, rowk = ty == kb;
+      r[ks] = colk ? p : r[ks];
+      c[ks] = rowk ? -1.0 : c[ks];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) a[rr][ks] = 0.0;
-      }
-      if (ty == kb) {
-        c[ks] = -1.0;
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) a[ks][cc] = 0.0;
+      for (int m = 0; m < 4; ++m) {
+        a[m][ks] = colk ? 0.0 : a[m][ks];
+        a[ks][m] = rowk ? 0.0 : a[ks][m];
       }
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
@@ -321,6 +318,24 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
     for (int cc = 0; cc < 4; ++cc) DT[(tx + 16 * cc) * kGJBlock + ty + 16 * rr] = a[rr][cc];
 }
 
+// Inverse of the first diagonal block (later ones are formed by the panel
+// update that produces them).
+__global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
+                                                         double* __restrict__ DT) {
+  static_assert(kGJBlock == 64 && kBlock == 256, "16x16 threads of 4x4 micro-tiles");
+  __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double a[4][4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int i = ty + 16 * rr, j = tx + 16 * cc;
+      a[rr][cc] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+    }
+  block_inverse(a, prow, pcol, DT);
+}
+
 // Row panel and update in one launch, grid (ceil(n / 64), ceil(n / 64)) of
 // 64x64 tiles (J, I).  The block of tile (I, J) first forms its own 64 columns
 // of the row panel, X_J = D A_KJ (X_K = D, from A_KK taken as the identity) --
@@ -329,10 +344,12 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
 //   B_ij = X[i-k0][j]                                          (I = K)
 //   B_ij = (J = K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]        (otherwise).
 // Both products read their operands from LDS, D^T / A_IK^T on the left (rows
-// q, padded against bank conflicts) and A_KJ / X_J on the right.
+// q, padded against bank conflicts) and A_KJ / X_J on the right.  The block of
+// the next diagonal tile (kb+1, kb+1) then inverts its result in place and
+// writes it transposed to DTnext, so the next step needs no separate launch.
 __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int nb, const double* __restrict__ A,
                                                             const double* __restrict__ DT,
-                                                            double* __restrict__ B) {
+                                                            double* __restrict__ B, double* __restrict__ DTnext) {
   constexpr int P = kGJBlock + 1;
   __shared__ double sL[kGJBlock][P];  // D^T, then A_IK^T
   __shared__ double sR[kGJBlock][P];  // A_KJ (identity for J = K), then X_J
@@ -429,6 +446,18 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
       const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
       if (i < n && j < n) B[(long long)i * n + j] = y[rr][cc];
     }
+  if (I == kb + 1 && J == kb + 1) {  // uniform per block
+    const int nbn = min(n - i0, kGJBlock);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int i = ty + 16 * rr, j = tx + 16 * cc;
+        if (!(i < nbn && j < nbn)) y[rr][cc] = (i == j) ? 1.0 : 0.0;
+      }
+    __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
+    block_inverse(y, prow, pcol, DTnext);
+  }
 }
 
 __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __restrict__ B) {
@@ -754,12 +783,14 @@ void launch_coarse_assemble(const Level& C, const double* Ke, const double* E, d
 }
 void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, hipStream_t s) {
   double* buf[2] = {A, B};
+  double* dt[2] = {D, D + kGJBlock * kGJBlock};  // pivot inverses, alternating by step
   int cur = 0;
-  for (int k0 = 0; k0 < n; k0 += kGJBlock) {
+  const int t = (n + 63) / 64;
+  k_gj_block_inv<<<1, kBlock, 0, s>>>(n, 0, n < kGJBlock ? n : kGJBlock, A, dt[0]);
+  for (int kb = 0; kb < t; ++kb) {
+    const int k0 = kb * kGJBlock;
     const int nb = (n - k0) < kGJBlock ? (n - k0) : kGJBlock;
-    const int t = (n + 63) / 64;
-    k_gj_block_inv<<<1, kBlock, 0, s>>>(n, k0, nb, buf[cur], D);
-    k_gj_panel_update<<<dim3(t, t), kBlock, 0, s>>>(n, k0 / kGJBlock, nb, buf[cur], D, buf[1 - cur]);
+    k_gj_panel_update<<<dim3(t, t), kBlock, 0, s>>>(n, kb, nb, buf[cur], dt[kb & 1], buf[1 - cur], dt[(kb + 1) & 1]);
     cur = 1 - cur;
   }
   *result = buf[cur];
