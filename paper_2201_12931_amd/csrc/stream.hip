@@ -283,11 +283,17 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     const bool out_plane = kk - 1 >= kc0 && kk - 1 < kc1;
     const Rsrc ry = plane_rsrc(yg + 3 * plane * (out_plane ? kk - 1 : 0), out_plane ? vbytes : 0);
     // u of plane kk (fixed DOFs masked when the input may be non-zero there)
+    // (a wave-uniform test skips the selects for rows without fixed DOFs)
     T ue[R + 1][3];
 #pragma unroll
-    for (int r = 0; r <= R; ++r)
+    for (int r = 0; r <= R; ++r) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ue[r][c] = MASKIN ? select_bit(mc[r], c, T(0), uc[r][c]) : uc[r][c];
+      for (int c = 0; c < 3; ++c) ue[r][c] = uc[r][c];
+      if (MASKIN && __any(mc[r] != 0)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ue[r][c] = select_bit(mc[r], c, T(0), uc[r][c]);
+      }
+    }
     // x-edge modes of row r: s = u(i+1) + u(i), d = u(i+1) - u(i).  The
     // difference is formed as -(u(i) - u(i+1)) so that both shifts fold into
     // their additions (lane 63 reads 0 from its missing neighbour).
