@@ -61,9 +61,9 @@ void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s
     kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
 }
 
-// dotp (K u only, may be null): one partial of u . (A u) per workgroup, per
-// right-hand side stream_blocks(...) of them, right-hand side r at
-// dotp + r * stream_blocks(...).
+// dotp (K u without input masking only, may be null): one partial of
+// u . (A u) per workgroup, per right-hand side stream_blocks(...) of them,
+// right-hand side r at dotp + r * stream_blocks(...).
 template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,

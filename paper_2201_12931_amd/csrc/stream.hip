@@ -160,7 +160,8 @@ __device__ inline double select_bit(int m, int c, double a, double b) { return (
 // entry) and is masked on load; without it (every vector inside the solver is
 // zero there) only the outputs use the support bits.
 // PRE > 0: zchunk is PRE and all inputs of the workgroup are requested up front.
-template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE>
+// DOT (K u only): also one partial of u . (A u) per workgroup into dotp.
+template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
         const T Au = select_bit(mo[r], c, uo[r][c], Ku[c]);
         if (MODE == kApply) {
           v[c] = Au;
-          if (dotp && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;
+          if (DOT && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;
         } else if (MODE == kSmooth)
           v[c] = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
         else
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       body(kk, uc, mc, Ec, mo, fo, wo);
     }
   }
-  if (MODE == kApply && dotp) {  // one partial per workgroup, in a fixed order
+  if (DOT) {  // one partial per workgroup, in a fixed order
     __shared__ double wsum[W];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
@@ -489,15 +490,18 @@ template <typename T, int R, int W, int MINW, bool MASKIN, int PRE>
 void launch_stream_mode(int mode, dim3 grid, dim3 block, const Level& L, const HaarCoef<T>& q, const T* E,
                         const T* u, const T* f, const T* wd, T* y, int zchunk, int nchunks, const int* act,
                         double* dotp, hipStream_t s, const LaunchTimer& t) {
-  if (mode == kApply)
-    launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
-                 nchunks, act, dotp);
+  if (mode == kApply && dotp && !MASKIN)
+    launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN, PRE, !MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y,
+                 zchunk, nchunks, act, dotp);
+  else if (mode == kApply)
+    launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN, PRE, false>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
+                 nchunks, act, nullptr);
   else if (mode == kSmooth)
-    launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
-                 nchunks, act, dotp);
+    launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN, PRE, false>, grid, block, s, t, L, q, E, u, f, wd, y,
+                 zchunk, nchunks, act, nullptr);
   else
-    launch_timed(k_stream<T, kResidual, R, W, MINW, MASKIN, PRE>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
-                 nchunks, act, dotp);
+    launch_timed(k_stream<T, kResidual, R, W, MINW, MASKIN, PRE, false>, grid, block, s, t, L, q, E, u, f, wd, y,
+                 zchunk, nchunks, act, nullptr);
 }
 
 template <typename T, int R, int W, int MINW>
