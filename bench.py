@@ -39,8 +39,8 @@ def smooth_bytes_per_launch(g) -> float:
 # the kernel source they were taken on: any change to the kernel voids them.
 TRAFFIC = {
     # profiles/stream_smooth_f32_L0_cantilever_128x64x64_rf_traffic.md
-    ("cantilever_128x64x64_rf", "stream", 4, 0, "8c1b250da06b086a"): 44793150.7,
-    ("cantilever_128x64x64_rf", "stream", 4, 4, "8c1b250da06b086a"): 41928507.2,
+    ("cantilever_128x64x64_rf", "stream", 4, 0, "1750fc0128f078c2"): 44794255.1,
+    ("cantilever_128x64x64_rf", "stream", 4, 4, "1750fc0128f078c2"): 41929576.2,
 }
 
 
