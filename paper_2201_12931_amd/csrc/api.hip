@@ -491,8 +491,11 @@ int tune_tail(hexmg_grid* g, hipStream_t s) {
 // sides, plus the partial sums of r . z.  In mixed precision the binary32
 // right-hand side is formed inside the first sweep and z is widened inside the
 // dot product.
+// z = M^{-1} r and the partials of r . z.  In mixed precision z is written in
+// binary64 only with write_z; otherwise it stays in the binary32 buffer
+// g->vu32[0] (the CG update widens it on the fly).
 void precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials, int nrhs, const int* act,
-                  hipStream_t s) {
+                  hipStream_t s, bool write_z = true) {
   const long long N = 3ll * g->lv[0].nn;
   if (g->desc.precision == HEXMG_FP64) {
     VView<double> v = view64(g);
@@ -507,7 +510,10 @@ void precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials
       launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
       vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s, true);
     }
-    launch_to64_dot(N, g->vu32[0], r, z, rz_partials, nrhs, act, s);
+    if (write_z)
+      launch_to64_dot(N, g->vu32[0], r, z, rz_partials, nrhs, act, s);
+    else
+      launch_dot_mixed(N, g->vu32[0], r, rz_partials, nrhs, act, s);
   }
 }
 
@@ -853,8 +859,13 @@ struct PcgRun {
   int issue_next() {
     const int k = issued;
     g->prof_tag = k + 1;
-    precondition(g, g->r, g->z, g->partials, nb, g->active, s);
-    launch_update_p(N(), g->partials, g->scalars, g->active, g->z, g->p, (k - 1) & 1, nb, s);
+    if (g->desc.precision == HEXMG_FP64) {
+      precondition(g, g->r, g->z, g->partials, nb, g->active, s);
+      launch_update_p<double>(N(), g->partials, g->scalars, g->active, g->z, g->p, (k - 1) & 1, nb, s);
+    } else {
+      precondition(g, g->r, g->z, g->partials, nb, g->active, s, false);
+      launch_update_p<float>(N(), g->partials, g->scalars, g->active, g->vu32[0], g->p, (k - 1) & 1, nb, s);
+    }
     return issue_iteration(k + 1);
   }
   int begin() {

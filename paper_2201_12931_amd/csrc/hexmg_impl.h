@@ -136,8 +136,12 @@ void launch_update_xr(long long n, const double* pq_partials, int npq, double* s
 void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
                      hipStream_t s);
 // rz_new = sum of rz partials; beta = rz_new / rz[parity]; p = z + beta p; rz[1-parity] = rz_new
-void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const double* z,
-                     double* p, int parity, int nrhs, hipStream_t s);
+template <typename TZ>
+void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
+                     int parity, int nrhs, hipStream_t s);
+// partials of r . (double) u32 (the binary32 V-cycle output, not widened in memory)
+void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
+                      hipStream_t s);
 // z64 = (double) u32 and partials of r . z64
 void launch_to64_dot(long long n, const float* u32, const double* r, double* z, double* partials, int nrhs,
                      const int* act, hipStream_t s);

@@ -598,8 +598,10 @@ __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __res
 }
 
 // grid (kReduceBlocks, nrhs): beta from the rz partials, p = z + beta p
+// z in binary64, or the binary32 V-cycle output widened on the fly
+template <typename TZ>
 __global__ void k_update_p(long long n, const double* __restrict__ rz_partials, double* __restrict__ sc,
-                           const int* __restrict__ active, const double* __restrict__ z, double* __restrict__ p,
+                           const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
                            int parity) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
@@ -615,7 +617,25 @@ __global__ void k_update_p(long long n, const double* __restrict__ rz_partials, 
   p += off;
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
-    p[i] = z[i] + beta * p[i];
+    p[i] = (double)z[i] + beta * p[i];
+}
+
+// partials of r . (double) u32 (grid (kReduceBlocks, nrhs)); the widened z is not stored
+__global__ void k_dot_mixed(long long n, const float* __restrict__ u32, const double* __restrict__ r,
+                            double* __restrict__ partials, const int* __restrict__ act) {
+  const int rhs = blockIdx.y;
+  partials += (long long)kReduceBlocks * rhs;
+  if (act && !act[rhs]) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const long long off = n * rhs;
+  double acc = 0.0;
+#pragma unroll 4
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    acc += r[off + i] * (double)u32[off + i];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
 // z = (double) u32 and the partials of r . z (grid (kReduceBlocks, nrhs))
@@ -827,9 +847,18 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
                      hipStream_t s) {
   k_rr_check<<<nrhs, kBlock, 0, s>>>(rr_partials, sc, active, host_slot);
 }
-void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const double* z,
-                     double* p, int parity, int nrhs, hipStream_t s) {
-  k_update_p<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, sc, active, z, p, parity);
+template <typename TZ>
+void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
+                     int parity, int nrhs, hipStream_t s) {
+  k_update_p<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, sc, active, z, p, parity);
+}
+template void launch_update_p<double>(long long, const double*, double*, const int*, const double*, double*, int,
+                                      int, hipStream_t);
+template void launch_update_p<float>(long long, const double*, double*, const int*, const float*, double*, int, int,
+                                     hipStream_t);
+void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
+                      hipStream_t s) {
+  k_dot_mixed<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, u32, r, partials, act);
 }
 void launch_to64_dot(long long n, const float* u32, const double* r, double* z, double* partials, int nrhs,
                      const int* act, hipStream_t s) {
