@@ -131,6 +131,7 @@ size_t carve(hexmg_grid* g, char* base) {
   g->Abuf[0] = c.take<double>(nc * nc);
   g->Abuf[1] = c.take<double>(nc * nc);
   g->gjD = c.take<double>(2 * kGJBlock * kGJBlock);
+  g->Ecoarse = c.take<double>(g->lv[L - 1].ne);
   g->Ke64 = c.take<double>(576);
   g->Ke32 = c.take<float>(576);
   const size_t N0 = 3ull * g->lv[0].nn;
@@ -680,6 +681,41 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
   // the previous coarsest inverse may still be in flight on the auxiliary stream
   if (g->coarse_pending) HIP_TRY(hipStreamWaitEvent(s, g->ev_coarse, 0));
   launch_simp(g->lv[0].ne, rho, d.E0, d.Emin, d.penal, 1.0, g->E64[0], g->E32[0], g->rho[0], g->flags, s);
+  // Coarsest level on the auxiliary stream: its moduli straight from level 0
+  // (or the Galerkin stencil, which needs the levels above), assembly,
+  // Gauss-Jordan inverse, symmetrization; everything it reads is final when
+  // it is forked.
+  const int nc = g->nc;
+  hipStream_t a = g->aux_stream;
+  auto fork_coarsest = [&]() -> int {
+    HIP_TRY(hipEventRecord(g->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(a, g->ev_fork, 0));
+    const Level& C = g->lv[g->L - 1];
+    if (g->galerkin) {
+      launch_dense_from_stencil(C, g->S64[g->L - 1], g->Abuf[0], a);
+    } else {
+      const double* Ec = g->E64[0];
+      if (g->L > 1) {
+        const bool dens = d.coarse_avg == HEXMG_AVG_DENSITY;
+        const double scale = double(1 << (g->L - 1));
+        launch_coarsest_moduli(g->lv[0], C, 1 << (g->L - 1), dens ? g->rho[0] : g->E64[0], dens, d.E0, d.Emin,
+                               d.penal, scale, g->Ecoarse, a);
+        Ec = g->Ecoarse;
+      }
+      launch_coarse_assemble(C, g->Ke64, Ec, g->Abuf[0], a);
+    }
+    double* inv = nullptr;
+    launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, &inv, a);
+    double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
+    launch_symmetrize(nc, inv, other, a);
+    HIP_TRY(hipEventRecord(g->ev_coarse, a));
+    g->Ainv = other;
+    g->coarse_pending = true;
+    g->coarse_waited_valid = false;
+    return 0;
+  };
+  if (!g->galerkin)
+    if (int e = fork_coarsest()) return e;
   launch_or_flags(kReduceBlocks, g->flags, g->flags + kReduceBlocks, s);
   HIP_TRY(hipMemcpyAsync(g->host_scalars, g->flags + kReduceBlocks, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(g->ev_flag, s));
@@ -691,29 +727,12 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     else
       launch_modulus_from_mean(g->lv[l - 1], g->lv[l], g->E64[l - 1], 2.0, g->E64[l], g->E32[l], s);
   }
-  const int nc = g->nc;
   if (g->galerkin) {  // Eq. 23 products, level by level, as stencils
     launch_galerkin_first(g->lv[0], g->lv[1], g->E64[0], g->Gc, g->Ke64, g->S64[1], g->S32[1], s);
     for (int l = 1; l + 1 < g->L; ++l)
       launch_galerkin_coarsen(g->lv[l], g->lv[l + 1], g->S64[l], g->S64[l + 1], g->S32[l + 1], s);
+    if (int e = fork_coarsest()) return e;
   }
-  // Coarsest level on the auxiliary stream: assemble (or take the stencil),
-  // invert by Gauss-Jordan, symmetrize.  Everything it reads is final here.
-  HIP_TRY(hipEventRecord(g->ev_fork, s));
-  HIP_TRY(hipStreamWaitEvent(g->aux_stream, g->ev_fork, 0));
-  hipStream_t a = g->aux_stream;
-  if (g->galerkin)
-    launch_dense_from_stencil(g->lv[g->L - 1], g->S64[g->L - 1], g->Abuf[0], a);
-  else
-    launch_coarse_assemble(g->lv[g->L - 1], g->Ke64, g->E64[g->L - 1], g->Abuf[0], a);
-  double* inv = nullptr;
-  launch_gj_blocked(nc, g->Abuf[0], g->Abuf[1], g->gjD, &inv, a);
-  double* other = (inv == g->Abuf[0]) ? g->Abuf[1] : g->Abuf[0];
-  launch_symmetrize(nc, inv, other, a);
-  HIP_TRY(hipEventRecord(g->ev_coarse, a));
-  g->Ainv = other;
-  g->coarse_pending = true;
-  g->coarse_waited_valid = false;
   if (g->galerkin) {
     launch_diag(g->lv[0], g->Ke64, g->E64[0], d.omega, g->wd64[0], g->wd32[0], s);
     for (int l = 1; l < g->L; ++l) launch_stencil_diag(g->lv[l], g->S64[l], d.omega, g->wd64[l], g->wd32[l], s);

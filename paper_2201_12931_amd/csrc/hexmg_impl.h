@@ -106,6 +106,10 @@ void launch_modulus_from_density(int ne, const double* rho, double E0, double Em
                                  double scale, double* E64, float* E32, hipStream_t s);
 void launch_modulus_from_mean(const Level& F, const Level& C, const double* Ef, double scale,
                               double* E64, float* E32, hipStream_t s);
+// Coarsest-level moduli from level 0 in one launch (one block per coarsest
+// element, blocks of blk^3 fine elements; v0 = densities or fine moduli).
+void launch_coarsest_moduli(const Level& F, const Level& C, int blk, const double* v0, bool density, double E0,
+                            double Emin, double p, double scale, double* Ec, hipStream_t s);
 void launch_diag(const Level& L, const double* Ke, const double* E, double omega, double* wdinv64,
                  float* wdinv32, hipStream_t s);
 void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s);
@@ -252,7 +256,8 @@ struct hexmg_grid {
   std::vector<double*> vf64, vu64, vt64, vr64;
   std::vector<float*> vf32, vu32, vt32, vr32;
   double* Abuf[2];  // coarsest operator / Gauss-Jordan ping-pong
-  double* gjD;      // kGJBlock^2
+  double* gjD;      // 2 kGJBlock^2
+  double* Ecoarse;  // coarsest moduli for the coarsest operator (auxiliary stream)
   double* Ainv;     // points at the buffer holding the symmetrized inverse
   int nc;         // coarsest DOFs
   double* Ke64;   // 576

@@ -163,6 +163,29 @@ __global__ void k_modulus_from_density(int ne, const double* __restrict__ rho, d
   E32[e] = (float)E;
 }
 
+// Moduli of the coarsest level straight from level 0, one block per coarsest
+// element: the mean of the blk^3 fine densities (density averaging) or fine
+// moduli (modulus averaging) of its block -- the nested means of the level
+// hierarchy, summed in one pass -- then the SIMP modulus of the mean density
+// times scale, or scale times the mean modulus.  Feeds only the coarsest
+// operator, so that its assembly does not wait for the other levels.
+__global__ void k_coarsest_moduli(Level F, Level C, int blk, const double* __restrict__ v0, int density,
+                                  double E0, double Emin, double p, double scale, double* __restrict__ Ec) {
+  const int e = blockIdx.x;
+  const int I = e % C.nx, t = e / C.nx, J = t % C.ny, K = t / C.ny;
+  const int nb = blk * blk * blk;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nb; q += kBlock) {
+    const int dx = q % blk, r = q / blk, dy = r % blk, dz = r / blk;
+    s += v0[(I * blk + dx) + (long long)F.nx * ((J * blk + dy) + (long long)F.ny * (K * blk + dz))];
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) {
+    const double m = s / nb;
+    Ec[e] = density ? scale * (Emin + pow(m, p) * (E0 - Emin)) : scale * m;
+  }
+}
+
 __global__ void k_modulus_from_mean(Level F, Level C, const double* __restrict__ Ef, double scale,
                                     double* __restrict__ E64, float* __restrict__ E32) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
@@ -785,6 +808,10 @@ void launch_modulus_from_density(int ne, const double* rho, double E0, double Em
 void launch_modulus_from_mean(const Level& F, const Level& C, const double* Ef, double scale,
                               double* E64, float* E32, hipStream_t s) {
   k_modulus_from_mean<<<blocks_for(C.ne), kBlock, 0, s>>>(F, C, Ef, scale, E64, E32);
+}
+void launch_coarsest_moduli(const Level& F, const Level& C, int blk, const double* v0, bool density, double E0,
+                            double Emin, double p, double scale, double* Ec, hipStream_t s) {
+  k_coarsest_moduli<<<C.ne, kBlock, 0, s>>>(F, C, blk, v0, density ? 1 : 0, E0, Emin, p, scale, Ec);
 }
 void launch_diag(const Level& L, const double* Ke, const double* E, double omega, double* wdinv64,
                  float* wdinv32, hipStream_t s) {
