@@ -359,6 +359,25 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
   block_inverse(a, prow, pcol, DT);
 }
 
+// 64x64x64 product on the matrix cores: wave w accumulates rows 16w..16w+15
+// of L^T-stored-left times right, acc[t] holding the 16x16 output tile t
+// (columns 16t..16t+15).  v_mfma_f64_16x16x4f64 lane layout: the left operand
+// of lane l is element (row l%16, k l/16), the right one (k l/16, column l%16),
+// and output value v of lane l is element (row 4v + l/16, column l%16).
+typedef double d4 __attribute__((ext_vector_type(4)));
+template <int P>
+__device__ inline void mfma_64(const double (&sLT)[kGJBlock][P], const double (&sR)[kGJBlock][P], double sign,
+                               d4 (&acc)[4]) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int ks = 0; ks < kGJBlock / 4; ++ks) {
+    const int q = 4 * ks + (l >> 4);
+    const double a = sign * sLT[q][16 * w + (l & 15)];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sR[q][16 * t + (l & 15)], acc[t], 0, 0, 0);
+  }
+}
+
 // Row panel and update in one launch, grid (ceil(n / 64), ceil(n / 64)) of
 // 64x64 tiles (J, I).  The block of tile (I, J) first forms its own 64 columns
 // of the row panel, X_J = D A_KJ (X_K = D, from A_KK taken as the identity) --
@@ -366,19 +385,24 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
 // than a launch -- then
 //   B_ij = X[i-k0][j]                                          (I = K)
 //   B_ij = (J = K ? 0 : A_ij) - sum_q A[i][k0+q] X[q][j]        (otherwise).
-// Both products read their operands from LDS, D^T / A_IK^T on the left (rows
-// q, padded against bank conflicts) and A_KJ / X_J on the right.  The block of
-// the next diagonal tile (kb+1, kb+1) then inverts its result in place and
-// writes it transposed to DTnext, so the next step needs no separate launch.
+// Both products run on the binary64 matrix cores from LDS operands, D^T /
+// A_IK^T on the left (rows q, padded against bank conflicts) and A_KJ / X_J on
+// the right.  The block of the next diagonal tile (kb+1, kb+1) then inverts
+// its result in place and writes it transposed to DTnext, so the next step
+// needs no separate launch.
 __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int nb, const double* __restrict__ A,
                                                             const double* __restrict__ DT,
                                                             double* __restrict__ B, double* __restrict__ DTnext) {
+  static_assert(kGJBlock == 64 && kBlock == 256, "four waves of 16 output rows");
   constexpr int P = kGJBlock + 1;
   __shared__ double sL[kGJBlock][P];  // D^T, then A_IK^T
   __shared__ double sR[kGJBlock][P];  // A_KJ (identity for J = K), then X_J
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int k0 = kb * kGJBlock, I = blockIdx.y, J = blockIdx.x;
   const int i0 = I * kGJBlock, j0 = J * kGJBlock;
+  // row / column of output value v of tile t for this lane
+  auto orow = [&](int v) { return 16 * w + 4 * v + (l >> 4); };
+  auto ocol = [&](int t) { return 16 * t + (l & 15); };
   // every global load of a stage is issued before the first LDS store
   constexpr int kPer = kGJBlock * kGJBlock / kBlock;  // 16 elements per thread
   {
@@ -398,36 +422,21 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
     }
   }
   __syncthreads();
-  double x[4][4] = {};
-#pragma unroll 4
-  for (int q = 0; q < kGJBlock; ++q) {
-    double l[4], rr_[4];
+  d4 acc[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      l[m] = sL[q][ty + 16 * m];
-      rr_[m] = sR[q][tx + 16 * m];
-    }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) x[rr][cc] = fma(l[rr], rr_[cc], x[rr][cc]);
-  }
+  for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  mfma_64<P>(sL, sR, 1.0, acc);  // acc = X_J
   if (I == kb) {  // rows of the pivot block: B_K* = X
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
-        if (i < n && j < n) B[(long long)i * n + j] = x[rr][cc];
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + orow(v), j = j0 + ocol(t);
+        if (i < n && j < n) B[(long long)i * n + j] = acc[t][v];
       }
     return;  // uniform per block
   }
-  __syncthreads();  // every read of sL and sR is done
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) sR[ty + 16 * rr][tx + 16 * cc] = x[rr][cc];
-  double y[4][4];
+  d4 y[4];
   {
     double va[kPer];
 #pragma unroll
@@ -436,12 +445,17 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
       va[m] = (i0 + r < n && c < nb) ? A[(long long)(i0 + r) * n + k0 + c] : 0.0;
     }
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
-        y[rr][cc] = (J != kb && i < n && j < n) ? A[(long long)i * n + j] : 0.0;
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + orow(v), j = j0 + ocol(t);
+        y[t][v] = (J != kb && i < n && j < n) ? A[(long long)i * n + j] : 0.0;
       }
+    __syncthreads();  // every read of sL and sR is done
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sR[orow(v)][ocol(t)] = acc[t][v];
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
       const int e = threadIdx.x + kBlock * m, r = e >> 6, c = e & 63;
@@ -449,37 +463,34 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
     }
   }
   __syncthreads();
-#pragma unroll 4
-  for (int q = 0; q < kGJBlock; ++q) {
-    double l[4], xr[4];
+  mfma_64<P>(sL, sR, -1.0, y);  // y = A_IJ - A_IK X_J
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      l[m] = sL[q][ty + 16 * m];
-      xr[m] = sR[q][tx + 16 * m];
-    }
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) y[rr][cc] = fma(-l[rr], xr[cc], y[rr][cc]);
-  }
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int i = i0 + ty + 16 * rr, j = j0 + tx + 16 * cc;
-      if (i < n && j < n) B[(long long)i * n + j] = y[rr][cc];
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + orow(v), j = j0 + ocol(t);
+      if (i < n && j < n) B[(long long)i * n + j] = y[t][v];
     }
   if (I == kb + 1 && J == kb + 1) {  // uniform per block
+    // to the 4x4 micro-tile layout of block_inverse through LDS
+    __syncthreads();  // the product's reads of sR are done
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sR[orow(v)][ocol(t)] = y[t][v];
+    __syncthreads();
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     const int nbn = min(n - i0, kGJBlock);
+    double a[4][4];
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
         const int i = ty + 16 * rr, j = tx + 16 * cc;
-        if (!(i < nbn && j < nbn)) y[rr][cc] = (i == j) ? 1.0 : 0.0;
+        a[rr][cc] = (i < nbn && j < nbn) ? sR[i][j] : (i == j ? 1.0 : 0.0);
       }
     __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
-    block_inverse(y, prow, pcol, DTnext);
+    block_inverse(a, prow, pcol, DTnext);
   }
 }
 
