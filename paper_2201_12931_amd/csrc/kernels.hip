@@ -293,38 +293,63 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
 // In-place inverse of the 64x64 tile held in a (padded with the identity
 // beyond its nb x nb block), by the block's 256 threads; written transposed to
 // DT (DT[j*64+i] = D_ij).  prow / pcol: the block's LDS exchange buffers.
-__device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][kGJBlock], double (&pcol)[2][kGJBlock],
-                                     double* __restrict__ DT) {
+//
+// Gauss-Jordan with 2x2 pivot blocks K = {k, k+1} (32 steps, one barrier
+// each): with Q = A_KK^{-1} (closed form), every element takes
+//   a_ij <- z_ij - c_i0 r_0j - c_i1 r_1j,
+// z = a with rows and columns k, k+1 cleared, c_i = (a_ik, a_i,k+1) for i not
+// in K and -e_i for i in K, r_j = Q (a_kj, a_k+1,j) for j not in K and the
+// column Q e_j for j in K.  That leaves Q on K x K, Q A_Kj on the pivot rows,
+// -A_iK Q on the pivot columns and A_ij - A_iK Q A_Kj elsewhere: two scalar
+// steps at once.  The 2x2 diagonal blocks of an SPD matrix and of its Schur
+// complements are SPD, so no pivoting is needed.
+__device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][2][kGJBlock],
+                                     double (&pcol)[2][2][kGJBlock], double* __restrict__ DT) {
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks)  // slot of row / column k in the owners' registers
+  for (int ks = 0; ks < 4; ++ks)  // slot of rows / columns k, k+1 in the owners' registers
 #pragma unroll 2
-    for (int kb = 0; kb < 16; ++kb) {  // owner index (ty of row k, tx of column k)
-      const int k = 16 * ks + kb, par = kb & 1;
-      if (ty == kb) {
+    for (int kp = 0; kp < 8; ++kp) {  // rows k, k+1 are owned by ty = 2kp, 2kp+1 (columns by tx)
+      const int kb = 2 * kp, k = 16 * ks + kb, par = kp & 1;
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) prow[par][tx + 16 * cc] = a[ks][cc];
-      }
-      if (tx == kb) {
+      for (int h = 0; h < 2; ++h) {
+        if (ty == kb + h) {
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) pcol[par][ty + 16 * rr] = a[rr][ks];
+          for (int cc = 0; cc < 4; ++cc) prow[par][h][tx + 16 * cc] = a[ks][cc];
+        }
+        if (tx == kb + h) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) pcol[par][h][ty + 16 * rr] = a[rr][ks];
+        }
       }
       __syncthreads();
-      // 1/a_kk: hardware reciprocal and two Newton steps (each squares the
-      // relative error), shorter than the IEEE division sequence on this
-      // latency-bound chain
-      const double akk = prow[par][k];
-      double p = __builtin_amdgcn_rcp(akk);
-      p = fma(p, fma(-akk, p, 1.0), p);
-      p = fma(p, fma(-akk, p, 1.0), p);
-      double r[4], c[4];
+      const double p00 = prow[par][0][k], p01 = prow[par][0][k + 1];
+      const double p10 = prow[par][1][k], p11 = prow[par][1][k + 1];
+      // 1/det: hardware reciprocal and two Newton steps (each squares the
+      // relative error), shorter than the IEEE division on this latency-bound chain
+      const double det = p00 * p11 - p01 * p10;
+      double id = __builtin_amdgcn_rcp(det);
+      id = fma(id, fma(-det, id, 1.0), id);
+      id = fma(id, fma(-det, id, 1.0), id);
+      const double q00 = p11 * id, q01 = -p01 * id, q10 = -p10 * id, q11 = p00 * id;
+      double r0[4], r1[4], c0[4], c1[4];
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) r[cc] = prow[par][tx + 16 * cc] * p;
+      for (int cc = 0; cc < 4; ++cc) {
+        const double x0 = prow[par][0][tx + 16 * cc], x1 = prow[par][1][tx + 16 * cc];
+        r0[cc] = q00 * x0 + q01 * x1;
+        r1[cc] = q10 * x0 + q11 * x1;
+      }
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) c[rr] = pcol[par][ty + 16 * rr];
-      const bool colk = tx == kb, rowk = ty == kb;
-      r[ks] = colk ? p : r[ks];
-      c[ks] = rowk ? -1.0 : c[ks];
+      for (int rr = 0; rr < 4; ++rr) {
+        c0[rr] = pcol[par][0][ty + 16 * rr];
+        c1[rr] = pcol[par][1][ty + 16 * rr];
+      }
+      const bool colk0 = tx == kb, colk1 = tx == kb + 1, rowk0 = ty == kb, rowk1 = ty == kb + 1;
+      r0[ks] = colk0 ? q00 : (colk1 ? q01 : r0[ks]);
+      r1[ks] = colk0 ? q10 : (colk1 ? q11 : r1[ks]);
+      c0[ks] = rowk0 ? -1.0 : (rowk1 ? 0.0 : c0[ks]);
+      c1[ks] = rowk0 ? 0.0 : (rowk1 ? -1.0 : c1[ks]);
+      const bool colk = colk0 || colk1, rowk = rowk0 || rowk1;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         a[m][ks] = colk ? 0.0 : a[m][ks];
@@ -333,7 +358,7 @@ __device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][kGJBlo
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) a[rr][cc] = fma(-c[rr], r[cc], a[rr][cc]);
+        for (int cc = 0; cc < 4; ++cc) a[rr][cc] = fma(-c1[rr], r1[cc], fma(-c0[rr], r0[cc], a[rr][cc]));
     }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
@@ -346,7 +371,7 @@ __device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][kGJBlo
 __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
                                                          double* __restrict__ DT) {
   static_assert(kGJBlock == 64 && kBlock == 256, "16x16 threads of 4x4 micro-tiles");
-  __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
+  __shared__ double prow[2][2][kGJBlock], pcol[2][2][kGJBlock];
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   double a[4][4];
 #pragma unroll
@@ -489,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
         const int i = ty + 16 * rr, j = tx + 16 * cc;
         a[rr][cc] = (i < nbn && j < nbn) ? sR[i][j] : (i == j ? 1.0 : 0.0);
       }
-    __shared__ double prow[2][kGJBlock], pcol[2][kGJBlock];
+    __shared__ double prow[2][2][kGJBlock], pcol[2][2][kGJBlock];
     block_inverse(a, prow, pcol, DTnext);
   }
 }
