@@ -239,7 +239,8 @@ int hexmg_element_matrix(double nu, double *Ke_host);
  * for the streaming kernel, the planes per z-chunk and the tile shape index
  * (rows per thread / waves per workgroup; any output pointer may be NULL).
  * With HEXMG_KERNEL_AUTO the choice is made by timing the candidates
- * (node-gather; every streaming shape with 2..64 planes per chunk) on the
+ * (node-gather; every streaming shape with 1..64 planes per chunk -- a chunk
+ * of one plane requests all its inputs before any arithmetic) on the
  * grid's stream during the first successful hexmg_set_density, separately
  * for K u, the sweep and the residual. */
 int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int *kernel, int *zchunk, int *shape);
