@@ -75,7 +75,8 @@ typedef struct hexmg_grid *hexmg_grid_t;
 
 typedef struct {
   int nx, ny, nz;       /* elements per axis; each divisible by 2^(levels-1);
-                           3 (nx+1)(ny+1)(nz+1) < 2^31 and 24 (nx+1)(ny+1) < 2^31 */
+                           3 (nx+1)(ny+1)(nz+1) < 2^31, 24 (nx+1)(ny+1) < 2^31,
+                           ny + 1 <= 65535 and nz + 1 <= 65535 */
   int levels;           /* multigrid levels, >= 1; level 0 is the given grid */
   double E0, Emin, nu, penal; /* 1, 1e-9, 0.3, 3 in the paper's examples */
   int precision;        /* HEXMG_FP64 | HEXMG_MIXED */
@@ -249,7 +250,9 @@ int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int *kernel, in
  * modes): kernel
  * HEXMG_KERNEL_STREAM (zchunk >= 1 planes per chunk, shape 0 .. number of
  * shapes - 1) or HEXMG_KERNEL_GATHER.  Later automatic tuning does not undo it.
- * Returns -1 for an unknown kernel, shape or level. */
+ * Returns -1 for an unknown kernel, shape or level, and for a z-chunk so small
+ * that ceil((nz_level + 1) / zchunk) * max_nrhs exceeds 65535 (the launch
+ * grid's z limit). */
 int hexmg_set_kernel_choice(hexmg_grid_t grid, int level, int dtype, int kernel, int zchunk, int shape);
 
 /* The coarse part of the V-cycle (Alg. 3) may run as one cooperative launch

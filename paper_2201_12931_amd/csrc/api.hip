@@ -52,6 +52,8 @@ int validate(const hexmg_grid_desc* d) {
   if (3 * nn >= (1ll << 31)) return fail(HEXMG_ERR_INVALID, "grid too large (3*nodes must be < 2^31)");
   if (24ll * (d->nx + 1) * (d->ny + 1) >= (1ll << 31))
     return fail(HEXMG_ERR_INVALID, "xy plane too large (24*(nx+1)*(ny+1) must be < 2^31)");
+  if (d->ny + 1 > 65535 || d->nz + 1 > 65535)
+    return fail(HEXMG_ERR_INVALID, "ny + 1 and nz + 1 must be <= 65535 (launch grid limits)");
   const long long nnc = (long long)(d->nx / q + 1) * (d->ny / q + 1) * (d->nz / q + 1);
   if (3 * nnc > 6144) return fail(HEXMG_ERR_INVALID, "coarsest level too large for the dense solve (> 6144 DOFs); add levels");
   if (!(d->Emin > 0.0) || !(d->E0 > d->Emin) || !std::isfinite(d->E0))
@@ -226,7 +228,8 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
   std::vector<hexmg_grid::Choice> cand;
   for (int sh = 0; sh < stream_shapes(f32); ++sh)
     for (int zc : {1, 2, 4, 8, 16, 32, 64})
-      if (zc <= L.nzn || zc == 2) cand.push_back({HEXMG_KERNEL_STREAM, zc, sh});
+      if ((zc <= L.nzn || zc == 2) && (long long)((L.nzn + zc - 1) / zc) * g->desc.max_nrhs <= 65535)
+        cand.push_back({HEXMG_KERNEL_STREAM, zc, sh});
   cand.push_back({HEXMG_KERNEL_GATHER, 0, 0});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1240,6 +1243,9 @@ int hexmg_set_kernel_choice(hexmg_grid_t g, int level, int dtype, int kernel, in
   } else if (kernel == HEXMG_KERNEL_STREAM) {
     if (zchunk < 1 || shape < 0 || shape >= stream_shapes(dtype == HEXMG_F32))
       return fail(HEXMG_ERR_INVALID, "bad z-chunk or shape");
+    const int nzn = g->lv[level].nzn;
+    if ((long long)((nzn + zchunk - 1) / zchunk) * g->desc.max_nrhs > 65535)
+      return fail(HEXMG_ERR_INVALID, "z-chunk too small: z-chunks times max_nrhs must be <= 65535");
   } else {
     return fail(HEXMG_ERR_INVALID, "bad kernel");
   }

@@ -51,6 +51,11 @@ def test_descriptor_validation():
     # coarsest level too large for the dense direct solve
     with pytest.raises(hexmg.HexmgError):
         hexmg.workspace_size(hexmg.default_desc(64, 32, 32, 1))
+    # node planes beyond the launch grid's y/z limits
+    for shape in ((2, 65536, 2), (2, 2, 65536)):
+        with pytest.raises(hexmg.HexmgError) as e:
+            hexmg.workspace_size(hexmg.default_desc(*shape, 1))
+        assert "65535" in hexmg.last_error()
 
 
 def test_workspace_scales_with_grid():
