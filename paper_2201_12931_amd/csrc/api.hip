@@ -491,27 +491,27 @@ int tune_tail(hexmg_grid* g, hipStream_t s) {
   return 0;
 }
 
-// z = V(r) in the grid's precision for nrhs <= max_nrhs binary64 right-hand
-// sides, plus the partial sums of r . z.  In mixed precision the binary32
-// right-hand side is formed inside the first sweep and z is widened inside the
-// dot product.
-// z = M^{-1} r and the partials of r . z.  In mixed precision z is written in
-// binary64 only with write_z; otherwise it stays in the binary32 buffer
-// g->vu32[0] (the CG update widens it on the fly).
+// z = M^{-1} r (the V-cycle in the grid's precision) for nrhs <= max_nrhs
+// binary64 right-hand sides, and the partials of r . z.  In mixed precision
+// the binary32 right-hand side is formed inside the first sweep, and z is
+// written in binary64 only with write_z; otherwise it stays in the binary32
+// buffer g->vu32[0] (the CG update widens it on the fly).  With first_done the
+// first sweep (and in mixed precision the binary32 copy of r) was already
+// written by the CG residual update.
 void precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials, int nrhs, const int* act,
-                  hipStream_t s, bool write_z = true) {
+                  hipStream_t s, bool write_z = true, bool first_done = false) {
   const long long N = 3ll * g->lv[0].nn;
   if (g->desc.precision == HEXMG_FP64) {
     VView<double> v = view64(g);
-    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s);
+    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s, first_done);
     launch_dot_partial(N, r, z, rz_partials, nrhs, act, s);
   } else {
     VView<float> v = view32(g);
     if (g->L == 1) {  // the coarsest level is the whole grid: no sweep to fuse into
-      launch_f64_to_f32(N, r, g->vf32[0], nrhs, act, s);
+      if (!first_done) launch_f64_to_f32(N, r, g->vf32[0], nrhs, act, s);
       vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s);
     } else {
-      launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
+      if (!first_done) launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
       vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s, true);
     }
     if (write_z)
@@ -855,7 +855,8 @@ struct PcgRun {
     HIP_TRY(hipEventRecord(ev[k % 3], s));
     return 0;
   }
-  // iteration k (1-based): q = A p, alpha, x and r updates, ||r||^2 and the test
+  // iteration k (1-based): q = A p, alpha, the r update (its x update follows
+  // in the next p update, or at the end), ||r||^2 and the test
   int issue_iteration(int k) {
     double* sc = g->scalars;
     g->prof_tag = k;
@@ -872,21 +873,29 @@ struct PcgRun {
       launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
       npq = kReduceBlocks;
     }
-    launch_update_xr(N(), g->partials, npq, sc, g->active, g->p, g->q, u, g->r, g->partials2, (k - 1) & 1, nb, s);
+    // r -= alpha q with the next preconditioner's first sweep (x += alpha p follows in the p update)
+    const bool sweep = g->L > 1;
+    if (g->desc.precision == HEXMG_FP64)
+      launch_update_r_first<double>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2, (k - 1) & 1,
+                                    g->wd64[0], nullptr, sweep ? g->vt64[0] : nullptr, nb, s);
+    else
+      launch_update_r_first<float>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2, (k - 1) & 1,
+                                   g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr, nb, s);
     launch_rr_check(g->partials2, sc, g->active, slot(k), nb, s);
     issued = k;
     return post(k, false);
   }
-  // z = M^{-1} r, beta, p = z + beta p (after iteration k), then iteration k+1
+  // z = M^{-1} r (its first sweep already formed), beta, x += alpha p (iteration k)
+  // and p = z + beta p, then iteration k+1
   int issue_next() {
     const int k = issued;
     g->prof_tag = k + 1;
     if (g->desc.precision == HEXMG_FP64) {
-      precondition(g, g->r, g->z, g->partials, nb, g->active, s);
-      launch_update_p<double>(N(), g->partials, g->scalars, g->active, g->z, g->p, (k - 1) & 1, nb, s);
+      precondition(g, g->r, g->z, g->partials, nb, g->active, s, true, true);
+      launch_update_px<double>(N(), g->partials, g->scalars, g->active, g->z, g->p, u, (k - 1) & 1, nb, s);
     } else {
-      precondition(g, g->r, g->z, g->partials, nb, g->active, s, false);
-      launch_update_p<float>(N(), g->partials, g->scalars, g->active, g->vu32[0], g->p, (k - 1) & 1, nb, s);
+      precondition(g, g->r, g->z, g->partials, nb, g->active, s, false, true);
+      launch_update_px<float>(N(), g->partials, g->scalars, g->active, g->vu32[0], g->p, u, (k - 1) & 1, nb, s);
     }
     return issue_iteration(k + 1);
   }
@@ -913,6 +922,7 @@ struct PcgRun {
   int enqueue_finish(int read) {
     const Level& L0 = g->lv[0];
     double* sc = g->scalars;
+    launch_flush_x(N(), sc, g->p, u, nb, s);  // the last iteration's x += alpha p
     HIP_TRY(hipEventRecord(t1, s));
     g->prof_tag = 0;
     gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s);  // true residual in binary64

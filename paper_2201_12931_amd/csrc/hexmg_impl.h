@@ -131,18 +131,24 @@ void launch_reduce_final(const double* partials, double* out, int stride, int nr
 // init: active = (ff > 0), its = 0, stop = rtol^2 ff (rtol2 <= 0: never)
 void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s);
 // alpha = rz[parity] / (sum of the npq pq partials of a right-hand side, which
-// are also npq apart); x += alpha p; r -= alpha q; rr partials
-void launch_update_xr(long long n, const double* pq_partials, int npq, double* sc, const int* active,
-                      const double* p, const double* q, double* x, double* r, double* rr_partials, int parity,
-                      int nrhs, hipStream_t s);
+// are also npq apart); r -= alpha q; rr partials; the first Jacobi sweep from
+// zero t = wdinv * r (mixed: on the binary32 copy f32 of r; t may be null);
+// x += alpha p is left to launch_update_px / launch_flush_x (s[kXPend])
+template <typename TW>
+void launch_update_r_first(long long n, const double* pq_partials, int npq, double* sc, const int* active,
+                           const double* q, double* r, double* rr_partials, int parity, const TW* wdinv, float* f32,
+                           TW* t, int nrhs, hipStream_t s);
 // rr = sum of partials; its += 1; convergence / breakdown clears active; the
 // scalars of every right-hand side are written to host_slot (pinned host memory)
 void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
                      hipStream_t s);
-// rz_new = sum of rz partials; beta = rz_new / rz[parity]; p = z + beta p; rz[1-parity] = rz_new
+// rz_new = sum of rz partials; beta = rz_new / rz[parity]; x += alpha p (the
+// previous iteration's); p = z + beta p; rz[1-parity] = rz_new
 template <typename TZ>
-void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
-                     int parity, int nrhs, hipStream_t s);
+void launch_update_px(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
+                      double* x, int parity, int nrhs, hipStream_t s);
+// x += alpha p for the right-hand sides where it is still due (s[kXPend])
+void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s);
 // partials of r . (double) u32 (the binary32 V-cycle output, not widened in memory)
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s);
@@ -235,6 +241,7 @@ enum ScalarSlot {
   kActive = 10,  // copy of the device active flag
   kTmp = 11,
   kTmp2 = 12,
+  kXPend = 13,   // 1 while the last iteration's x += alpha p has not been applied
   kScalars = 16
 };
 

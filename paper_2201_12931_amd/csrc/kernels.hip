@@ -575,16 +575,23 @@ __global__ void k_pcg_init(double rtol2, double* __restrict__ sc, int* __restric
   s[kStop] = rtol2 > 0.0 ? rtol2 * ff : -1.0;
   s[kRr] = ff;
   s[kPq] = 0.0;
+  s[kXPend] = 0.0;
 }
 
 // grid (kReduceBlocks, nrhs).  alpha = rz / pq with pq the sum of npq partials
 // per right-hand side; every block sums the same partials in the same order,
-// so all blocks use the identical alpha.  x += alpha p, r -= alpha q, and the
-// partials of ||r||^2.
-__global__ void k_update_xr(long long n, const double* __restrict__ pq_partials, int npq, double* __restrict__ sc,
-                            const int* __restrict__ active, const double* __restrict__ p,
-                            const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
-                            double* __restrict__ rr_partials, int parity) {
+// so all blocks use the identical alpha.  r -= alpha q and the partials of
+// ||r||^2, fused with the first Jacobi sweep from zero of the preconditioner
+// that follows (t = omega D^{-1} r; in mixed precision on the binary32 copy of
+// r, written to f32).  t may be null (no sweep: the coarsest level is the
+// whole grid).  The matching x += alpha p is left to k_update_px, or to
+// k_flush_x when the solve stops; s[kXPend] records whether it is due.
+template <typename TW>
+__global__ void k_update_r_first(long long n, const double* __restrict__ pq_partials, int npq,
+                                 double* __restrict__ sc, const int* __restrict__ active,
+                                 const double* __restrict__ q, double* __restrict__ r,
+                                 double* __restrict__ rr_partials, int parity, const TW* __restrict__ wdinv,
+                                 float* __restrict__ f32, TW* __restrict__ t) {
   const int rhs = blockIdx.y;
   rr_partials += (long long)kReduceBlocks * rhs;
   if (!active[rhs]) {
@@ -596,26 +603,34 @@ __global__ void k_update_xr(long long n, const double* __restrict__ pq_partials,
   const double pq = block_sum_all(pqs);
   double* s = sc + kScalars * rhs;
   const double alpha = s[kRz0 + parity] / pq;
+  const bool ok = pq > 0.0 && pq < 1e308;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s[kPq] = pq;
     s[kAlpha] = alpha;
+    s[kXPend] = ok ? 1.0 : 0.0;
   }
-  if (!(pq > 0.0 && pq < 1e308)) {  // breakdown: keep the previous iterate; the check flags it
+  if (!ok) {  // breakdown: keep the previous iterate; the check flags it
     if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
     return;
   }
   const long long off = n * rhs;
-  p += off;
   q += off;
-  x += off;
   r += off;
+  if (f32) f32 += off;
+  if (t) t += off;
   double acc = 0.0;
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
-    x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     acc += ri * ri;
+    if constexpr (sizeof(TW) == 4) {
+      const float fv = (float)ri;
+      f32[i] = fv;
+      if (t) t[i] = wdinv[i] * fv;
+    } else {
+      if (t) t[i] = wdinv[i] * ri;
+    }
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) rr_partials[blockIdx.x] = acc;
@@ -656,17 +671,20 @@ __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __res
   __threadfence_system();
 }
 
-// grid (kReduceBlocks, nrhs): beta from the rz partials, p = z + beta p
-// z in binary64, or the binary32 V-cycle output widened on the fly
+// grid (kReduceBlocks, nrhs): beta from the rz partials; the previous
+// iteration's x += alpha p (always due while the right-hand side is active:
+// a breakdown clears the flag), then p = z + beta p.  z in binary64, or the
+// binary32 V-cycle output widened on the fly.
 template <typename TZ>
-__global__ void k_update_p(long long n, const double* __restrict__ rz_partials, double* __restrict__ sc,
-                           const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
-                           int parity) {
+__global__ void k_update_px(long long n, const double* __restrict__ rz_partials, double* __restrict__ sc,
+                            const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
+                            double* __restrict__ x, int parity) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
   const double rz = sum_partials(rz_partials + (long long)kReduceBlocks * rhs);
   double* s = sc + kScalars * rhs;
   const double beta = rz / s[kRz0 + parity];
+  const double alpha = s[kAlpha];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s[kRz0 + 1 - parity] = rz;
     s[kBeta] = beta;
@@ -674,9 +692,28 @@ __global__ void k_update_p(long long n, const double* __restrict__ rz_partials, 
   const long long off = n * rhs;
   z += off;
   p += off;
+  x += off;
+#pragma unroll 4
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    const double pi = p[i];
+    x[i] += alpha * pi;
+    p[i] = (double)z[i] + beta * pi;
+  }
+}
+
+// grid (kReduceBlocks, nrhs): the x += alpha p still due when the solve stops
+__global__ void k_flush_x(long long n, const double* __restrict__ sc, const double* __restrict__ p,
+                          double* __restrict__ x) {
+  const int rhs = blockIdx.y;
+  const double* s = sc + kScalars * rhs;
+  if (s[kXPend] == 0.0) return;
+  const double alpha = s[kAlpha];
+  const long long off = n * rhs;
+  p += off;
+  x += off;
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
-    p[i] = (double)z[i] + beta * p[i];
+    x[i] += alpha * p[i];
 }
 
 // partials of r . (double) u32 (grid (kReduceBlocks, nrhs)); the widened z is not stored
@@ -899,26 +936,34 @@ void launch_reduce_final(const double* partials, double* out, int stride, int nr
 void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s) {
   k_pcg_init<<<1, ((nrhs + 63) / 64) * 64, 0, s>>>(rtol2, sc, active, nrhs);
 }
-void launch_update_xr(long long n, const double* pq_partials, int npq, double* sc, const int* active,
-                      const double* p, const double* q, double* x, double* r, double* rr_partials, int parity,
-                      int nrhs, hipStream_t s) {
-  k_update_xr<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, npq, sc, active, p, q, x, r, rr_partials,
-                                                           parity);
+template <typename TW>
+void launch_update_r_first(long long n, const double* pq_partials, int npq, double* sc, const int* active,
+                           const double* q, double* r, double* rr_partials, int parity, const TW* wdinv, float* f32,
+                           TW* t, int nrhs, hipStream_t s) {
+  k_update_r_first<TW><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, npq, sc, active, q, r,
+                                                                     rr_partials, parity, wdinv, f32, t);
 }
+template void launch_update_r_first<double>(long long, const double*, int, double*, const int*, const double*,
+                                            double*, double*, int, const double*, float*, double*, int, hipStream_t);
+template void launch_update_r_first<float>(long long, const double*, int, double*, const int*, const double*,
+                                           double*, double*, int, const float*, float*, float*, int, hipStream_t);
 
 void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
                      hipStream_t s) {
   k_rr_check<<<nrhs, kBlock, 0, s>>>(rr_partials, sc, active, host_slot);
 }
 template <typename TZ>
-void launch_update_p(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
-                     int parity, int nrhs, hipStream_t s) {
-  k_update_p<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, sc, active, z, p, parity);
+void launch_update_px(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
+                      double* x, int parity, int nrhs, hipStream_t s) {
+  k_update_px<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, sc, active, z, p, x, parity);
 }
-template void launch_update_p<double>(long long, const double*, double*, const int*, const double*, double*, int,
-                                      int, hipStream_t);
-template void launch_update_p<float>(long long, const double*, double*, const int*, const float*, double*, int, int,
-                                     hipStream_t);
+template void launch_update_px<double>(long long, const double*, double*, const int*, const double*, double*,
+                                       double*, int, int, hipStream_t);
+template void launch_update_px<float>(long long, const double*, double*, const int*, const float*, double*, double*,
+                                      int, int, hipStream_t);
+void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s) {
+  k_flush_x<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x);
+}
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s) {
   k_dot_mixed<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, u32, r, partials, act);
