@@ -73,7 +73,7 @@ int stream_blocks(const Level& L, bool f32, int shape, int zchunk);
 // most partials a fused dot product may leave per right-hand side
 constexpr int kMaxDotParts = 8192;
 
-constexpr int kReduceBlocks = 512;  // partial sums per reduction (fixed: deterministic)
+constexpr int kReduceBlocks = 1024;  // partial sums per reduction (fixed: deterministic)
 constexpr int kOcProbes = 32;       // Lagrange multipliers evaluated per OC pass
 constexpr int kBlock = 256;
 constexpr int kGJBlock = 64;  // pivot block of the blocked Gauss-Jordan inverse
