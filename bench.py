@@ -152,8 +152,9 @@ def main():
     def step(grid):
         grid.set_density(rho_d)
         code, info = grid.solve(f_d, u_d, rtol=rtol, maxit=500)
-        c = grid.compliance_sensitivity(f_d, u_d, dc_d)
-        return code, info[0], c[0]
+        # the solve already formed the compliance f . u (binary64, on the device)
+        grid.compliance_sensitivity(f_d, u_d, dc_d, compliance=False)
+        return code, info[0], info[0]["compliance"]
 
     if args.coarse_cycle:  # before the first set_density: the timed choice is then skipped
         lv, nb = (int(v) for v in args.coarse_cycle.split(":"))

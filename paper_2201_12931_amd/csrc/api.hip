@@ -138,7 +138,8 @@ size_t carve(hexmg_grid* g, char* base) {
   g->Ke32 = c.take<float>(576);
   const size_t N0 = 3ull * g->lv[0].nn;
   g->r = c.take<double>(N0 * R);
-  g->z = c.take<double>(N0 * R);
+  // binary64 z only for binary64 solves (mixed precision keeps z in binary32)
+  g->z = g->desc.precision == HEXMG_FP64 ? c.take<double>(N0 * R) : nullptr;
   g->p = c.take<double>(N0 * R);
   g->q = c.take<double>(N0 * R);
   g->partials = c.take<double>((size_t)kMaxDotParts * R);  // >= kReduceBlocks
@@ -903,15 +904,12 @@ struct PcgRun {
     const Level& L0 = g->lv[0];
     double* sc = g->scalars;
     HIP_TRY(hipEventRecord(t0, s));
-    launch_mask_copy(L0, f, g->r, nb, s);  // r0 = M f
-    launch_fill(N() * nb, 0.0, u, s);      // x0 = 0
-    dot(g, N(), g->r, g->r, sc + kFf, nb, s);
-    launch_pcg_init(rtol > 0.0 ? rtol * rtol : -1.0, sc, g->active, nb, s);
+    launch_pcg_start(L0, f, g->r, u, g->partials, nb, s);  // r0 = M f, x0 = 0, ||r0||^2 partials
+    launch_pcg_init(rtol > 0.0 ? rtol * rtol : -1.0, g->partials, sc, g->active, nb, s);
     if (maxit == 0) return enqueue_finish(0);
     g->prof_tag = 1;
-    precondition(g, g->r, g->z, g->partials, nb, g->active, s);  // z0 = M^{-1} r0
+    precondition(g, g->r, g->p, g->partials, nb, g->active, s);  // p0 = z0 = M^{-1} r0
     launch_reduce_final(g->partials, sc + kRz0, kScalars, nb, s);
-    HIP_TRY(hipMemcpyAsync(g->p, g->z, N() * nb * sizeof(double), hipMemcpyDeviceToDevice, s));  // p0 = z0
     if (int e = issue_iteration(1)) return e;
     if (maxit >= 2)
       if (int e = issue_next()) return e;
@@ -926,10 +924,7 @@ struct PcgRun {
     HIP_TRY(hipEventRecord(t1, s));
     g->prof_tag = 0;
     gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s);  // true residual in binary64
-    launch_mask_copy(L0, f, g->z, nb, s);
-    launch_sub(N() * nb, g->z, g->q, g->z, s);
-    dot(g, N(), g->z, g->z, sc + kTmp, nb, s);
-    dot(g, N(), f, u, sc + kTmp2, nb, s);
+    launch_pcg_final(L0, f, g->q, u, g->partials, g->partials2, sc, nb, s);  // ||M f - A x||^2, f . x
     final_slot = read + 2;  // a slot no result in flight is written to
     phase = kFinish;
     return post(final_slot, true);

@@ -128,8 +128,15 @@ void launch_dot_partial(long long n, const double* x, const double* y, double* p
 // out[r * stride] = sum of partials[r][0..kReduceBlocks)
 void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s);
 // CG steps with the scalars computed on the device (see ScalarSlot):
-// init: active = (ff > 0), its = 0, stop = rtol^2 ff (rtol2 <= 0: never)
-void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s);
+// start: r = M f, x = 0, partials of ||r||^2 ([nrhs][kReduceBlocks])
+void launch_pcg_start(const Level& L, const double* f, double* r, double* x, double* partials, int nrhs,
+                      hipStream_t s);
+// init: ff from the start's partials; active = (ff > 0), its = 0, stop = rtol^2 ff (rtol2 <= 0: never)
+void launch_pcg_init(double rtol2, const double* ff_partials, double* sc, int* active, int nrhs, hipStream_t s);
+// after q = A x: sc[kTmp] = ||M f - q||^2 and sc[kTmp2] = f . x per right-hand
+// side (pa, pb: [nrhs][kReduceBlocks] partials)
+void launch_pcg_final(const Level& L, const double* f, const double* q, const double* x, double* pa, double* pb,
+                      double* sc, int nrhs, hipStream_t s);
 // alpha = rz[parity] / (sum of the npq pq partials of a right-hand side, which
 // are also npq apart); r -= alpha q; rr partials; the first Jacobi sweep from
 // zero t = wdinv * r (mixed: on the binary32 copy f32 of r; t may be null);
@@ -155,10 +162,7 @@ void launch_dot_mixed(long long n, const float* u32, const double* r, double* pa
 // z64 = (double) u32 and partials of r . z64
 void launch_to64_dot(long long n, const float* u32, const double* r, double* z, double* partials, int nrhs,
                      const int* act, hipStream_t s);
-void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s);
 void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s);
-void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);
-void launch_fill(long long n, double v, double* x, hipStream_t s);
 
 void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
                         double coef, double pm1, int accumulate, double* dc, hipStream_t s);

@@ -561,11 +561,38 @@ __global__ void k_reduce_final(const double* __restrict__ partials, double* __re
   if (threadIdx.x == 0) out[(long long)stride * blockIdx.x] = s;
 }
 
-__global__ void k_pcg_init(double rtol2, double* __restrict__ sc, int* __restrict__ active, int nrhs) {
-  const int r = threadIdx.x;
-  if (r >= nrhs) return;
+// grid (kReduceBlocks, nrhs): r = M f (fixed DOFs zeroed), x = 0 and the
+// partials of ||r||^2 (the summation order of k_dot_partial)
+__global__ void k_pcg_start(Level L, const double* __restrict__ f, double* __restrict__ r, double* __restrict__ x,
+                            double* __restrict__ partials) {
+  const long long n = 3ll * L.nn;
+  const long long off = n * blockIdx.y;
+  f += off;
+  r += off;
+  x += off;
+  partials += (long long)kReduceBlocks * blockIdx.y;
+  double acc = 0.0;
+#pragma unroll 4
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    const int node = (int)(i / 3), c = (int)(i % 3);
+    const double ri = ((L.mask[node] >> c) & 1) ? 0.0 : f[i];
+    r[i] = ri;
+    x[i] = 0.0;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// One block per right-hand side: ff = ||M f||^2 from the partials, then
+// active = (ff > 0), its = 0, stop = rtol^2 ff (rtol2 <= 0: never)
+__global__ void k_pcg_init(double rtol2, const double* __restrict__ ff_partials, double* __restrict__ sc,
+                           int* __restrict__ active) {
+  const int r = blockIdx.x;
+  const double ff = sum_partials(ff_partials + (long long)kReduceBlocks * r);
+  if (threadIdx.x != 0) return;
   double* s = sc + kScalars * r;
-  const double ff = s[kFf];
+  s[kFf] = ff;
   const bool finite = ff == ff && ff < 1e308;
   const int a = (ff > 0.0 && finite) ? 1 : 0;
   active[r] = a;
@@ -576,6 +603,40 @@ __global__ void k_pcg_init(double rtol2, double* __restrict__ sc, int* __restric
   s[kRr] = ff;
   s[kPq] = 0.0;
   s[kXPend] = 0.0;
+}
+
+// grid (kReduceBlocks, nrhs), after q = A x: the partials of ||M f - q||^2
+// (true residual) into pa and of f . x into pb (the order of k_dot_partial)
+__global__ void k_pcg_final_dots(Level L, const double* __restrict__ f, const double* __restrict__ q,
+                                 const double* __restrict__ x, double* __restrict__ pa, double* __restrict__ pb) {
+  const long long n = 3ll * L.nn;
+  const long long off = n * blockIdx.y;
+  f += off;
+  q += off;
+  x += off;
+  double a = 0.0, b = 0.0;
+#pragma unroll 4
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    const int node = (int)(i / 3), c = (int)(i % 3);
+    const double fi = f[i];
+    const double ri = (((L.mask[node] >> c) & 1) ? 0.0 : fi) - q[i];
+    a += ri * ri;
+    b += fi * x[i];
+  }
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) {
+    pa[(long long)kReduceBlocks * blockIdx.y + blockIdx.x] = a;
+    pb[(long long)kReduceBlocks * blockIdx.y + blockIdx.x] = b;
+  }
+}
+
+// grid (nrhs, 2): sc[kTmp] = sum of pa, sc[kTmp2] = sum of pb, per right-hand side
+__global__ void k_pcg_final_sums(const double* __restrict__ pa, const double* __restrict__ pb,
+                                 double* __restrict__ sc) {
+  const double* p = (blockIdx.y ? pb : pa) + (long long)kReduceBlocks * blockIdx.x;
+  const double v = sum_partials(p);
+  if (threadIdx.x == 0) sc[kScalars * blockIdx.x + (blockIdx.y ? kTmp2 : kTmp)] = v;
 }
 
 // grid (kReduceBlocks, nrhs).  alpha = rz / pq with pq the sum of npq partials
@@ -755,31 +816,12 @@ __global__ void k_to64_dot(long long n, const float* __restrict__ u32, const dou
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-__global__ void k_mask_copy(Level L, const double* __restrict__ f, double* __restrict__ r) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= 3ll * L.nn) return;
-  const long long off = 3ll * L.nn * blockIdx.y;  // right-hand side
-  const int n = (int)(i / 3), c = (int)(i % 3);
-  r[off + i] = ((L.mask[n] >> c) & 1) ? 0.0 : f[off + i];
-}
-
 __global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* __restrict__ b,
                              const int* __restrict__ act) {
   if (act && !act[blockIdx.y]) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   const long long off = n * blockIdx.y;
   if (i < n) b[off + i] = (float)a[off + i];
-}
-
-__global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b,
-                      double* __restrict__ c) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) c[i] = a[i] - b[i];
-}
-
-__global__ void k_fill(long long n, double v, double* __restrict__ x) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] = v;
 }
 
 // Adjoint sensitivity (Eq. 7 with u* = u): dc_e = coef rho_e^(p-1) u_e^T K0 u_e,
@@ -933,8 +975,17 @@ void launch_dot_partial(long long n, const double* x, const double* y, double* p
 void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s) {
   k_reduce_final<<<nrhs, kBlock, 0, s>>>(partials, out, stride);
 }
-void launch_pcg_init(double rtol2, double* sc, int* active, int nrhs, hipStream_t s) {
-  k_pcg_init<<<1, ((nrhs + 63) / 64) * 64, 0, s>>>(rtol2, sc, active, nrhs);
+void launch_pcg_start(const Level& L, const double* f, double* r, double* x, double* partials, int nrhs,
+                      hipStream_t s) {
+  k_pcg_start<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(L, f, r, x, partials);
+}
+void launch_pcg_init(double rtol2, const double* ff_partials, double* sc, int* active, int nrhs, hipStream_t s) {
+  k_pcg_init<<<nrhs, kBlock, 0, s>>>(rtol2, ff_partials, sc, active);
+}
+void launch_pcg_final(const Level& L, const double* f, const double* q, const double* x, double* pa, double* pb,
+                      double* sc, int nrhs, hipStream_t s) {
+  k_pcg_final_dots<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(L, f, q, x, pa, pb);
+  k_pcg_final_sums<<<dim3(nrhs, 2), kBlock, 0, s>>>(pa, pb, sc);
 }
 template <typename TW>
 void launch_update_r_first(long long n, const double* pq_partials, int npq, double* sc, const int* active,
@@ -972,17 +1023,8 @@ void launch_to64_dot(long long n, const float* u32, const double* r, double* z, 
                      const int* act, hipStream_t s) {
   k_to64_dot<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, u32, r, z, partials, act);
 }
-void launch_mask_copy(const Level& L, const double* f, double* r, int nrhs, hipStream_t s) {
-  k_mask_copy<<<dim3(blocks_for(3ll * L.nn), nrhs), kBlock, 0, s>>>(L, f, r);
-}
 void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s) {
   k_f64_to_f32<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, a, b, act);
-}
-void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s) {
-  k_sub<<<blocks_for(n), kBlock, 0, s>>>(n, a, b, c);
-}
-void launch_fill(long long n, double v, double* x, hipStream_t s) {
-  k_fill<<<blocks_for(n), kBlock, 0, s>>>(n, v, x);
 }
 void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
                         double coef, double pm1, int accumulate, double* dc, hipStream_t s) {

@@ -301,16 +301,19 @@ class Grid:
             _check(code, ok=(OK, NOT_CONVERGED))
         return code, [x.as_dict() for x in infos]
 
-    def compliance_sensitivity(self, f, u, dc=None, weights=None, stream=None):
+    def compliance_sensitivity(self, f, u, dc=None, weights=None, stream=None, compliance=True):
+        """Compliances f . u (returned; None with compliance=False, which skips
+        the dot products and their host read) and, with dc, the sensitivity."""
         import numpy as np
         import torch
 
         nrhs = f.numel() // self.n_dof
-        c = np.zeros(nrhs, dtype=np.float64)
+        c = np.zeros(nrhs, dtype=np.float64) if compliance else None
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
         _check(lib().hexmg_compliance_sensitivity(
             self.handle, _dev(f, torch.float64, name="f"), _dev(u, torch.float64, name="u"), nrhs,
-            None if w is None else w.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
+            None if w is None else w.ctypes.data_as(ctypes.c_void_p),
+            None if c is None else c.ctypes.data_as(ctypes.c_void_p),
             None if dc is None else _dev(dc, torch.float64, self.n_elem, "dc"), _stream(stream)))
         return c
 
