@@ -658,7 +658,7 @@ int hexmg_grid_destroy(hexmg_grid_t g) {
   if (!g) return 0;
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
   if (g->aux_stream) (void)hipStreamDestroy(g->aux_stream);
-  for (hipEvent_t e : {g->ev_fork, g->ev_coarse, g->ev_flag})
+  for (hipEvent_t e : {g->ev_fork, g->ev_coarse, g->ev_flag, g->ev_read})
     if (e) (void)hipEventDestroy(e);
   for (auto& r : g->recs) {
     (void)hipEventDestroy(r.a);
@@ -679,18 +679,22 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     if (hipStreamCreateWithFlags(&g->aux_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_coarse, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&g->ev_flag, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&g->ev_flag, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_read, hipEventDisableTiming) != hipSuccess)
       return fail(HEXMG_ERR_DEVICE, "stream or event creation failed");
   }
   // the previous coarsest inverse may still be in flight on the auxiliary stream
   if (g->coarse_pending) HIP_TRY(hipStreamWaitEvent(s, g->ev_coarse, 0));
-  launch_simp(g->lv[0].ne, rho, d.E0, d.Emin, d.penal, 1.0, g->E64[0], g->E32[0], g->rho[0], g->flags, s);
   // Coarsest level on the auxiliary stream: its moduli straight from level 0
   // (or the Galerkin stencil, which needs the levels above), assembly,
   // Gauss-Jordan inverse, symmetrization; everything it reads is final when
-  // it is forked.
+  // it is forked.  With density averaging it reads the caller's rho and is
+  // forked before the SIMP kernel; the stream then waits for that read before
+  // later work (which may overwrite rho) is ordered after this call.
   const int nc = g->nc;
   hipStream_t a = g->aux_stream;
+  const bool dens = d.coarse_avg == HEXMG_AVG_DENSITY;
+  const bool early = !g->galerkin && g->L > 1 && dens;
   auto fork_coarsest = [&]() -> int {
     HIP_TRY(hipEventRecord(g->ev_fork, s));
     HIP_TRY(hipStreamWaitEvent(a, g->ev_fork, 0));
@@ -700,10 +704,10 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     } else {
       const double* Ec = g->E64[0];
       if (g->L > 1) {
-        const bool dens = d.coarse_avg == HEXMG_AVG_DENSITY;
         const double scale = double(1 << (g->L - 1));
-        launch_coarsest_moduli(g->lv[0], C, 1 << (g->L - 1), dens ? g->rho[0] : g->E64[0], dens, d.E0, d.Emin,
-                               d.penal, scale, g->Ecoarse, a);
+        launch_coarsest_moduli(g->lv[0], C, 1 << (g->L - 1), dens ? (early ? rho : g->rho[0]) : g->E64[0], dens,
+                               d.E0, d.Emin, d.penal, scale, g->Ecoarse, a);
+        if (early) HIP_TRY(hipEventRecord(g->ev_read, a));
         Ec = g->Ecoarse;
       }
       launch_coarse_assemble(C, g->Ke64, Ec, g->Abuf[0], a);
@@ -718,7 +722,10 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     g->coarse_waited_valid = false;
     return 0;
   };
-  if (!g->galerkin)
+  if (early)
+    if (int e = fork_coarsest()) return e;
+  launch_simp(g->lv[0].ne, rho, d.E0, d.Emin, d.penal, 1.0, g->E64[0], g->E32[0], g->rho[0], g->flags, s);
+  if (!g->galerkin && !early)
     if (int e = fork_coarsest()) return e;
   launch_or_flags(kReduceBlocks, g->flags, g->flags + kReduceBlocks, s);
   HIP_TRY(hipMemcpyAsync(g->host_scalars, g->flags + kReduceBlocks, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -743,6 +750,7 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
   } else {
     for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], d.omega, g->wd64[l], g->wd32[l], s);
   }
+  if (early) HIP_TRY(hipStreamWaitEvent(s, g->ev_read, 0));
   HIP_TRY(hipGetLastError());
   // validity of rho: wait only for the flag, not for the set-up queued behind it
   int bad = 0;

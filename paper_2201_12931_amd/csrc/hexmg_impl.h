@@ -309,7 +309,7 @@ struct hexmg_grid {
   // hexmg_set_density and the first steps of the next solve; the first use of
   // it on a stream waits for ev_coarse (coarse_waited: the stream that has).
   hipStream_t aux_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_coarse = nullptr, ev_flag = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_coarse = nullptr, ev_flag = nullptr, ev_read = nullptr;
   hipStream_t coarse_waited = nullptr;
   bool coarse_waited_valid = false;  // coarse_waited names a stream (the null stream is one)
   bool coarse_pending = false;

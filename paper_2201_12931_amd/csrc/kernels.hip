@@ -283,73 +283,111 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
 // thread t = 16 ty + tx owns rows ty + 16 rr and columns tx + 16 cc
 // (rr, cc = 0..3), so that the 16 lanes of a row read consecutive words.
 
-// Inverse of the diagonal block, written transposed (DT[j*64+i] = D_ij) for
-// the panel kernel.  Step k: the owners of row k and of column k publish them
-// through LDS (double-buffered: one barrier per step); then every element
-// takes a_ij <- a_ij - c_i r_j with r_j = a_kj / a_kk and c_i = a_ik, where the
-// pivot row and column are first cleared and c_k = -1, r_k = 1/a_kk, which
-// leaves 1/a_kk at (k,k), r_j on row k and -c_i/a_kk on column k.  Rows and
-// columns beyond nb are padded with the identity.
 // In-place inverse of the 64x64 tile held in a (padded with the identity
 // beyond its nb x nb block), by the block's 256 threads; written transposed to
 // DT (DT[j*64+i] = D_ij).  prow / pcol: the block's LDS exchange buffers.
 //
-// Gauss-Jordan with 2x2 pivot blocks K = {k, k+1} (32 steps, one barrier
-// each): with Q = A_KK^{-1} (closed form), every element takes
-//   a_ij <- z_ij - c_i0 r_0j - c_i1 r_1j,
-// z = a with rows and columns k, k+1 cleared, c_i = (a_ik, a_i,k+1) for i not
-// in K and -e_i for i in K, r_j = Q (a_kj, a_k+1,j) for j not in K and the
-// column Q e_j for j in K.  That leaves Q on K x K, Q A_Kj on the pivot rows,
-// -A_iK Q on the pivot columns and A_ij - A_iK Q A_Kj elsewhere: two scalar
-// steps at once.  The 2x2 diagonal blocks of an SPD matrix and of its Schur
-// complements are SPD, so no pivoting is needed.
-__device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][2][kGJBlock],
-                                     double (&pcol)[2][2][kGJBlock], double* __restrict__ DT) {
+// Gauss-Jordan with 4x4 pivot blocks K = {k, .., k+3} (16 steps; the owners
+// of the pivot rows and columns publish them through LDS, double-buffered, so
+// one barrier per step): with Q = A_KK^{-1}, every element takes
+//   a_ij <- z_ij - sum_h c_ih r_hj   (h = 0..3),
+// z = a with the rows and columns of K cleared, c_i = (a_i,k+h)_h for i not
+// in K and -e_i for i in K, r_j = Q (a_k+h,j)_h for j not in K and the column
+// Q e_j for j in K.  That leaves Q on K x K, Q A_Kj on the pivot rows,
+// -A_iK Q on the pivot columns and A_ij - A_iK Q A_Kj elsewhere: four scalar
+// steps at once.  The 4x4 diagonal blocks of an SPD matrix and of its Schur
+// complements are SPD, so no pivoting is needed; Q comes from the 2x2 block
+// form (inverse of the leading 2x2 block, of its Schur complement, then the
+// off-diagonal blocks).
+__device__ inline void inv2(double a00, double a01, double a10, double a11, double (&q)[2][2]) {
+  // 1/det: hardware reciprocal and two Newton steps (each squares the
+  // relative error), shorter than the IEEE division on this latency-bound chain
+  const double det = a00 * a11 - a01 * a10;
+  double id = __builtin_amdgcn_rcp(det);
+  id = fma(id, fma(-det, id, 1.0), id);
+  id = fma(id, fma(-det, id, 1.0), id);
+  q[0][0] = a11 * id;
+  q[0][1] = -a01 * id;
+  q[1][0] = -a10 * id;
+  q[1][1] = a00 * id;
+}
+
+__device__ inline void inv4(const double (&p)[4][4], double (&q)[4][4]) {
+  double ai[2][2], x[2][2], y[2][2], sm[2][2], si[2][2];
+  inv2(p[0][0], p[0][1], p[1][0], p[1][1], ai);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      x[r][c] = ai[r][0] * p[0][2 + c] + ai[r][1] * p[1][2 + c];  // A^-1 B
+      y[r][c] = p[2 + r][0] * ai[0][c] + p[2 + r][1] * ai[1][c];  // C A^-1
+    }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) sm[r][c] = p[2 + r][2 + c] - (y[r][0] * p[0][2 + c] + y[r][1] * p[1][2 + c]);
+  inv2(sm[0][0], sm[0][1], sm[1][0], sm[1][1], si);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      q[2 + r][2 + c] = si[r][c];
+      q[r][2 + c] = -(x[r][0] * si[0][c] + x[r][1] * si[1][c]);
+      q[2 + r][c] = -(si[r][0] * y[0][c] + si[r][1] * y[1][c]);
+    }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) q[r][c] = ai[r][c] - (q[r][2] * y[0][c] + q[r][3] * y[1][c]);
+}
+
+__device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][4][kGJBlock],
+                                     double (&pcol)[2][4][kGJBlock], double* __restrict__ DT) {
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks)  // slot of rows / columns k, k+1 in the owners' registers
+  for (int ks = 0; ks < 4; ++ks)  // slot of the pivot rows / columns in the owners' registers
 #pragma unroll 2
-    for (int kp = 0; kp < 8; ++kp) {  // rows k, k+1 are owned by ty = 2kp, 2kp+1 (columns by tx)
-      const int kb = 2 * kp, k = 16 * ks + kb, par = kp & 1;
+    for (int kp = 0; kp < 4; ++kp) {  // rows k..k+3 are owned by ty = 4kp..4kp+3 (columns by tx)
+      const int kb = 4 * kp, k = 16 * ks + kb, par = kp & 1;
+      const int hy = ty - kb, hx = tx - kb;  // 0..3 for the owners
+      const bool rowk = hy >= 0 && hy < 4, colk = hx >= 0 && hx < 4;
+      if (rowk) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (ty == kb + h) {
+        for (int cc = 0; cc < 4; ++cc) prow[par][hy][tx + 16 * cc] = a[ks][cc];
+      }
+      if (colk) {
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) prow[par][h][tx + 16 * cc] = a[ks][cc];
-        }
-        if (tx == kb + h) {
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) pcol[par][h][ty + 16 * rr] = a[rr][ks];
-        }
+        for (int rr = 0; rr < 4; ++rr) pcol[par][hx][ty + 16 * rr] = a[rr][ks];
       }
       __syncthreads();
-      const double p00 = prow[par][0][k], p01 = prow[par][0][k + 1];
-      const double p10 = prow[par][1][k], p11 = prow[par][1][k + 1];
-      // 1/det: hardware reciprocal and two Newton steps (each squares the
-      // relative error), shorter than the IEEE division on this latency-bound chain
-      const double det = p00 * p11 - p01 * p10;
-      double id = __builtin_amdgcn_rcp(det);
-      id = fma(id, fma(-det, id, 1.0), id);
-      id = fma(id, fma(-det, id, 1.0), id);
-      const double q00 = p11 * id, q01 = -p01 * id, q10 = -p10 * id, q11 = p00 * id;
-      double r0[4], r1[4], c0[4], c1[4];
+      double pk[4][4], q[4][4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) pk[h][g] = prow[par][h][k + g];
+      inv4(pk, q);
+      double rv[4][4], cv[4][4];  // [h][cc], [h][rr]
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
-        const double x0 = prow[par][0][tx + 16 * cc], x1 = prow[par][1][tx + 16 * cc];
-        r0[cc] = q00 * x0 + q01 * x1;
-        r1[cc] = q10 * x0 + q11 * x1;
+        double xg[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) xg[g] = prow[par][g][tx + 16 * cc];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) rv[h][cc] = q[h][0] * xg[0] + q[h][1] * xg[1] + q[h][2] * xg[2] + q[h][3] * xg[3];
       }
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        c0[rr] = pcol[par][0][ty + 16 * rr];
-        c1[rr] = pcol[par][1][ty + 16 * rr];
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) cv[h][rr] = pcol[par][h][ty + 16 * rr];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        // Q e_hx as exact 0/1 weights (a select chain here is turned into an
+        // indexed stack array)
+        const double qh = q[h][0] * (hx == 0 ? 1.0 : 0.0) + q[h][1] * (hx == 1 ? 1.0 : 0.0) +
+                          q[h][2] * (hx == 2 ? 1.0 : 0.0) + q[h][3] * (hx == 3 ? 1.0 : 0.0);
+        rv[h][ks] = colk ? qh : rv[h][ks];
+        cv[h][ks] = rowk ? (hy == h ? -1.0 : 0.0) : cv[h][ks];
       }
-      const bool colk0 = tx == kb, colk1 = tx == kb + 1, rowk0 = ty == kb, rowk1 = ty == kb + 1;
-      r0[ks] = colk0 ? q00 : (colk1 ? q01 : r0[ks]);
-      r1[ks] = colk0 ? q10 : (colk1 ? q11 : r1[ks]);
-      c0[ks] = rowk0 ? -1.0 : (rowk1 ? 0.0 : c0[ks]);
-      c1[ks] = rowk0 ? 0.0 : (rowk1 ? -1.0 : c1[ks]);
-      const bool colk = colk0 || colk1, rowk = rowk0 || rowk1;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         a[m][ks] = colk ? 0.0 : a[m][ks];
@@ -358,7 +396,9 @@ __device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][2][kGJ
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) a[rr][cc] = fma(-c1[rr], r1[cc], fma(-c0[rr], r0[cc], a[rr][cc]));
+        for (int cc = 0; cc < 4; ++cc)
+          a[rr][cc] = fma(-cv[3][rr], rv[3][cc],
+                          fma(-cv[2][rr], rv[2][cc], fma(-cv[1][rr], rv[1][cc], fma(-cv[0][rr], rv[0][cc], a[rr][cc]))));
     }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
@@ -371,7 +411,7 @@ __device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][2][kGJ
 __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
                                                          double* __restrict__ DT) {
   static_assert(kGJBlock == 64 && kBlock == 256, "16x16 threads of 4x4 micro-tiles");
-  __shared__ double prow[2][2][kGJBlock], pcol[2][2][kGJBlock];
+  __shared__ double prow[2][4][kGJBlock], pcol[2][4][kGJBlock];
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   double a[4][4];
 #pragma unroll
@@ -514,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
         const int i = ty + 16 * rr, j = tx + 16 * cc;
         a[rr][cc] = (i < nbn && j < nbn) ? sR[i][j] : (i == j ? 1.0 : 0.0);
       }
-    __shared__ double prow[2][2][kGJBlock], pcol[2][2][kGJBlock];
+    __shared__ double prow[2][4][kGJBlock], pcol[2][4][kGJBlock];
     block_inverse(a, prow, pcol, DTnext);
   }
 }
