@@ -279,26 +279,17 @@ __global__ void k_coarse_assemble(Level C, const double* __restrict__ Ke, const 
 // which is nb scalar Gauss-Jordan steps applied at once.  A is read, B written.
 // The SPD coarse matrix (identity rows at fixed DOFs) needs no pivoting.
 //
-// Both kernels hold a 64x64 tile in registers, 16 elements per thread:
-// thread t = 16 ty + tx owns rows ty + 16 rr and columns tx + 16 cc
-// (rr, cc = 0..3), so that the 16 lanes of a row read consecutive words.
-
-// In-place inverse of the 64x64 tile held in a (padded with the identity
-// beyond its nb x nb block), by the block's 256 threads; written transposed to
-// DT (DT[j*64+i] = D_ij).  prow / pcol: the block's LDS exchange buffers.
-//
-// Gauss-Jordan with 4x4 pivot blocks K = {k, .., k+3} (16 steps; the owners
-// of the pivot rows and columns publish them through LDS, double-buffered, so
-// one barrier per step): with Q = A_KK^{-1}, every element takes
-//   a_ij <- z_ij - sum_h c_ih r_hj   (h = 0..3),
+// Gauss-Jordan on a pivot block K of size b (b consecutive scalar steps at
+// once): with Q = A_KK^{-1}, every element takes
+//   a_ij <- z_ij - sum_h c_ih r_hj   (h = 0..b-1),
 // z = a with the rows and columns of K cleared, c_i = (a_i,k+h)_h for i not
 // in K and -e_i for i in K, r_j = Q (a_k+h,j)_h for j not in K and the column
 // Q e_j for j in K.  That leaves Q on K x K, Q A_Kj on the pivot rows,
-// -A_iK Q on the pivot columns and A_ij - A_iK Q A_Kj elsewhere: four scalar
-// steps at once.  The 4x4 diagonal blocks of an SPD matrix and of its Schur
-// complements are SPD, so no pivoting is needed; Q comes from the 2x2 block
-// form (inverse of the leading 2x2 block, of its Schur complement, then the
-// off-diagonal blocks).
+// -A_iK Q on the pivot columns and A_ij - A_iK Q A_Kj elsewhere.  The diagonal
+// blocks of an SPD matrix and of its Schur complements are SPD, so no
+// pivoting is needed.  For b = 4, Q comes from the 2x2 block form (inverse of
+// the leading 2x2 block, of its Schur complement, then the off-diagonal
+// blocks).
 __device__ inline void inv2(double a00, double a01, double a10, double a11, double (&q)[2][2]) {
   // 1/det: hardware reciprocal and two Newton steps (each squares the
   // relative error), shorter than the IEEE division on this latency-bound chain
@@ -341,87 +332,119 @@ __device__ inline void inv4(const double (&p)[4][4], double (&q)[4][4]) {
     for (int c = 0; c < 2; ++c) q[r][c] = ai[r][c] - (q[r][2] * y[0][c] + q[r][3] * y[1][c]);
 }
 
-__device__ inline void block_inverse(double (&a)[4][4], double (&prow)[2][4][kGJBlock],
-                                     double (&pcol)[2][4][kGJBlock], double* __restrict__ DT) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// In-place inverse of the SPD 64x64 tile in LDS (row-major, padded rows; the
+// identity beyond its nb x nb block), by the block's 256 threads; written
+// transposed to DT (DT[j*64+i] = M_ij).  Block Gauss-Jordan with 16x16 pivot
+// blocks K (four steps, the unified update above with h = 0..15):
+//   Q = M_KK^{-1}                     16x16, one element per thread, by four
+//                                     steps of 4x4 pivot blocks (inv4);
+//   R = Q M_K*, with R_K = Q          on the matrix cores, one 16x16 tile per wave;
+//   M <- Z - C R                      on the matrix cores, 16 rows per wave,
+// with Z = M with the rows and columns of K cleared and C = M_*K, C_K = -I.
+// sR16: 16 rows of exchange space for R; sQ, pr, pc: small exchange buffers.
+template <int RR>
+__device__ inline void block_inverse(double (&sM)[kGJBlock][kGJBlock + 1], double (&sR16)[RR][kGJBlock + 1],
+                                     double (&sQ)[16][17], double (&pr)[2][4][16], double (&pc)[2][4][16],
+                                     double* __restrict__ DT) {
+  static_assert(RR >= 16 && kGJBlock == 64 && kBlock == 256, "four waves, 16x16 pivot blocks");
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int ti = t >> 4, tj = t & 15;  // element of the 16x16 pivot block
+  const int lr = l & 15, lk = l >> 4;  // matrix-core operand row / k of this lane
+#pragma unroll 1
+  for (int s = 0; s < 4; ++s) {
+    const int k0 = 16 * s;
+    // Q = M_KK^{-1}: Gauss-Jordan on 4x4 pivot blocks, one element per thread
+    double a = sM[k0 + ti][k0 + tj];
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks)  // slot of the pivot rows / columns in the owners' registers
-#pragma unroll 2
-    for (int kp = 0; kp < 4; ++kp) {  // rows k..k+3 are owned by ty = 4kp..4kp+3 (columns by tx)
-      const int kb = 4 * kp, k = 16 * ks + kb, par = kp & 1;
-      const int hy = ty - kb, hx = tx - kb;  // 0..3 for the owners
+    for (int m = 0; m < 4; ++m) {
+      const int kb = 4 * m, par = m & 1;
+      const int hy = ti - kb, hx = tj - kb;
       const bool rowk = hy >= 0 && hy < 4, colk = hx >= 0 && hx < 4;
-      if (rowk) {
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) prow[par][hy][tx + 16 * cc] = a[ks][cc];
-      }
-      if (colk) {
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) pcol[par][hx][ty + 16 * rr] = a[rr][ks];
-      }
+      if (rowk) pr[par][hy][tj] = a;
+      if (colk) pc[par][hx][ti] = a;
       __syncthreads();
       double pk[4][4], q[4][4];
 #pragma unroll
       for (int h = 0; h < 4; ++h)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) pk[h][g] = prow[par][h][k + g];
+        for (int g = 0; g < 4; ++g) pk[h][g] = pr[par][h][kb + g];
       inv4(pk, q);
-      double rv[4][4], cv[4][4];  // [h][cc], [h][rr]
+      double xg[4];
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        double xg[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) xg[g] = prow[par][g][tx + 16 * cc];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) rv[h][cc] = q[h][0] * xg[0] + q[h][1] * xg[1] + q[h][2] * xg[2] + q[h][3] * xg[3];
-      }
-#pragma unroll
-      for (int h = 0; h < 4; ++h)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) cv[h][rr] = pcol[par][h][ty + 16 * rr];
+      for (int g = 0; g < 4; ++g) xg[g] = pr[par][g][tj];
+      double acc = (rowk || colk) ? 0.0 : a;
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        // Q e_hx as exact 0/1 weights (a select chain here is turned into an
-        // indexed stack array)
+        // Q e_hx as exact 0/1 weights (a select chain here becomes an indexed stack array)
         const double qh = q[h][0] * (hx == 0 ? 1.0 : 0.0) + q[h][1] * (hx == 1 ? 1.0 : 0.0) +
                           q[h][2] * (hx == 2 ? 1.0 : 0.0) + q[h][3] * (hx == 3 ? 1.0 : 0.0);
-        rv[h][ks] = colk ? qh : rv[h][ks];
-        cv[h][ks] = rowk ? (hy == h ? -1.0 : 0.0) : cv[h][ks];
+        const double r = colk ? qh : q[h][0] * xg[0] + q[h][1] * xg[1] + q[h][2] * xg[2] + q[h][3] * xg[3];
+        const double c = rowk ? (hy == h ? -1.0 : 0.0) : pc[par][h][ti];
+        acc = fma(-c, r, acc);
       }
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        a[m][ks] = colk ? 0.0 : a[m][ks];
-        a[ks][m] = rowk ? 0.0 : a[ks][m];
-      }
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc)
-          a[rr][cc] = fma(-cv[3][rr], rv[3][cc],
-                          fma(-cv[2][rr], rv[2][cc], fma(-cv[1][rr], rv[1][cc], fma(-cv[0][rr], rv[0][cc], a[rr][cc]))));
+      a = acc;
     }
+    sQ[ti][tj] = a;
+    __syncthreads();
+    // R = Q M_K* (tile w), R_K = Q
+    if (w == s) {
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
+      for (int v = 0; v < 4; ++v) sR16[4 * v + lk][k0 + lr] = sQ[4 * v + lk][lr];
+    } else {
+      d4 r = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) DT[(tx + 16 * cc) * kGJBlock + ty + 16 * rr] = a[rr][cc];
+      for (int ks = 0; ks < 4; ++ks)
+        r = __builtin_amdgcn_mfma_f64_16x16x4f64(sQ[lr][4 * ks + lk], sM[k0 + 4 * ks + lk][16 * w + lr], r, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sR16[4 * v + lk][16 * w + lr] = r[v];
+    }
+    __syncthreads();
+    // rows 16w..16w+15: M <- Z - C R
+    {
+      d4 y[4];
+      double cneg[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          y[ct][v] = (w == s || ct == s) ? 0.0 : sM[16 * w + 4 * v + lk][16 * ct + lr];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        cneg[ks] = (w == s) ? (lr == 4 * ks + lk ? 1.0 : 0.0) : -sM[16 * w + lr][k0 + 4 * ks + lk];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          y[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(cneg[ks], sR16[4 * ks + lk][16 * ct + lr], y[ct], 0, 0, 0);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sM[16 * w + 4 * v + lk][16 * ct + lr] = y[ct][v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < kGJBlock * kGJBlock / kBlock; ++e) {
+    const int idx = t + kBlock * e, j = idx >> 6, i = idx & 63;
+    DT[j * kGJBlock + i] = sM[i][j];
+  }
 }
 
 // Inverse of the first diagonal block (later ones are formed by the panel
 // update that produces them).
 __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, const double* __restrict__ A,
                                                          double* __restrict__ DT) {
-  static_assert(kGJBlock == 64 && kBlock == 256, "16x16 threads of 4x4 micro-tiles");
-  __shared__ double prow[2][4][kGJBlock], pcol[2][4][kGJBlock];
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double a[4][4];
+  __shared__ double sM[kGJBlock][kGJBlock + 1], sR16[16][kGJBlock + 1], sQ[16][17];
+  __shared__ double pr[2][4][16], pc[2][4][16];
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int i = ty + 16 * rr, j = tx + 16 * cc;
-      a[rr][cc] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-    }
-  block_inverse(a, prow, pcol, DT);
+  for (int e = 0; e < kGJBlock * kGJBlock / kBlock; ++e) {
+    const int idx = threadIdx.x + kBlock * e, i = idx >> 6, j = idx & 63;
+    sM[i][j] = (i < nb && j < nb) ? A[(long long)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  block_inverse(sM, sR16, sQ, pr, pc, DT);
 }
 
 // 64x64x64 product on the matrix cores: wave w accumulates rows 16w..16w+15
@@ -429,7 +452,6 @@ __global__ __launch_bounds__(kBlock) void k_gj_block_inv(int n, int k0, int nb, 
 // (columns 16t..16t+15).  v_mfma_f64_16x16x4f64 lane layout: the left operand
 // of lane l is element (row l%16, k l/16), the right one (k l/16, column l%16),
 // and output value v of lane l is element (row 4v + l/16, column l%16).
-typedef double d4 __attribute__((ext_vector_type(4)));
 template <int P>
 __device__ inline void mfma_64(const double (&sLT)[kGJBlock][P], const double (&sR)[kGJBlock][P], double sign,
                                d4 (&acc)[4]) {
@@ -537,25 +559,19 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
       if (i < n && j < n) B[(long long)i * n + j] = y[t][v];
     }
   if (I == kb + 1 && J == kb + 1) {  // uniform per block
-    // to the 4x4 micro-tile layout of block_inverse through LDS
-    __syncthreads();  // the product's reads of sR are done
+    // the new diagonal tile to LDS (identity beyond its nbn x nbn block), then its inverse
+    __syncthreads();  // the product's reads of sR and sL are done
+    const int nbn = min(n - i0, kGJBlock);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sR[orow(v)][ocol(t)] = y[t][v];
-    __syncthreads();
-    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-    const int nbn = min(n - i0, kGJBlock);
-    double a[4][4];
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        const int i = ty + 16 * rr, j = tx + 16 * cc;
-        a[rr][cc] = (i < nbn && j < nbn) ? sR[i][j] : (i == j ? 1.0 : 0.0);
+      for (int v = 0; v < 4; ++v) {
+        const int i = orow(v), j = ocol(t);
+        sR[i][j] = (i < nbn && j < nbn) ? y[t][v] : (i == j ? 1.0 : 0.0);
       }
-    __shared__ double prow[2][4][kGJBlock], pcol[2][4][kGJBlock];
-    block_inverse(a, prow, pcol, DTnext);
+    __shared__ double sQ[16][17], pr[2][4][16], pc[2][4][16];
+    __syncthreads();
+    block_inverse(sR, sL, sQ, pr, pc, DTnext);
   }
 }
 
