@@ -385,7 +385,7 @@ void wait_coarse(hexmg_grid* g, hipStream_t s) {
 // (the deeper levels' right-hand sides come out of the masked restriction).
 template <typename T>
 void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrhs, const int* act, hipStream_t s,
-                  bool first_done = false, bool maskin = false) {
+                  bool first_done = false, bool maskin = false, double* dotp = nullptr) {
   const Level& L = g->lv[l];
   if (l == g->L - 1) {
     wait_coarse(g, s);
@@ -420,9 +420,21 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   if (!done) vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, act, s, fuse);
   launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, act, s);
   for (int it = 0; it < nu; ++it) {
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act);
+    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act, it == nu - 1 ? dotp : nullptr);
     cur = 1 - cur;
   }
+}
+
+// Partials per right-hand side of f . out formed inside the last level-0
+// sweep of the V-cycle (its streaming kernel), or 0 where that sweep cannot
+// form them (no sweep, the node-gather kernel, too many workgroups).
+template <typename T>
+int sweep_dot_parts(const hexmg_grid* g) {
+  if (g->L < 2) return 0;
+  const hexmg_grid::Choice& ch = (sizeof(T) == 4 ? g->choice32 : g->choice64)[0][kSmooth];
+  if (ch.kernel != HEXMG_KERNEL_STREAM) return 0;
+  const int nb = stream_blocks(g->lv[0], sizeof(T) == 4, ch.shape, ch.zchunk);
+  return nb <= kMaxDotParts ? nb : 0;
 }
 
 // Times the rest of the V-cycle from each level ls >= 1 launched step by step
@@ -493,33 +505,42 @@ int tune_tail(hexmg_grid* g, hipStream_t s) {
 }
 
 // z = M^{-1} r (the V-cycle in the grid's precision) for nrhs <= max_nrhs
-// binary64 right-hand sides, and the partials of r . z.  In mixed precision
-// the binary32 right-hand side is formed inside the first sweep, and z is
-// written in binary64 only with write_z; otherwise it stays in the binary32
-// buffer g->vu32[0] (the CG update widens it on the fly).  With first_done the
-// first sweep (and in mixed precision the binary32 copy of r) was already
-// written by the CG residual update.
-void precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials, int nrhs, const int* act,
-                  hipStream_t s, bool write_z = true, bool first_done = false) {
+// binary64 right-hand sides, and the partials of r . z; returns how many
+// partials each right-hand side has (kReduceBlocks apart from fuse_dot).  In
+// mixed precision the binary32 right-hand side is formed inside the first
+// sweep, and z is written in binary64 only with write_z; otherwise it stays in
+// the binary32 buffer g->vu32[0] (the CG update widens it on the fly).  With
+// first_done the first sweep (and in mixed precision the binary32 copy of r)
+// was already written by the CG residual update.  With fuse_dot the partials
+// come from the last level-0 sweep where it can form them (in mixed precision
+// as the binary32 copy of r, which the V-cycle consumes, times z), the
+// returned count apart.
+int precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials, int nrhs, const int* act,
+                 hipStream_t s, bool write_z = true, bool first_done = false, bool fuse_dot = false) {
   const long long N = 3ll * g->lv[0].nn;
   if (g->desc.precision == HEXMG_FP64) {
     VView<double> v = view64(g);
-    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s, first_done);
+    const int nd = fuse_dot ? sweep_dot_parts<double>(g) : 0;
+    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s, first_done, false, nd ? rz_partials : nullptr);
+    if (nd) return nd;
     launch_dot_partial(N, r, z, rz_partials, nrhs, act, s);
-  } else {
-    VView<float> v = view32(g);
-    if (g->L == 1) {  // the coarsest level is the whole grid: no sweep to fuse into
-      if (!first_done) launch_f64_to_f32(N, r, g->vf32[0], nrhs, act, s);
-      vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s);
-    } else {
-      if (!first_done) launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
-      vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s, true);
-    }
-    if (write_z)
-      launch_to64_dot(N, g->vu32[0], r, z, rz_partials, nrhs, act, s);
-    else
-      launch_dot_mixed(N, g->vu32[0], r, rz_partials, nrhs, act, s);
+    return kReduceBlocks;
   }
+  VView<float> v = view32(g);
+  const int nd = fuse_dot && !write_z ? sweep_dot_parts<float>(g) : 0;
+  if (g->L == 1) {  // the coarsest level is the whole grid: no sweep to fuse into
+    if (!first_done) launch_f64_to_f32(N, r, g->vf32[0], nrhs, act, s);
+    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s);
+  } else {
+    if (!first_done) launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
+    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s, true, false, nd ? rz_partials : nullptr);
+  }
+  if (nd) return nd;
+  if (write_z)
+    launch_to64_dot(N, g->vu32[0], r, z, rz_partials, nrhs, act, s);
+  else
+    launch_dot_mixed(N, g->vu32[0], r, rz_partials, nrhs, act, s);
+  return kReduceBlocks;
 }
 
 // out[r * kScalars] = x_r . y_r for each right-hand side r
@@ -900,11 +921,12 @@ struct PcgRun {
     const int k = issued;
     g->prof_tag = k + 1;
     if (g->desc.precision == HEXMG_FP64) {
-      precondition(g, g->r, g->z, g->partials, nb, g->active, s, true, true);
-      launch_update_px<double>(N(), g->partials, g->scalars, g->active, g->z, g->p, u, (k - 1) & 1, nb, s);
+      const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, true, true, true);
+      launch_update_px<double>(N(), g->partials, nrz, g->scalars, g->active, g->z, g->p, u, (k - 1) & 1, nb, s);
     } else {
-      precondition(g, g->r, g->z, g->partials, nb, g->active, s, false, true);
-      launch_update_px<float>(N(), g->partials, g->scalars, g->active, g->vu32[0], g->p, u, (k - 1) & 1, nb, s);
+      const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, false, true, true);
+      launch_update_px<float>(N(), g->partials, nrz, g->scalars, g->active, g->vu32[0], g->p, u, (k - 1) & 1, nb,
+                              s);
     }
     return issue_iteration(k + 1);
   }

@@ -61,9 +61,10 @@ void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s
     kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
 }
 
-// dotp (K u without input masking only, may be null): one partial of
-// u . (A u) per workgroup, per right-hand side stream_blocks(...) of them,
-// right-hand side r at dotp + r * stream_blocks(...).
+// dotp (K u and the sweep, without input masking only; may be null): one
+// partial per workgroup of u . (A u) (K u) or of f . y (sweep), per
+// right-hand side stream_blocks(...) of them, right-hand side r at
+// dotp + r * stream_blocks(...).
 template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
@@ -149,11 +150,12 @@ void launch_update_r_first(long long n, const double* pq_partials, int npq, doub
 // scalars of every right-hand side are written to host_slot (pinned host memory)
 void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
                      hipStream_t s);
-// rz_new = sum of rz partials; beta = rz_new / rz[parity]; x += alpha p (the
-// previous iteration's); p = z + beta p; rz[1-parity] = rz_new
+// rz_new = sum of the nrz rz partials of a right-hand side (nrz apart);
+// beta = rz_new / rz[parity]; x += alpha p (the previous iteration's);
+// p = z + beta p; rz[1-parity] = rz_new
 template <typename TZ>
-void launch_update_px(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
-                      double* x, int parity, int nrhs, hipStream_t s);
+void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
+                      double* p, double* x, int parity, int nrhs, hipStream_t s);
 // x += alpha p for the right-hand sides where it is still due (s[kXPend])
 void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s);
 // partials of r . (double) u32 (the binary32 V-cycle output, not widened in memory)

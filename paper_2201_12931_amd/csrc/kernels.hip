@@ -788,17 +788,20 @@ __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __res
   __threadfence_system();
 }
 
-// grid (kReduceBlocks, nrhs): beta from the rz partials; the previous
+// grid (kReduceBlocks, nrhs): beta from the nrz rz partials (every block sums
+// them in the same order); the previous
 // iteration's x += alpha p (always due while the right-hand side is active:
 // a breakdown clears the flag), then p = z + beta p.  z in binary64, or the
 // binary32 V-cycle output widened on the fly.
 template <typename TZ>
-__global__ void k_update_px(long long n, const double* __restrict__ rz_partials, double* __restrict__ sc,
+__global__ void k_update_px(long long n, const double* __restrict__ rz_partials, int nrz, double* __restrict__ sc,
                             const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
                             double* __restrict__ x, int parity) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const double rz = sum_partials(rz_partials + (long long)kReduceBlocks * rhs);
+  double rzs = 0.0;
+  for (int i = threadIdx.x; i < nrz; i += kBlock) rzs += rz_partials[(long long)nrz * rhs + i];
+  const double rz = block_sum_all(rzs);
   double* s = sc + kScalars * rhs;
   const double beta = rz / s[kRz0 + parity];
   const double alpha = s[kAlpha];
@@ -1060,14 +1063,14 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
   k_rr_check<<<nrhs, kBlock, 0, s>>>(rr_partials, sc, active, host_slot);
 }
 template <typename TZ>
-void launch_update_px(long long n, const double* rz_partials, double* sc, const int* active, const TZ* z, double* p,
-                      double* x, int parity, int nrhs, hipStream_t s) {
-  k_update_px<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, sc, active, z, p, x, parity);
+void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
+                      double* p, double* x, int parity, int nrhs, hipStream_t s) {
+  k_update_px<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, nrz, sc, active, z, p, x, parity);
 }
-template void launch_update_px<double>(long long, const double*, double*, const int*, const double*, double*,
+template void launch_update_px<double>(long long, const double*, int, double*, const int*, const double*, double*,
                                        double*, int, int, hipStream_t);
-template void launch_update_px<float>(long long, const double*, double*, const int*, const float*, double*, double*,
-                                      int, int, hipStream_t);
+template void launch_update_px<float>(long long, const double*, int, double*, const int*, const float*, double*,
+                                      double*, int, int, hipStream_t);
 void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s) {
   k_flush_x<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x);
 }

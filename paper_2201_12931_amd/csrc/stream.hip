@@ -160,7 +160,9 @@ __device__ inline double select_bit(int m, int c, double a, double b) { return (
 // entry) and is masked on load; without it (every vector inside the solver is
 // zero there) only the outputs use the support bits.
 // PRE > 0: zchunk is PRE and all inputs of the workgroup are requested up front.
-// DOT (K u only): also one partial of u . (A u) per workgroup into dotp.
+// DOT (K u and the sweep, without MASKIN): also one partial per workgroup
+// into dotp, of u . (A u) for K u and of f . y (the right-hand side times the
+// new iterate) for the sweep.
 template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const T* __restrict__ ug, const T* __restrict__ fg,
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       }
     }
   }
-  // With dotp (K u only): this thread's share of u . (A u) over its outputs.
+  // With DOT: this thread's share of the dot product over its outputs.
   double dot = 0.0;
 
   // Inputs of the epilogue of iteration kk (output plane kk-1): support bits,
@@ -320,9 +322,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
         if (MODE == kApply) {
           v[c] = Au;
           if (DOT && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;
-        } else if (MODE == kSmooth)
+        } else if (MODE == kSmooth) {
           v[c] = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
-        else
+          if (DOT && out_plane && offo[r] != kOutside) dot += (double)fo[r][c] * (double)v[c];
+        } else
           v[c] = fo[r][c] - Au;
       }
       store3(ry, offo[r], v);
@@ -496,6 +499,9 @@ void launch_stream_mode(int mode, dim3 grid, dim3 block, const Level& L, const H
   else if (mode == kApply)
     launch_timed(k_stream<T, kApply, R, W, MINW, MASKIN, PRE, false>, grid, block, s, t, L, q, E, u, f, wd, y, zchunk,
                  nchunks, act, nullptr);
+  else if (mode == kSmooth && dotp && !MASKIN)
+    launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN, PRE, !MASKIN>, grid, block, s, t, L, q, E, u, f, wd, y,
+                 zchunk, nchunks, act, dotp);
   else if (mode == kSmooth)
     launch_timed(k_stream<T, kSmooth, R, W, MINW, MASKIN, PRE, false>, grid, block, s, t, L, q, E, u, f, wd, y,
                  zchunk, nchunks, act, nullptr);
