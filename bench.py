@@ -41,8 +41,8 @@ def smooth_bytes_per_launch(g) -> float:
 # sweep and the last sweep of each V-cycle, which also forms r . z.
 TRAFFIC = {
     # profiles/stream_smooth_f32_L0_cantilever_128x64x64_rf_traffic.md
-    ("cantilever_128x64x64_rf", "stream", 4, 0, "8ead8bc237e0e6af"): 44809968.2,
-    ("cantilever_128x64x64_rf", "stream", 4, 4, "8ead8bc237e0e6af"): 41919250.2,
+    ("cantilever_128x64x64_rf", "stream", 4, 0, "af1a4333bf3d22e2"): 44811741.9,
+    ("cantilever_128x64x64_rf", "stream", 4, 4, "af1a4333bf3d22e2"): 41935410.0,
 }
 
 

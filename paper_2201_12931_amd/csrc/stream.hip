@@ -537,13 +537,15 @@ void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>
 
 // Shapes (rows per thread R, waves per workgroup W, minimum waves per SIMD the
 // register allocation targets).  binary32: (2,4,2) (3,4,2) (4,4,1) (3,8,1)
-// (2,8,1); binary64: (1,8,2) (2,4,1) (taller binary64 tiles spill).  A tile
-// computes W*R element rows for W*R-1 output node rows, so the taller tiles
-// repeat less work at their edges.  All fit without spilling to memory.
-int stream_shapes(bool f32) { return f32 ? 5 : 2; }
+// (2,8,1) (1,8,2) (1,4,2); binary64: (1,8,2) (2,4,1) (1,4,2) (taller binary64
+// tiles spill).  A tile computes W*R element rows for W*R-1 output node rows, so the
+// taller tiles repeat less work at their edges, and the one-row shapes have
+// the shortest chain per thread (small, latency-bound levels).  All fit
+// without spilling to memory.
+int stream_shapes(bool f32) { return f32 ? 7 : 3; }
 int stream_out_rows(bool f32, int shape) {
-  static const int r32[5] = {4 * 2 - 1, 4 * 3 - 1, 4 * 4 - 1, 8 * 3 - 1, 8 * 2 - 1};
-  static const int r64[2] = {8 * 1 - 1, 4 * 2 - 1};
+  static const int r32[7] = {4 * 2 - 1, 4 * 3 - 1, 4 * 4 - 1, 8 * 3 - 1, 8 * 2 - 1, 8 * 1 - 1, 4 * 1 - 1};
+  static const int r64[3] = {8 * 1 - 1, 4 * 2 - 1, 4 * 1 - 1};
   return f32 ? r32[shape] : r64[shape];
 }
 
@@ -560,13 +562,19 @@ void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarC
       launch_stream_impl<T, 4, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
     else if (shape == 3)
       launch_stream_impl<T, 3, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
-    else
+    else if (shape == 4)
       launch_stream_impl<T, 2, 8, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
+    else if (shape == 5)
+      launch_stream_impl<T, 1, 8, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
+    else
+      launch_stream_impl<T, 1, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
   } else {
     if (shape == 0)
       launch_stream_impl<T, 1, 8, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
-    else
+    else if (shape == 1)
       launch_stream_impl<T, 2, 4, 1>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
+    else
+      launch_stream_impl<T, 1, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
   }
 }
 template void launch_stream<float>(int, bool, int, const Level&, const HaarCoef<float>&, const float*,

@@ -327,7 +327,7 @@ def test_stream_and_gather_kernels_agree():
 
 
 @pytest.mark.parametrize("dtype_name,shape", [("f32", 0), ("f32", 1), ("f32", 2), ("f32", 3), ("f32", 4),
-                                              ("f64", 0), ("f64", 1)])
+                                              ("f32", 5), ("f32", 6), ("f64", 0), ("f64", 1), ("f64", 2)])
 @pytest.mark.parametrize("zchunk", [1, 2, 3, 8])
 def test_every_stream_shape(dtype_name, shape, zchunk):
     """Each streaming tile shape and several z-chunk lengths, forced through
