@@ -857,6 +857,7 @@ struct PcgRun {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
   enum Phase { kIterate, kFinish, kDone } phase = kIterate;
   int issued = 0, target = 0, final_slot = 0, status = 0;
+  std::vector<double> prev_rr;  // ||r||^2 of the last iteration read, per right-hand side
 
   int init() {
     for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -933,6 +934,7 @@ struct PcgRun {
   int begin() {
     const Level& L0 = g->lv[0];
     double* sc = g->scalars;
+    prev_rr.assign(nb, 0.0);
     HIP_TRY(hipEventRecord(t0, s));
     launch_pcg_start(L0, f, g->r, u, g->partials, nb, s);  // r0 = M f, x0 = 0, ||r0||^2 partials
     launch_pcg_init(rtol > 0.0 ? rtol * rtol : -1.0, g->partials, sc, g->active, nb, s);
@@ -959,14 +961,31 @@ struct PcgRun {
     phase = kFinish;
     return post(final_slot, true);
   }
+  // Whether the iteration after `target` (already in flight) is expected to
+  // meet the stop test for every active right-hand side: ||r||^2 shrinking by
+  // the last observed factor would reach the threshold.  Speculating one more
+  // iteration beyond it would then only queue launches that exit at once.
+  bool predict_last(const double* h) {
+    bool all = true;
+    for (int k = 0; k < nb; ++k) {
+      const double* q = h + k * kScalars;
+      const double rr = q[kRr], prev = prev_rr[k] > 0.0 ? prev_rr[k] : q[kFf];
+      if (q[kActive] != 0.0 && !(prev > 0.0 && rr * (rr / prev) <= q[kStop])) all = false;
+    }
+    return all;
+  }
   int advance() {
     if (phase == kIterate) {
       const double* h = slot(target);
       int nact = 0;
       for (int k = 0; k < nb; ++k) nact += h[k * kScalars + kActive] != 0.0;
       if (nact == 0 || target >= maxit) return enqueue_finish(target);
-      if (issued < maxit)
+      // keep one iteration in flight beyond the one waited for, unless that
+      // one is expected to be the last
+      const bool last = predict_last(h);
+      while (issued < maxit && issued < target + 2 && !(issued == target + 1 && last))
         if (int e = issue_next()) return e;
+      for (int k = 0; k < nb; ++k) prev_rr[k] = h[k * kScalars + kRr];
       ++target;
       return 0;
     }

@@ -183,6 +183,28 @@ def test_cantilever_32x16x16_fp64_against_direct():
     assert info[0]["compliance"] > c_ref * (1 - 1e-4)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_level_solve_against_direct(precision):
+    """One level: the preconditioner is the exact coarse inverse itself (no
+    sweep to fuse the residual update or r . z into), so PCG stops after one
+    or two iterations at the direct solution."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case single-level solve {precision}", flush=True)
+    dims = (6, 4, 4)
+    prec = hexmg.FP64 if precision == "fp64" else hexmg.MIXED
+    g, rho, mask, grid = make_case(dims, 1, density="uniform", precision=prec)
+    f = W.cantilever_line_load(g)
+    K = fem.assemble_stiffness(*dims, fem.simp_modulus(rho))
+    u_ref = fem.solve_direct(K, f, fem.free_dof_mask(mask))
+    u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+    code, info = grid.solve(gpu(f), u, rtol=1e-10, maxit=20)
+    assert code == 0 and info[0]["status"] == 0
+    assert info[0]["iterations"] <= (1 if precision == "fp64" else 4)
+    assert rel(u.cpu().numpy(), u_ref) < (1e-9 if precision == "fp64" else 1e-6)
+    assert info[0]["compliance"] == pytest.approx(fem.compliance(f, u_ref), rel=1e-8)
+
+
 def test_sensitivity_multi_rhs_weights():
     dims = (16, 8, 8)
     g, rho, mask, grid = make_case(dims, 3)
