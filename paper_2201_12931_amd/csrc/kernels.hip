@@ -175,6 +175,7 @@ __global__ void k_coarsest_moduli(Level F, Level C, int blk, const double* __res
   const int I = e % C.nx, t = e / C.nx, J = t % C.ny, K = t / C.ny;
   const int nb = blk * blk * blk;
   double s = 0.0;
+#pragma unroll 8
   for (int q = threadIdx.x; q < nb; q += kBlock) {
     const int dx = q % blk, r = q / blk, dy = r % blk, dz = r / blk;
     s += v0[(I * blk + dx) + (long long)F.nx * ((J * blk + dy) + (long long)F.ny * (K * blk + dz))];
@@ -575,10 +576,24 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel_update(int n, int kb, int n
   }
 }
 
+// B = (A + A^T) / 2 by 32x32 tiles: tile (I, J) reads the mirror tile (J, I)
+// with rows along the lanes and transposes it through LDS, so both reads and
+// the write are row-contiguous.
 __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __restrict__ B) {
-  const int j = blockIdx.x * kBlock + threadIdx.x, i = blockIdx.y;
-  if (j >= n) return;
-  B[(long long)i * n + j] = 0.5 * (A[(long long)i * n + j] + A[(long long)j * n + i]);
+  __shared__ double mt[32][33];
+  const int i0 = 32 * blockIdx.y, j0 = 32 * blockIdx.x;
+  const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;  // 8 rows of 32 per pass
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {  // mirror tile: A[j0 + r][i0 + c] -> mt[r][c]
+    const int r = r0 + 8 * p;
+    mt[r][c] = (j0 + r < n && i0 + c < n) ? A[(long long)(j0 + r) * n + i0 + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int r = r0 + 8 * p, i = i0 + r, j = j0 + c;
+    if (i < n && j < n) B[(long long)i * n + j] = 0.5 * (A[(long long)i * n + j] + mt[c][r]);
+  }
 }
 
 template <typename T>
@@ -1017,7 +1032,7 @@ void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, 
   *result = buf[cur];
 }
 void launch_symmetrize(int n, const double* A, double* B, hipStream_t s) {
-  k_symmetrize<<<dim3(blocks_for(n), n), kBlock, 0, s>>>(n, A, B);
+  k_symmetrize<<<dim3((n + 31) / 32, (n + 31) / 32), kBlock, 0, s>>>(n, A, B);
 }
 template <typename T>
 void launch_coarse_gemv(int n, const double* Ainv, const T* x, T* y, int nrhs, const int* act, hipStream_t s) {
