@@ -188,6 +188,7 @@ template <typename T>
 __device__ inline void gemv_row(int n, const double* __restrict__ Ainv, const T* __restrict__ x, T* __restrict__ y,
                                 int row, int lane) {
   double s = 0.0;
+#pragma unroll 8
   for (int c = lane; c < n; c += 64) s += Ainv[(long long)row * n + c] * (double)x[c];
   s = wave_sum64(s);
   if (lane == 0) y[row] = (T)s;
