@@ -168,3 +168,157 @@ def test_galerkin_mgpcg_matches_direct():
     h = mg.Hierarchy(16, 8, 8, rho, mask, 3, coarse_operator="galerkin")
     u, its, rel, _ = mg.mgpcg(h, f, rtol=1e-10)
     assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-8
+
+
+# ---- homogenization on non-uniform densities (Sec. 4.2.2, Sec. 6) ---------
+def _mean_of_children(v, nx, ny, nz):
+    """Coarse value of every coarse element as the mean over its eight children,
+    written out with loops (x fastest, as the element numbering)."""
+    out = []
+    for kc in range(nz // 2):
+        for jc in range(ny // 2):
+            for ic in range(nx // 2):
+                s = 0.0
+                for dk in (0, 1):
+                    for dj in (0, 1):
+                        for di in (0, 1):
+                            s += v[(2 * ic + di) + nx * ((2 * jc + dj) + ny * (2 * kc + dk))]
+                out.append(s / 8.0)
+    return np.array(out)
+
+
+def _simp_scalar(r, E0=1.0, Emin=1e-9):
+    # SIMP modulus with p = 3 for one density, as a plain product
+    return Emin + r * r * r * (E0 - Emin)
+
+
+def _coarse_moduli_loops(rho, dims, levels, avg):
+    """Per level, the modulus the re-discretized coarse element carries, by loops:
+    'density' averages the densities over the children and then applies SIMP;
+    'modulus' applies SIMP on the finest level and averages the moduli.  Level l
+    also carries the element-size factor 2^l."""
+    nx, ny, nz = dims
+    r = list(rho)
+    e = [_simp_scalar(v) for v in rho]
+    out = [np.array(e)]
+    for l in range(1, levels):
+        r = list(_mean_of_children(r, nx, ny, nz))
+        e = list(_mean_of_children(e, nx, ny, nz))
+        nx, ny, nz = nx // 2, ny // 2, nz // 2
+        mod = [_simp_scalar(v) for v in r] if avg == "density" else e
+        out.append((1 << l) * np.array(mod))
+    return out
+
+
+def _dense_loops(nx, ny, nz, E, Ke):
+    N = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    K = np.zeros((N, N))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                dofs = []
+                for kk in (0, 1):
+                    for jj in (0, 1):
+                        for ii in (0, 1):
+                            n = (i + ii) + (nx + 1) * ((j + jj) + (ny + 1) * (k + kk))
+                            dofs += [3 * n, 3 * n + 1, 3 * n + 2]
+                K[np.ix_(dofs, dofs)] += E[i + nx * (j + ny * k)] * Ke
+    return K
+
+
+@pytest.mark.parametrize("avg", ["density", "modulus"])
+def test_homogenized_moduli_on_nonuniform_density(avg):
+    """On i.i.d. densities the hierarchy's coarse moduli equal the loop-written
+    rule of its reading (average, then SIMP; or SIMP, then average; times 2^l),
+    and its assembled coarse operator equals the loop-assembled one with the
+    unit element stiffness, these moduli and the injected supports."""
+    from oracle.element import hex8_stiffness
+
+    dims, levels = (8, 8, 8), 3
+    g = W.Grid(*dims)
+    rho = W.iid_uniform_density(g, seed=21, lo=0.01)
+    mask = W.fixed_mask_face_x0(g)
+    h = mg.Hierarchy(*dims, rho, mask, levels, coarse_average=avg)
+    ref = _coarse_moduli_loops(rho, dims, levels, avg)
+    for l in range(levels):
+        assert np.abs(h.E[l] - ref[l]).max() <= 1e-15 * np.abs(ref[l]).max(), l
+    # level 1 operator, 4x4x4 elements, by loops
+    K1 = _dense_loops(4, 4, 4, ref[1], hex8_stiffness(0.3))
+    m1 = W.fixed_mask_face_x0(W.Grid(4, 4, 4))
+    free = np.repeat(m1 == 0, 3).astype(np.float64)
+    A1 = np.diag(free) @ K1 @ np.diag(free) + np.diag(1.0 - free)
+    assert np.abs(h.A[1].toarray() - A1).max() <= 1e-14 * np.abs(A1).max()
+
+
+def test_the_two_averaging_readings_differ():
+    """The two readings give coarse moduli that differ far beyond rounding on a
+    non-uniform density (so the test above would catch a swap), while on a
+    uniform density they coincide."""
+    dims = (8, 8, 8)
+    g = W.Grid(*dims)
+    mask = W.fixed_mask_face_x0(g)
+    rho = W.iid_uniform_density(g, seed=21, lo=0.01)
+    hd = mg.Hierarchy(*dims, rho, mask, 3, coarse_average="density")
+    hm = mg.Hierarchy(*dims, rho, mask, 3, coarse_average="modulus")
+    for l in (1, 2):
+        rel = np.abs(hd.E[l] - hm.E[l]).max() / np.abs(hm.E[l]).max()
+        assert rel > 1e-2, (l, rel)
+        # Jensen: the mean of x^3 is at least the cube of the mean
+        assert np.all(hm.E[l] >= hd.E[l] * (1 - 1e-15))
+    u = np.full(g.n_elem, 0.4)
+    hd = mg.Hierarchy(*dims, u, mask, 3, coarse_average="density")
+    hm = mg.Hierarchy(*dims, u, mask, 3, coarse_average="modulus")
+    for l in (1, 2):
+        assert np.abs(hd.E[l] - hm.E[l]).max() <= 1e-15 * hm.E[l].max()
+
+
+# ---- PCG iterates: Krylov minimisers (Alg. 1) -------------------------------
+def _krylov_minimiser(A, B, f, k):
+    """argmin of x^T A x / 2 - f^T x over span{B f, (B A) B f, ..., (B A)^(k-1) B f},
+    by a dense projection onto an orthonormal basis (Gram-Schmidt applied twice)."""
+    Q = []
+    v = B @ f
+    for _ in range(k):
+        w = v.copy()
+        for _rep in range(2):
+            for q in Q:
+                w -= (q @ w) * q
+        nrm = np.linalg.norm(w)
+        Q.append(w / nrm)
+        v = B @ (A @ v)
+    Q = np.column_stack(Q)
+    return Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ f)
+
+
+def test_pcg_iterates_are_krylov_minimisers_jacobi():
+    """With a fixed SPD preconditioner B, the k-th PCG iterate from x0 = 0 is the
+    A-energy minimiser over the k-dimensional Krylov space of B A and B f; here B
+    is the inverse diagonal, which converges slowly enough for ten steps."""
+    g, rho, h = _hier((6, 2, 2), 1)
+    A = h.A[0].toarray()
+    B = np.diag(1.0 / np.diag(A))
+    f = W.cantilever_line_load(g)
+    for k in range(1, 11):
+        x, its, _, _ = mg.pcg(lambda v: A @ v, f, lambda r: B @ r, fixed_iters=k)
+        xs = _krylov_minimiser(A, B, f, k)
+        e = x - xs
+        assert its == k
+        assert float(e @ A @ e) <= 1e-18 * float(xs @ A @ xs), k
+
+
+def test_mgpcg_iterates_are_krylov_minimisers():
+    """The same property for MGPCG with the V-cycle as B (a fixed linear SPD
+    operator, formed column by column on a small grid), which pins the recurrence
+    behind the fixed-iteration GPU parity cases."""
+    g = W.Grid(8, 4, 4)
+    rho = W.iid_uniform_density(g, seed=5, lo=0.05)
+    h = mg.Hierarchy(8, 4, 4, rho, W.fixed_mask_face_x0(g), 2)
+    n = g.n_dof
+    B = np.column_stack([h.vcycle(np.eye(n)[:, j]) for j in range(n)])
+    A = h.A[0].toarray()
+    f = W.cantilever_line_load(g)
+    for k in range(1, 6):
+        x, its, _, _ = mg.mgpcg(h, f, fixed_iters=k)
+        xs = _krylov_minimiser(A, B, f, k)
+        e = x - xs
+        assert float(e @ A @ e) <= 1e-16 * float(xs @ A @ xs), k
