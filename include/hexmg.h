@@ -53,6 +53,11 @@ extern "C" {
 /* precision of the solver (hexmg_grid_desc.precision) */
 #define HEXMG_FP64 0  /* every step in binary64 */
 #define HEXMG_MIXED 1 /* V-cycle in binary32; CG vectors, dots, outer K p and coarsest solve in binary64 */
+#define HEXMG_MIXED32 2 /* V-cycle and the outer K p in binary32 (a binary32 copy of p, binary32 q);
+                           CG vectors, dots, coarsest solve and compliance in binary64; the
+                           recursive residual is replaced by the binary64 M f - A x every
+                           rr_every iterations, and a solve whose recursive residual meets rtol
+                           while the binary64 one does not restarts CG from its iterate */
 
 /* element type of vectors passed to hexmg_apply_K / hexmg_vcycle */
 #define HEXMG_F64 0
@@ -79,7 +84,7 @@ typedef struct {
                            ny + 1 <= 65535 and nz + 1 <= 65535 */
   int levels;           /* multigrid levels, >= 1; level 0 is the given grid */
   double E0, Emin, nu, penal; /* 1, 1e-9, 0.3, 3 in the paper's examples */
-  int precision;        /* HEXMG_FP64 | HEXMG_MIXED */
+  int precision;        /* HEXMG_FP64 | HEXMG_MIXED | HEXMG_MIXED32 */
   int smooth_sweeps;    /* damped-Jacobi sweeps before and after the coarse correction */
   double omega;         /* Jacobi damping, 0 < omega <= 1 */
   int coarse_avg;       /* HEXMG_AVG_DENSITY | HEXMG_AVG_MODULUS */
@@ -92,11 +97,18 @@ typedef struct {
                            store 243 coefficients per node in both precisions (about
                            2.9 kB per coarse node) and are applied as stencils; the
                            cooperative coarse-cycle launch is not used with them. */
+  int vcycle_both;      /* 0 (default): V-cycle vectors and Jacobi diagonals only in the solver's
+                           precision (binary64 for HEXMG_FP64, binary32 otherwise), so
+                           hexmg_vcycle accepts only that dtype; 1: both precisions (about
+                           twice the V-cycle memory) and hexmg_vcycle accepts either */
+  int rr_every;         /* HEXMG_MIXED32 only: replace the recursive residual by the binary64
+                           one every rr_every iterations (0 = only when rtol is met) */
 } hexmg_grid_desc;
 
 /* Fill *desc with the defaults (E0 1, Emin 1e-9, nu 0.3, penal 3, FP64, 2 sweeps,
  * omega 0.6, density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0,
- * re-discretized coarse operators)
+ * re-discretized coarse operators, V-cycle vectors in the solver's precision only,
+ * residual replacement every 8 iterations)
  * for the given grid.  Host only. */
 int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc *desc);
 
@@ -131,7 +143,9 @@ int hexmg_apply_K(hexmg_grid_t grid, int level, int dtype, const void *u, void *
 /* z = V(r): one multigrid V-cycle (Alg. 3) on the finest level from a zero
  * initial guess, damped-Jacobi smoothing (Eq. 21), trilinear prolongation P,
  * restriction P^T, direct coarsest solve.  dtype HEXMG_F64 runs every level in
- * binary64, HEXMG_F32 in binary32 (coarsest solve in binary64 either way). */
+ * binary64, HEXMG_F32 in binary32 (coarsest solve in binary64 either way).
+ * Returns -1 for a dtype whose V-cycle vectors the grid does not hold (see
+ * hexmg_grid_desc.vcycle_both). */
 int hexmg_vcycle(hexmg_grid_t grid, int dtype, const void *r, void *z, int nrhs,
                  void *stream);
 
@@ -151,7 +165,11 @@ typedef struct {
  * (one kernel launch covers all of them; each stops on its own criterion);
  * more are taken in blocks of max_nrhs.  info: host array of nrhs entries (may
  * be NULL).  Synchronises the stream.  Returns 1 if some right-hand side did
- * not converge, -5 on breakdown (p^T A p <= 0). */
+ * not converge, -5 on breakdown (p^T A p <= 0).  With HEXMG_MIXED32 the outer
+ * product A p runs in binary32 and the recursive residual is replaced by the
+ * binary64 one every rr_every iterations; when the recursive residual meets
+ * rtol but the binary64 one does not, CG restarts from the current iterate
+ * (at most 8 times; iterations keep counting towards maxit). */
 int hexmg_solve(hexmg_grid_t grid, const double *f, double *u, int nrhs, double rtol,
                 int maxit, hexmg_solve_info *info, void *stream);
 

@@ -60,7 +60,10 @@ int validate(const hexmg_grid_desc* d) {
     return fail(HEXMG_ERR_INVALID, "need 0 < Emin < E0 < inf");
   if (!(d->nu > -1.0 && d->nu < 0.5)) return fail(HEXMG_ERR_INVALID, "need -1 < nu < 0.5");
   if (!(d->penal >= 1.0 && d->penal <= 16.0)) return fail(HEXMG_ERR_INVALID, "need 1 <= penal <= 16");
-  if (d->precision != HEXMG_FP64 && d->precision != HEXMG_MIXED) return fail(HEXMG_ERR_INVALID, "bad precision");
+  if (d->precision != HEXMG_FP64 && d->precision != HEXMG_MIXED && d->precision != HEXMG_MIXED32)
+    return fail(HEXMG_ERR_INVALID, "bad precision");
+  if (d->vcycle_both != 0 && d->vcycle_both != 1) return fail(HEXMG_ERR_INVALID, "vcycle_both must be 0 or 1");
+  if (d->rr_every < 0) return fail(HEXMG_ERR_INVALID, "rr_every must be >= 0");
   if (d->smooth_sweeps < 1 || d->smooth_sweeps > 64) return fail(HEXMG_ERR_INVALID, "smooth_sweeps in [1,64]");
   if (!(d->omega > 0.0 && d->omega <= 1.0)) return fail(HEXMG_ERR_INVALID, "need 0 < omega <= 1");
   if (d->coarse_avg != HEXMG_AVG_DENSITY && d->coarse_avg != HEXMG_AVG_MODULUS)
@@ -110,23 +113,31 @@ size_t carve(hexmg_grid* g, char* base) {
   g->vt32.assign(L, nullptr);
   g->vr32.assign(L, nullptr);
   const size_t R = (size_t)g->desc.max_nrhs;
+  // V-cycle vectors and Jacobi diagonals in the solver's precision, and in the
+  // other one only when the descriptor asks for both.
+  const bool v64 = g->desc.precision == HEXMG_FP64 || g->desc.vcycle_both;
+  const bool v32 = g->desc.precision != HEXMG_FP64 || g->desc.vcycle_both;
   for (int l = 0; l < L; ++l) {
     const Level& lv = g->lv[l];
     const size_t N = 3ull * lv.nn;
     g->rho[l] = c.take<double>(lv.ne);
     g->E64[l] = c.take<double>(lv.ne);
     g->E32[l] = c.take<float>(lv.ne);
-    g->wd64[l] = c.take<double>(N);
-    g->wd32[l] = c.take<float>(N);
     g->mask[l] = c.take<uint8_t>(lv.nn);
-    g->vf64[l] = c.take<double>(N * R);
-    g->vu64[l] = c.take<double>(N * R);
-    g->vt64[l] = c.take<double>(N * R);
-    g->vr64[l] = c.take<double>(N * R);
-    g->vf32[l] = c.take<float>(N * R);
-    g->vu32[l] = c.take<float>(N * R);
-    g->vt32[l] = c.take<float>(N * R);
-    g->vr32[l] = c.take<float>(N * R);
+    if (v64) {
+      g->wd64[l] = c.take<double>(N);
+      g->vf64[l] = c.take<double>(N * R);
+      g->vu64[l] = c.take<double>(N * R);
+      g->vt64[l] = c.take<double>(N * R);
+      g->vr64[l] = c.take<double>(N * R);
+    }
+    if (v32) {
+      g->wd32[l] = c.take<float>(N);
+      g->vf32[l] = c.take<float>(N * R);
+      g->vu32[l] = c.take<float>(N * R);
+      g->vt32[l] = c.take<float>(N * R);
+      g->vr32[l] = c.take<float>(N * R);
+    }
   }
   const size_t nc = 3ull * g->lv[L - 1].nn;
   g->nc = (int)nc;
@@ -142,11 +153,15 @@ size_t carve(hexmg_grid* g, char* base) {
   g->z = g->desc.precision == HEXMG_FP64 ? c.take<double>(N0 * R) : nullptr;
   g->p = c.take<double>(N0 * R);
   g->q = c.take<double>(N0 * R);
+  // binary32 copy of p and binary32 q for the binary32 outer K p
+  g->p32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
+  g->q32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
   g->partials = c.take<double>((size_t)kMaxDotParts * R);  // >= kReduceBlocks
   g->partials2 = c.take<double>(kReduceBlocks * R);
   g->scalars = c.take<double>(kScalars * R);
   g->flags = c.take<int>(kReduceBlocks + 1);
   g->active = c.take<int>(R);
+  g->repl = c.take<int>(R);
   g->oc_partials = c.take<double>((size_t)kReduceBlocks * kOcProbes);
   g->oc_vol = c.take<double>(kOcProbes);
   g->galerkin = g->desc.coarse_op == HEXMG_COARSE_GALERKIN && L > 1;
@@ -218,13 +233,15 @@ void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int le
 // three modes (K u, damped-Jacobi sweep, residual; zero vectors, the level's
 // own scratch buffers) and keeps the fastest per mode.  The streaming kernel
 // is kept unless the node-gather is more than 5% faster.
+// modes: how many of the three modes to time (1 = K u only; f and wd may then
+// be null).
 template <typename T>
 int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::array<hexmg_grid::Choice, 3>* out,
-               hipStream_t s) {
+               hipStream_t s, int modes = 3) {
   const Level& L = g->lv[level];
   const size_t bytes = 3ull * L.nn * sizeof(T);
   HIP_TRY(hipMemsetAsync(u, 0, bytes, s));
-  HIP_TRY(hipMemsetAsync(f, 0, bytes, s));
+  if (f) HIP_TRY(hipMemsetAsync(f, 0, bytes, s));
   const bool f32 = sizeof(T) == 4;
   std::vector<hexmg_grid::Choice> cand;
   for (int sh = 0; sh < stream_shapes(f32); ++sh)
@@ -235,7 +252,7 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  for (int mode = 0; mode < 3; ++mode) {
+  for (int mode = 0; mode < modes; ++mode) {
     float best_stream = 1e30f, best_gather = 1e30f;
     hexmg_grid::Choice bs{HEXMG_KERNEL_STREAM, 4, 0};
     // small levels run for a few microseconds per launch: more repetitions
@@ -263,10 +280,20 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
   return 0;
 }
 
+// Every level and mode of the precisions whose V-cycle vectors the grid holds
+// (they serve as scratch); without binary64 ones, the level-0 binary64 K u
+// (outer product and true residual) on the CG vectors p and q.
 int tune_kernels(hexmg_grid* g, hipStream_t s) {
   for (int l = 0; l < (g->galerkin ? 1 : g->L); ++l) {
-    if (int e = tune_level<double>(g, l, g->vu64[l], g->vf64[l], g->vt64[l], g->wd64[l], &g->choice64[l], s)) return e;
-    if (int e = tune_level<float>(g, l, g->vu32[l], g->vf32[l], g->vt32[l], g->wd32[l], &g->choice32[l], s)) return e;
+    if (g->vu64[l]) {
+      if (int e = tune_level<double>(g, l, g->vu64[l], g->vf64[l], g->vt64[l], g->wd64[l], &g->choice64[l], s))
+        return e;
+    } else if (l == 0) {
+      if (int e = tune_level<double>(g, 0, g->p, nullptr, g->q, nullptr, &g->choice64[0], s, 1)) return e;
+    }
+    if (g->vu32[l])
+      if (int e = tune_level<float>(g, l, g->vu32[l], g->vf32[l], g->vt32[l], g->wd32[l], &g->choice32[l], s))
+        return e;
   }
   g->tuned = true;
   return 0;
@@ -450,6 +477,7 @@ int tune_tail(hexmg_grid* g, hipStream_t s) {
   tblocks = 0;
   const int maxb = coarse_cycle_max_blocks<T>();
   if (g->L < 3 || maxb <= 0 || g->galerkin) return 0;
+  if ((f32 ? (const void*)g->vu32[0] : (const void*)g->vu64[0]) == nullptr) return 0;  // precision not held
   VView<T> v = [&] {
     if constexpr (sizeof(T) == 4)
       return view32(g);
@@ -578,6 +606,8 @@ int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc* d) {
   d->max_nrhs = 1;
   d->kernel = HEXMG_KERNEL_AUTO;
   d->fixed_mask = nullptr;
+  d->vcycle_both = 0;
+  d->rr_every = 8;
   return 0;
 }
 
@@ -677,6 +707,11 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
 
 int hexmg_grid_destroy(hexmg_grid_t g) {
   if (!g) return 0;
+  // Work queued on the library's own streams (the coarsest inverse on the
+  // auxiliary stream, a batched solve's stream) still writes the caller's
+  // workspace: let it finish before the caller may reuse that memory.
+  if (g->aux_stream) (void)hipStreamSynchronize(g->aux_stream);
+  if (g->own_stream) (void)hipStreamSynchronize(g->own_stream);
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
   if (g->aux_stream) (void)hipStreamDestroy(g->aux_stream);
   for (hipEvent_t e : {g->ev_fork, g->ev_coarse, g->ev_flag, g->ev_read})
@@ -820,6 +855,8 @@ int hexmg_vcycle(hexmg_grid_t g, int dtype, const void* r, void* z, int nrhs, vo
   g->last_stream = s;
   const long long N = 3ll * g->lv[0].nn;
   if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
+  if ((dtype == HEXMG_F64 ? (const void*)g->vu64[0] : (const void*)g->vu32[0]) == nullptr)
+    return fail(HEXMG_ERR_INVALID, "the grid holds no V-cycle vectors of this dtype (create it with vcycle_both = 1)");
   for (int k = 0; k < nrhs; k += g->desc.max_nrhs) {
     const int nb = (nrhs - k) < g->desc.max_nrhs ? (nrhs - k) : g->desc.max_nrhs;
     if (dtype == HEXMG_F64) {
@@ -857,6 +894,10 @@ struct PcgRun {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
   enum Phase { kIterate, kFinish, kDone } phase = kIterate;
   int issued = 0, target = 0, final_slot = 0, status = 0;
+  int limit = 0;    // host iteration number the run may not pass (maxit, moved by restarts)
+  int tag_off = 0;  // host iteration number minus the device's, for profile tags after a restart
+  int restarts = 0;
+  std::vector<int> its_off;  // per right-hand side: host iteration number minus 1 minus its iterations so far
   std::vector<double> prev_rr;  // ||r||^2 of the last iteration read, per right-hand side
 
   int init() {
@@ -888,30 +929,60 @@ struct PcgRun {
   }
   // iteration k (1-based): q = A p, alpha, the r update (its x update follows
   // in the next p update, or at the end), ||r||^2 and the test
+  bool m32() const { return g->desc.precision == HEXMG_MIXED32; }
   int issue_iteration(int k) {
     double* sc = g->scalars;
-    g->prof_tag = k;
+    g->prof_tag = k - tag_off;
     // q = A p, with p . q formed inside the streaming kernel when it is the
     // level-0 choice and its workgroups are few enough; else a separate pass
-    const hexmg_grid::Choice& ch = g->choice64[0][kApply];
+    const bool f32 = m32();
+    const hexmg_grid::Choice& ch = (f32 ? g->choice32 : g->choice64)[0][kApply];
     int npq = 0;
     if (ch.kernel == HEXMG_KERNEL_STREAM) {
-      const int nbk = stream_blocks(g->lv[0], false, ch.shape, ch.zchunk);
+      const int nbk = stream_blocks(g->lv[0], f32, ch.shape, ch.zchunk);
       if (nbk <= kMaxDotParts) npq = nbk;
     }
-    gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active, npq ? g->partials : nullptr);
+    if (f32)
+      gather<float>(g, kApply, 0, g->p32, nullptr, nullptr, g->q32, nb, s, false, g->active,
+                    npq ? g->partials : nullptr);
+    else
+      gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active,
+                     npq ? g->partials : nullptr);
     if (!npq) {
-      launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
+      if (f32)
+        launch_dot_mixed(N(), g->q32, g->p, g->partials, nb, g->active, s);
+      else
+        launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
       npq = kReduceBlocks;
     }
     // r -= alpha q with the next preconditioner's first sweep (x += alpha p follows in the p update)
     const bool sweep = g->L > 1;
-    if (g->desc.precision == HEXMG_FP64)
-      launch_update_r_first<double>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2, (k - 1) & 1,
-                                    g->wd64[0], nullptr, sweep ? g->vt64[0] : nullptr, nb, s);
-    else
-      launch_update_r_first<float>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2, (k - 1) & 1,
-                                   g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr, nb, s);
+    if (g->desc.precision == HEXMG_FP64) {
+      launch_update_r_first<double, double>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2,
+                                            (k - 1) & 1, g->wd64[0], nullptr, sweep ? g->vt64[0] : nullptr, nb, s);
+    } else if (!f32) {
+      launch_update_r_first<float, double>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2,
+                                           (k - 1) & 1, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr, nb, s);
+    } else {
+      // binary32 A p; every rr_every-th iteration of a right-hand side its
+      // residual is replaced by the binary64 M f - A x (x brought up to date
+      // first).  The device decides per right-hand side from its own
+      // iteration count (flags in repl); the host launches the replacement
+      // kernels only in iterations where some right-hand side may need them.
+      const int every = g->desc.rr_every;
+      bool replace = false;
+      for (int r = 0; r < nb && every > 0; ++r) replace = replace || (k - its_off[r]) % every == 0;
+      if (replace) launch_replace_flags(sc, g->active, g->repl, nb, every, s);
+      launch_update_r_first<float, float>(N(), g->partials, npq, sc, g->active, g->q32, g->r, g->partials2,
+                                          (k - 1) & 1, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr, nb, s,
+                                          replace ? g->repl : nullptr);
+      if (replace) {
+        launch_flush_x(N(), sc, g->p, u, nb, s, g->repl);
+        gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s, false, g->repl);
+        launch_replace_r(g->lv[0], f, g->q, g->r, g->partials2, g->wd32[0], g->vf32[0],
+                         sweep ? g->vt32[0] : nullptr, sc, g->repl, nb, s);
+      }
+    }
     launch_rr_check(g->partials2, sc, g->active, slot(k), nb, s);
     issued = k;
     return post(k, false);
@@ -920,14 +991,14 @@ struct PcgRun {
   // and p = z + beta p, then iteration k+1
   int issue_next() {
     const int k = issued;
-    g->prof_tag = k + 1;
+    g->prof_tag = k + 1 - tag_off;
     if (g->desc.precision == HEXMG_FP64) {
       const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, true, true, true);
       launch_update_px<double>(N(), g->partials, nrz, g->scalars, g->active, g->z, g->p, u, (k - 1) & 1, nb, s);
     } else {
       const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, false, true, true);
       launch_update_px<float>(N(), g->partials, nrz, g->scalars, g->active, g->vu32[0], g->p, u, (k - 1) & 1, nb,
-                              s);
+                              s, m32() ? g->p32 : nullptr);
     }
     return issue_iteration(k + 1);
   }
@@ -935,6 +1006,8 @@ struct PcgRun {
     const Level& L0 = g->lv[0];
     double* sc = g->scalars;
     prev_rr.assign(nb, 0.0);
+    its_off.assign(nb, 0);
+    limit = maxit;
     HIP_TRY(hipEventRecord(t0, s));
     launch_pcg_start(L0, f, g->r, u, g->partials, nb, s);  // r0 = M f, x0 = 0, ||r0||^2 partials
     launch_pcg_init(rtol > 0.0 ? rtol * rtol : -1.0, g->partials, sc, g->active, nb, s);
@@ -942,11 +1015,48 @@ struct PcgRun {
     g->prof_tag = 1;
     precondition(g, g->r, g->p, g->partials, nb, g->active, s);  // p0 = z0 = M^{-1} r0
     launch_reduce_final(g->partials, sc + kRz0, kScalars, nb, s);
+    if (m32()) launch_f64_to_f32(N(), g->p, g->p32, nb, g->active, s);
     if (int e = issue_iteration(1)) return e;
     if (maxit >= 2)
       if (int e = issue_next()) return e;
     target = 1;
     phase = kIterate;
+    return 0;
+  }
+  // HEXMG_MIXED32: CG restarted from the current iterate for the right-hand
+  // sides whose binary64 residual (just computed by the finish, A x in q)
+  // misses the test although the recursive one met it: r = M f - A x,
+  // z = M^{-1} r, p = z, then iterations continue.  h: the finish's scalars.
+  int restart(const double* h) {
+    double* sc = g->scalars;
+    int its_min = maxit;
+    const int k1 = issued + 1;
+    for (int k = 0; k < nb; ++k) {
+      const double* q = h + k * kScalars;
+      if (q[kStatus] == 0.0 && q[kTmp] > q[kStop] && q[kIts] < maxit) {
+        its_min = std::min(its_min, (int)q[kIts]);
+        its_off[k] = k1 - 1 - (int)q[kIts];
+      }
+    }
+    int last_its = 0;
+    for (int k = 0; k < nb; ++k) last_its = std::max(last_its, (int)h[k * kScalars + kIts]);
+    ++restarts;
+    tag_off = issued - last_its;
+    limit = issued + (maxit - its_min);
+    launch_pcg_restart(sc, g->active, nb, maxit, s);
+    const bool sweep = g->L > 1;
+    launch_replace_r(g->lv[0], f, g->q, g->r, g->partials2, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr,
+                     sc, g->active, nb, s);
+    g->prof_tag = k1 - tag_off;
+    precondition(g, g->r, g->p, g->partials, nb, g->active, s, true, true);  // p = z = M^{-1} r
+    launch_reduce_final(g->partials, sc + kRz0 + ((k1 - 1) & 1), kScalars, nb, s);
+    launch_f64_to_f32(N(), g->p, g->p32, nb, g->active, s);
+    if (int e = issue_iteration(k1)) return e;
+    if (k1 + 1 <= limit)
+      if (int e = issue_next()) return e;
+    target = k1;
+    phase = kIterate;
+    for (int k = 0; k < nb; ++k) prev_rr[k] = 0.0;
     return 0;
   }
   int enqueue_finish(int read) {
@@ -979,11 +1089,11 @@ struct PcgRun {
       const double* h = slot(target);
       int nact = 0;
       for (int k = 0; k < nb; ++k) nact += h[k * kScalars + kActive] != 0.0;
-      if (nact == 0 || target >= maxit) return enqueue_finish(target);
+      if (nact == 0 || target >= limit) return enqueue_finish(target);
       // keep one iteration in flight beyond the one waited for, unless that
       // one is expected to be the last
       const bool last = predict_last(h);
-      while (issued < maxit && issued < target + 2 && !(issued == target + 1 && last))
+      while (issued < limit && issued < target + 2 && !(issued == target + 1 && last))
         if (int e = issue_next()) return e;
       for (int k = 0; k < nb; ++k) prev_rr[k] = h[k * kScalars + kRr];
       ++target;
@@ -998,6 +1108,14 @@ struct PcgRun {
     int last_its = 0;
     for (int k = 0; k < nb; ++k) last_its = std::max(last_its, (int)h[k * kScalars + kIts]);
     prune_profile(g, last_its);
+    if (m32() && restarts < 8) {  // binary64 residual short of the test: continue from x
+      bool any = false;
+      for (int k = 0; k < nb; ++k) {
+        const double* q = h + k * kScalars;
+        any = any || (q[kStatus] == 0.0 && q[kTmp] > q[kStop] && q[kIts] < maxit);
+      }
+      if (any) return restart(h);
+    }
     for (int k = 0; k < nb; ++k) {
       const double* q = h + k * kScalars;
       const int st = (int)q[kStatus];

@@ -214,8 +214,8 @@ __global__ void k_stencil_diag(Level L, const double* __restrict__ S, double ome
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double w = omega / S[(long long)(9 * 13 + 4 * c) * L.nn + n];
-    wd64[3ll * n + c] = w;
-    wd32[3ll * n + c] = (float)w;
+    if (wd64) wd64[3ll * n + c] = w;  // either output may be absent
+    if (wd32) wd32[3ll * n + c] = (float)w;
   }
 }
 

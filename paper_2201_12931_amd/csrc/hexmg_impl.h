@@ -142,10 +142,23 @@ void launch_pcg_final(const Level& L, const double* f, const double* q, const do
 // are also npq apart); r -= alpha q; rr partials; the first Jacobi sweep from
 // zero t = wdinv * r (mixed: on the binary32 copy f32 of r; t may be null);
 // x += alpha p is left to launch_update_px / launch_flush_x (s[kXPend])
-template <typename TW>
+// (q in binary64, or the binary32 A p of HEXMG_MIXED32; repl, may be null:
+// right-hand sides that get only alpha and s[kXPend], their residual being
+// replaced right after)
+template <typename TW, typename TQ>
 void launch_update_r_first(long long n, const double* pq_partials, int npq, double* sc, const int* active,
-                           const double* q, double* r, double* rr_partials, int parity, const TW* wdinv, float* f32,
-                           TW* t, int nrhs, hipStream_t s);
+                           const TQ* q, double* r, double* rr_partials, int parity, const TW* wdinv, float* f32,
+                           TW* t, int nrhs, hipStream_t s, const int* repl = nullptr);
+// repl[r] = active[r] and (iterations of r so far + 1) divisible by every
+void launch_replace_flags(const double* sc, const int* active, int* repl, int nrhs, int every, hipStream_t s);
+// residual replacement after q = A x (binary64, x complete): r = M f - q, rr
+// partials, binary32 copy of r and first sweep t (may be null); clears s[kXPend]
+void launch_replace_r(const Level& L, const double* f, const double* q, double* r, double* rr_partials,
+                      const float* wdinv, float* f32, float* t, double* sc, const int* active, int nrhs,
+                      hipStream_t s);
+// after the finish of a HEXMG_MIXED32 solve (binary64 residual in s[kTmp]):
+// reactivate the right-hand sides whose binary64 residual misses the test
+void launch_pcg_restart(double* sc, int* active, int nrhs, int maxit, hipStream_t s);
 // rr = sum of partials; its += 1; convergence / breakdown clears active; the
 // scalars of every right-hand side are written to host_slot (pinned host memory)
 void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
@@ -153,11 +166,13 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
 // rz_new = sum of the nrz rz partials of a right-hand side (nrz apart);
 // beta = rz_new / rz[parity]; x += alpha p (the previous iteration's);
 // p = z + beta p; rz[1-parity] = rz_new
+// (x += alpha p only while s[kXPend]; p32, may be null: binary32 copy of the new p)
 template <typename TZ>
 void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
-                      double* p, double* x, int parity, int nrhs, hipStream_t s);
+                      double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32 = nullptr);
 // x += alpha p for the right-hand sides where it is still due (s[kXPend])
-void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s);
+void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s,
+                    const int* act = nullptr);
 // partials of r . (double) u32 (the binary32 V-cycle output, not widened in memory)
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s);
@@ -295,11 +310,13 @@ struct hexmg_grid {
   bool tuned;
   // PCG
   double *r, *z, *p, *q;
+  float *p32, *q32;  // binary32 p and A p of HEXMG_MIXED32 (else null)
   double* partials;
   double* partials2;
   double* scalars;
   int* flags;     // per-block status flags (kReduceBlocks) + 1 result
   int* active;    // per right-hand side: 1 while its CG iteration runs
+  int* repl;      // per right-hand side: 1 where this iteration replaces the residual (HEXMG_MIXED32)
   double* host_ring;  // pinned: 3 slots of kScalars * max_nrhs doubles (results in flight)
   double* oc_partials;  // kReduceBlocks x kOcProbes
   double* oc_vol;       // kOcProbes

@@ -221,12 +221,16 @@ __global__ void k_diag(Level L, const double* __restrict__ Ke, const double* __r
   const double w0 = omega / ((mk & 1) ? 1.0 : d0);
   const double w1 = omega / ((mk & 2) ? 1.0 : d1);
   const double w2 = omega / ((mk & 4) ? 1.0 : d2);
-  wd64[3ll * n] = w0;
-  wd64[3ll * n + 1] = w1;
-  wd64[3ll * n + 2] = w2;
-  wd32[3ll * n] = (float)w0;
-  wd32[3ll * n + 1] = (float)w1;
-  wd32[3ll * n + 2] = (float)w2;
+  if (wd64) {  // either output may be absent (the grid holds one precision)
+    wd64[3ll * n] = w0;
+    wd64[3ll * n + 1] = w1;
+    wd64[3ll * n + 2] = w2;
+  }
+  if (wd32) {
+    wd32[3ll * n] = (float)w0;
+    wd32[3ll * n + 1] = (float)w1;
+    wd32[3ll * n + 2] = (float)w2;
+  }
 }
 
 __global__ void k_mask_default(Level L, uint8_t* __restrict__ mask) {
@@ -718,12 +722,16 @@ __global__ void k_pcg_final_sums(const double* __restrict__ pa, const double* __
 // r, written to f32).  t may be null (no sweep: the coarsest level is the
 // whole grid).  The matching x += alpha p is left to k_update_px, or to
 // k_flush_x when the solve stops; s[kXPend] records whether it is due.
-template <typename TW>
+// TQ: q in binary64, or the binary32 A p of the binary32 outer product
+// (widened on the fly).  repl (may be null): right-hand sides whose flag is
+// set get only alpha and the pending flag (their residual is replaced right
+// after, see k_replace_r).
+template <typename TW, typename TQ>
 __global__ void k_update_r_first(long long n, const double* __restrict__ pq_partials, int npq,
                                  double* __restrict__ sc, const int* __restrict__ active,
-                                 const double* __restrict__ q, double* __restrict__ r,
+                                 const TQ* __restrict__ q, double* __restrict__ r,
                                  double* __restrict__ rr_partials, int parity, const TW* __restrict__ wdinv,
-                                 float* __restrict__ f32, TW* __restrict__ t) {
+                                 float* __restrict__ f32, TW* __restrict__ t, const int* __restrict__ repl) {
   const int rhs = blockIdx.y;
   rr_partials += (long long)kReduceBlocks * rhs;
   if (!active[rhs]) {
@@ -741,7 +749,7 @@ __global__ void k_update_r_first(long long n, const double* __restrict__ pq_part
     s[kAlpha] = alpha;
     s[kXPend] = ok ? 1.0 : 0.0;
   }
-  if (!ok) {  // breakdown: keep the previous iterate; the check flags it
+  if (!ok || (repl && repl[rhs])) {  // breakdown: keep the previous iterate; the check flags it
     if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
     return;
   }
@@ -753,7 +761,7 @@ __global__ void k_update_r_first(long long n, const double* __restrict__ pq_part
   double acc = 0.0;
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
-    const double ri = r[i] - alpha * q[i];
+    const double ri = r[i] - alpha * (double)q[i];
     r[i] = ri;
     acc += ri * ri;
     if constexpr (sizeof(TW) == 4) {
@@ -808,10 +816,12 @@ __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __res
 // iteration's x += alpha p (always due while the right-hand side is active:
 // a breakdown clears the flag), then p = z + beta p.  z in binary64, or the
 // binary32 V-cycle output widened on the fly.
+// The x update is skipped when s[kXPend] is 0 (a residual replacement has
+// already applied it); p32 (may be null) receives a binary32 copy of the new p.
 template <typename TZ>
 __global__ void k_update_px(long long n, const double* __restrict__ rz_partials, int nrz, double* __restrict__ sc,
                             const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
-                            double* __restrict__ x, int parity) {
+                            double* __restrict__ x, int parity, float* __restrict__ p32) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
   double rzs = 0.0;
@@ -819,7 +829,7 @@ __global__ void k_update_px(long long n, const double* __restrict__ rz_partials,
   const double rz = block_sum_all(rzs);
   double* s = sc + kScalars * rhs;
   const double beta = rz / s[kRz0 + parity];
-  const double alpha = s[kAlpha];
+  const double alpha = s[kXPend] != 0.0 ? s[kAlpha] : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s[kRz0 + 1 - parity] = rz;
     s[kBeta] = beta;
@@ -828,6 +838,18 @@ __global__ void k_update_px(long long n, const double* __restrict__ rz_partials,
   z += off;
   p += off;
   x += off;
+  if (p32) {
+    p32 += off;
+#pragma unroll 4
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+      const double pi = p[i];
+      x[i] += alpha * pi;
+      const double pn = (double)z[i] + beta * pi;
+      p[i] = pn;
+      p32[i] = (float)pn;
+    }
+    return;
+  }
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     const double pi = p[i];
@@ -836,12 +858,78 @@ __global__ void k_update_px(long long n, const double* __restrict__ rz_partials,
   }
 }
 
+// grid (kReduceBlocks, nrhs), residual replacement after q = A x in binary64
+// (x complete, its pending update already applied): r = M f - q, the partials
+// of ||r||^2 (the order of k_dot_partial), the binary32 copy of r and the
+// preconditioner's first sweep t = omega D^-1 r (t may be null); clears
+// s[kXPend].  Right-hand sides whose flag is 0 are skipped.
+__global__ void k_replace_r(Level L, const double* __restrict__ f, const double* __restrict__ q,
+                            double* __restrict__ r, double* __restrict__ rr_partials, const float* __restrict__ wdinv,
+                            float* __restrict__ f32, float* __restrict__ t, double* __restrict__ sc,
+                            const int* __restrict__ active) {
+  const int rhs = blockIdx.y;
+  rr_partials += (long long)kReduceBlocks * rhs;
+  if (!active[rhs]) {
+    if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[kScalars * rhs + kXPend] = 0.0;
+  const long long n = 3ll * L.nn;
+  const long long off = n * rhs;
+  f += off;
+  q += off;
+  r += off;
+  f32 += off;
+  if (t) t += off;
+  double acc = 0.0;
+#pragma unroll 4
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    const int node = (int)(i / 3), c = (int)(i % 3);
+    const double ri = (((L.mask[node] >> c) & 1) ? 0.0 : f[i]) - q[i];
+    r[i] = ri;
+    acc += ri * ri;
+    const float fv = (float)ri;
+    f32[i] = fv;
+    if (t) t[i] = wdinv[i] * fv;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) rr_partials[blockIdx.x] = acc;
+}
+
+// One thread per right-hand side: repl = the right-hand side is active and
+// the iteration about to run is a multiple of every (its iterations so far + 1).
+__global__ void k_replace_flags(const double* __restrict__ sc, const int* __restrict__ active,
+                                int* __restrict__ repl, int nrhs, int every) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  const long long next = (long long)sc[kScalars * rhs + kIts] + 1;
+  repl[rhs] = (active[rhs] && next % every == 0) ? 1 : 0;
+}
+
+// One thread per right-hand side, after the binary64 residual of a finished
+// solve is in s[kTmp]: a right-hand side whose recursive residual met the
+// test while the binary64 one does not (and that has iterations left) is
+// restarted: active again, status 1, ||r||^2 = that residual.
+__global__ void k_pcg_restart(double* __restrict__ sc, int* __restrict__ active, int nrhs, int maxit) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  double* s = sc + kScalars * rhs;
+  const bool again = s[kStatus] == 0.0 && s[kTmp] > s[kStop] && s[kIts] < maxit;
+  active[rhs] = again ? 1 : 0;
+  s[kActive] = again ? 1.0 : 0.0;
+  if (again) {
+    s[kStatus] = 1.0;
+    s[kRr] = s[kTmp];
+  }
+}
+
 // grid (kReduceBlocks, nrhs): the x += alpha p still due when the solve stops
+// (act, may be null: only the right-hand sides whose flag is set)
 __global__ void k_flush_x(long long n, const double* __restrict__ sc, const double* __restrict__ p,
-                          double* __restrict__ x) {
+                          double* __restrict__ x, const int* __restrict__ act) {
   const int rhs = blockIdx.y;
   const double* s = sc + kScalars * rhs;
-  if (s[kXPend] == 0.0) return;
+  if (s[kXPend] == 0.0 || (act && !act[rhs])) return;
   const double alpha = s[kAlpha];
   const long long off = n * rhs;
   p += off;
@@ -1061,17 +1149,33 @@ void launch_pcg_final(const Level& L, const double* f, const double* q, const do
   k_pcg_final_dots<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(L, f, q, x, pa, pb);
   k_pcg_final_sums<<<dim3(nrhs, 2), kBlock, 0, s>>>(pa, pb, sc);
 }
-template <typename TW>
+template <typename TW, typename TQ>
 void launch_update_r_first(long long n, const double* pq_partials, int npq, double* sc, const int* active,
-                           const double* q, double* r, double* rr_partials, int parity, const TW* wdinv, float* f32,
-                           TW* t, int nrhs, hipStream_t s) {
-  k_update_r_first<TW><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, npq, sc, active, q, r,
-                                                                     rr_partials, parity, wdinv, f32, t);
+                           const TQ* q, double* r, double* rr_partials, int parity, const TW* wdinv, float* f32,
+                           TW* t, int nrhs, hipStream_t s, const int* repl) {
+  k_update_r_first<TW, TQ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, pq_partials, npq, sc, active, q, r,
+                                                                         rr_partials, parity, wdinv, f32, t, repl);
 }
-template void launch_update_r_first<double>(long long, const double*, int, double*, const int*, const double*,
-                                            double*, double*, int, const double*, float*, double*, int, hipStream_t);
-template void launch_update_r_first<float>(long long, const double*, int, double*, const int*, const double*,
-                                           double*, double*, int, const float*, float*, float*, int, hipStream_t);
+template void launch_update_r_first<double, double>(long long, const double*, int, double*, const int*,
+                                                    const double*, double*, double*, int, const double*, float*,
+                                                    double*, int, hipStream_t, const int*);
+template void launch_update_r_first<float, double>(long long, const double*, int, double*, const int*,
+                                                   const double*, double*, double*, int, const float*, float*,
+                                                   float*, int, hipStream_t, const int*);
+template void launch_update_r_first<float, float>(long long, const double*, int, double*, const int*,
+                                                  const float*, double*, double*, int, const float*, float*, float*,
+                                                  int, hipStream_t, const int*);
+void launch_replace_flags(const double* sc, const int* active, int* repl, int nrhs, int every, hipStream_t s) {
+  k_replace_flags<<<(nrhs + 63) / 64, 64, 0, s>>>(sc, active, repl, nrhs, every);
+}
+void launch_replace_r(const Level& L, const double* f, const double* q, double* r, double* rr_partials,
+                      const float* wdinv, float* f32, float* t, double* sc, const int* active, int nrhs,
+                      hipStream_t s) {
+  k_replace_r<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(L, f, q, r, rr_partials, wdinv, f32, t, sc, active);
+}
+void launch_pcg_restart(double* sc, int* active, int nrhs, int maxit, hipStream_t s) {
+  k_pcg_restart<<<(nrhs + 63) / 64, 64, 0, s>>>(sc, active, nrhs, maxit);
+}
 
 void launch_rr_check(const double* rr_partials, double* sc, int* active, double* host_slot, int nrhs,
                      hipStream_t s) {
@@ -1079,15 +1183,17 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
 }
 template <typename TZ>
 void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
-                      double* p, double* x, int parity, int nrhs, hipStream_t s) {
-  k_update_px<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, nrz, sc, active, z, p, x, parity);
+                      double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32) {
+  k_update_px<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, nrz, sc, active, z, p, x, parity,
+                                                                p32);
 }
 template void launch_update_px<double>(long long, const double*, int, double*, const int*, const double*, double*,
-                                       double*, int, int, hipStream_t);
+                                       double*, int, int, hipStream_t, float*);
 template void launch_update_px<float>(long long, const double*, int, double*, const int*, const float*, double*,
-                                      double*, int, int, hipStream_t);
-void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s) {
-  k_flush_x<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x);
+                                      double*, int, int, hipStream_t, float*);
+void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s,
+                    const int* act) {
+  k_flush_x<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x, act);
 }
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s) {

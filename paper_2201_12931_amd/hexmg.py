@@ -8,9 +8,11 @@ raises immediately -- there is no fallback implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -19,7 +21,7 @@ HEADER = os.path.join(ROOT, "include", "hexmg.h")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_WORKSPACE, ERR_DEVICE, ERR_NONFINITE, ERR_BREAKDOWN = -1, -2, -3, -4, -5
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED32 = 0, 1, 2
 F64, F32 = 0, 1
 AVG_DENSITY, AVG_MODULUS = 0, 1
 KERNEL_STREAM, KERNEL_GATHER, KERNEL_AUTO = 0, 1, 2
@@ -41,6 +43,7 @@ class GridDesc(ctypes.Structure):
         ("precision", ctypes.c_int), ("smooth_sweeps", ctypes.c_int),
         ("omega", ctypes.c_double), ("coarse_avg", ctypes.c_int), ("max_nrhs", ctypes.c_int),
         ("kernel", ctypes.c_int), ("fixed_mask", ctypes.c_void_p), ("coarse_op", ctypes.c_int),
+        ("vcycle_both", ctypes.c_int), ("rr_every", ctypes.c_int),
     ]
 
 
@@ -228,6 +231,20 @@ def batch_solve(grids, fs, us, rtol=1e-6, maxit=500, stream=None, check=True):
     return code, out
 
 
+_live_grids: "weakref.WeakSet[Grid]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_grids():
+    """Destroy the grids still open at interpreter exit while the HIP runtime is
+    still up (their streams and pinned buffers), before module teardown."""
+    for g in list(_live_grids):
+        try:
+            g.close()
+        except Exception:
+            pass
+
+
 class Grid:
     """Owns the workspace tensor and the opaque grid handle of one hexmg grid."""
 
@@ -245,11 +262,14 @@ class Grid:
         self.handle = h
         self.density_version = 0
         self.last_info = None
+        _live_grids.add(self)
 
     def close(self):
+        """Destroy the grid (waits for the library's own streams), then drop the workspace."""
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().hexmg_grid_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -31,6 +31,7 @@ def _grid(dims, levels, **kw):
     _gpu()
     g = W.Grid(*dims)
     rho = W.random_field_density(g, seed=5, length_scale=4.0, lo=0.01)
+    kw.setdefault("vcycle_both", 1)  # V-cycles in both precisions
     grid = hexmg.Grid(*dims, levels, **kw)
     grid.set_density(gpu(rho))
     return g, rho, grid

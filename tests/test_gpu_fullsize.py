@@ -199,14 +199,57 @@ def test_fullsize_256x128x128_oc_step():
     assert float(dvn @ xn) == pytest.approx(0.12, rel=1e-9)
 
 
-def test_fullsize_768x384x384():
+def test_fullsize_128x64x64_errors_against_oracle(c1):
+    """Error of u, compliance and sensitivity of the three solver precisions at
+    rtol 1e-6 against the oracle's MGPCG solved to 1e-12 (binary64, assembled
+    operators): compliance within 1e-5 for the mixed forms and 1e-9 for plain
+    binary64; every error is printed."""
+    from oracle import multigrid as mg
+    from paper_2201_12931_amd import hexmg
+
+    print("case full-size 128x64x64 errors vs oracle", flush=True)
+    g, rho, f, mask, spec, _ = c1
+    h = mg.Hierarchy(g.nx, g.ny, g.nz, rho, mask, spec["levels"])
+    u_ref, its, rel_ref, _ = mg.mgpcg(h, f, rtol=1e-12, maxit=200)
+    del h
+    assert rel_ref <= 1e-12
+    c_ref = fem.compliance(f, u_ref)
+    dc_ref = fem.sensitivity(g.nx, g.ny, g.nz, rho, u_ref)
+    print(f"oracle: {its} iterations, c = {c_ref:.15e}", flush=True)
+    bars = {hexmg.FP64: 1e-9, hexmg.MIXED: 1e-5, hexmg.MIXED32: 1e-5}
+    names = {hexmg.FP64: "fp64", hexmg.MIXED: "mixed", hexmg.MIXED32: "mixed32"}
+    for prec, bar in bars.items():
+        grid = hexmg.Grid(g.nx, g.ny, g.nz, spec["levels"], precision=prec)
+        grid.set_density(gpu(rho))
+        u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+        code, info = grid.solve(gpu(f), u, rtol=spec["rtol"])
+        assert code == 0 and info[0]["rel_res_true"] <= spec["rtol"]
+        dc = torch.empty(g.n_elem, dtype=torch.float64, device="cuda")
+        grid.compliance_sensitivity(gpu(f), u, dc, compliance=False)
+        un, dcn = u.cpu().numpy(), dc.cpu().numpy()
+        eu = float(np.linalg.norm(un - u_ref) / np.linalg.norm(u_ref))
+        ec = abs(info[0]["compliance"] - c_ref) / c_ref
+        edc = float(np.abs(dcn - dc_ref).max() / np.abs(dc_ref).max())
+        print(f"{names[prec]}: iterations {info[0]['iterations']}, true residual {info[0]['rel_res_true']:.3e}, "
+              f"error u {eu:.3e}, compliance {ec:.3e}, sensitivity {edc:.3e}", flush=True)
+        assert ec <= bar, (names[prec], ec)
+        grid.close()
+
+
+@pytest.fixture(scope="module")
+def c4():
+    _gpu()
+    return W.workload("cantilever_768x384x384_rf")
+
+
+def test_fullsize_768x384x384(c4):
     """113 M elements: K u in binary32 at sampled nodes, the mixed solve
     (sampled residual), and the sensitivity at sampled elements."""
     from paper_2201_12931_amd import hexmg
 
     _gpu()
     print("case full-size 768x384x384", flush=True)
-    g, rho, f, mask, spec = W.workload("cantilever_768x384x384_rf")
+    g, rho, f, mask, spec = c4
     grid = hexmg.Grid(g.nx, g.ny, g.nz, spec["levels"], precision=hexmg.MIXED)
     grid.set_density(gpu(rho))
     E = fem.simp_modulus(rho)
@@ -230,3 +273,43 @@ def test_fullsize_768x384x384():
     elems = sample_elements(g, n=100, seed=10)
     refs, scale = element_sensitivity(g, rho, un, elems)
     assert np.all(np.abs(dc.cpu().numpy()[elems] - refs) <= 1e-13 * scale + 1e-300)
+    grid.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed32"])
+def test_fullsize_768x384x384_fp64_and_mixed32(c4, precision):
+    """The plain binary64 form (K u in binary64 at sampled nodes to 1e-13) and
+    the binary32-outer-product form at 113 M elements: solve to 1e-6 with the
+    sampled residual, compliance = f^T u, sensitivity at sampled elements."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case full-size 768x384x384 {precision}", flush=True)
+    g, rho, f, mask, spec = c4
+    prec = hexmg.FP64 if precision == "fp64" else hexmg.MIXED32
+    grid = hexmg.Grid(g.nx, g.ny, g.nz, spec["levels"], precision=prec)
+    grid.set_density(gpu(rho))
+    nodes = sample_nodes(g, n_random=80, seed=11)
+    if prec == hexmg.FP64:
+        E = fem.simp_modulus(rho)
+        u64 = torch.randn(g.n_dof, dtype=torch.float64, device="cuda",
+                          generator=torch.Generator("cuda").manual_seed(6))
+        y64 = torch.empty_like(u64)
+        grid.apply_K(u64, y64)
+        ref = fem.apply_constrained_at_nodes(g.nx, g.ny, g.nz, E, mask, u64.cpu().numpy(), nodes)
+        y = y64.cpu().numpy().reshape(-1, 3)[nodes]
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+        del u64, y64
+    fd = gpu(f)
+    u = torch.empty_like(fd)
+    code, info = grid.solve(fd, u, rtol=spec["rtol"])
+    assert code == 0
+    print(f"{precision}: {info[0]['iterations']} iterations, true residual {info[0]['rel_res_true']:.3e}, "
+          f"compliance {info[0]['compliance']:.15e}", flush=True)
+    un = u.cpu().numpy()
+    check_solve(g, rho, mask, f, un, info[0], spec["rtol"], nodes)
+    dc = torch.empty(g.n_elem, dtype=torch.float64, device="cuda")
+    grid.compliance_sensitivity(fd, u, dc, compliance=False)
+    elems = sample_elements(g, n=100, seed=12)
+    refs, scale = element_sensitivity(g, rho, un, elems)
+    assert np.all(np.abs(dc.cpu().numpy()[elems] - refs) <= 1e-13 * scale + 1e-300)
+    grid.close()

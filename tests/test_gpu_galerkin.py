@@ -65,7 +65,7 @@ def test_galerkin_vcycle_parity(sweeps):
     g = W.Grid(*dims)
     rho = W.random_field_density(g, seed=7, length_scale=4.0, lo=0.01)
     mask = W.fixed_mask_face_x0(g)
-    grid = hexmg.Grid(*dims, levels, coarse_op=hexmg.COARSE_GALERKIN, smooth_sweeps=sweeps)
+    grid = hexmg.Grid(*dims, levels, coarse_op=hexmg.COARSE_GALERKIN, smooth_sweeps=sweeps, vcycle_both=1)
     grid.set_density(gpu(rho))
     h = mg.Hierarchy(*dims, rho, mask, levels, sweeps=sweeps, coarse_operator="galerkin")
     r = W.random_vector(g.n_dof, seed=24) * h.free[0]

@@ -40,6 +40,7 @@ def make_case(dims, levels, density="field", seed=1, **kw):
     else:
         rho = W.iid_uniform_density(g, seed=seed, lo=0.3)
     mask = W.fixed_mask_face_x0(g)
+    kw.setdefault("vcycle_both", 1)  # the cases run V-cycles in both precisions
     grid = hexmg.Grid(*dims, levels, **kw)
     grid.set_density(torch.from_numpy(rho).cuda())
     torch.cuda.synchronize()
@@ -239,6 +240,108 @@ def test_mixed_precision_solve():
         res[prec] = (info[0], u.cpu().numpy())
     c64, c32 = res[hexmg.FP64][0]["compliance"], res[hexmg.MIXED][0]["compliance"]
     assert c32 == pytest.approx(c64, rel=1e-5)
+
+
+@pytest.mark.parametrize("rr_every", [0, 3, 8])
+def test_mixed32_solve_against_direct(rr_every):
+    """Binary32 outer K p with binary64 CG vectors: the residual is replaced by
+    the binary64 M f - A x every rr_every iterations, and CG restarts from its
+    iterate while the binary64 residual misses rtol, so the solve reaches a
+    binary64 residual of 1e-10 and the direct solution."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case mixed32 solve rr_every={rr_every}", flush=True)
+    dims, levels = (32, 16, 16), 3
+    g, rho, mask, grid = make_case(dims, levels, precision=hexmg.MIXED32, rr_every=rr_every, vcycle_both=0)
+    f = W.cantilever_line_load(g)
+    K = fem.assemble_stiffness(*dims, fem.simp_modulus(rho))
+    u_ref = fem.solve_direct(K, f, fem.free_dof_mask(mask))
+    c_ref = fem.compliance(f, u_ref)
+    u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+    code, info = grid.solve(gpu(f), u, rtol=1e-10, maxit=300)
+    assert code == 0 and info[0]["status"] == 0, info
+    assert info[0]["rel_res_true"] <= 1e-10
+    assert info[0]["compliance"] == pytest.approx(c_ref, rel=1e-9)
+    assert rel(u.cpu().numpy(), u_ref) < 1e-7
+
+
+def test_mixed32_matches_mixed_and_fp64_compliance():
+    """The three precisions at rtol 1e-6 on a random field: binary64 residuals at
+    the tolerance and compliances within 1e-5 of each other."""
+    from paper_2201_12931_amd import hexmg
+
+    print("case mixed32 vs mixed vs fp64", flush=True)
+    dims, levels = (64, 32, 32), 4
+    _require_gpu()
+    g = W.Grid(*dims)
+    rho = W.random_field_density(g, seed=1, lo=0.01)
+    f = W.cantilever_line_load(g)
+    res = {}
+    for prec in (hexmg.FP64, hexmg.MIXED, hexmg.MIXED32):
+        grid = hexmg.Grid(*dims, levels, precision=prec)
+        grid.set_density(gpu(rho))
+        u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+        code, info = grid.solve(gpu(f), u, rtol=1e-6, maxit=300)
+        assert code == 0, prec
+        assert info[0]["rel_res_true"] <= 1e-6, (prec, info)
+        res[prec] = info[0]["compliance"]
+    assert res[hexmg.MIXED32] == pytest.approx(res[hexmg.FP64], rel=1e-5)
+    assert res[hexmg.MIXED] == pytest.approx(res[hexmg.FP64], rel=1e-5)
+
+
+def test_mixed32_multi_rhs_equals_single():
+    """Lockstep right-hand sides with binary32 K p and residual replacement equal
+    single solves bit for bit (same kernels, same order of every sum)."""
+    from paper_2201_12931_amd import hexmg
+
+    print("case mixed32 multi-rhs", flush=True)
+    dims, levels = (32, 16, 16), 3
+    _require_gpu()
+    g = W.Grid(*dims)
+    rho = gpu(W.random_field_density(g, seed=3, lo=0.01))
+    F = gpu(W.point_loads(g, 3, seed=30))
+    multi = hexmg.Grid(*dims, levels, precision=hexmg.MIXED32, max_nrhs=3, rr_every=4)
+    single = hexmg.Grid(*dims, levels, precision=hexmg.MIXED32, max_nrhs=1, rr_every=4)
+    for grid in (multi, single):
+        grid.set_density(rho)
+        for l in range(levels):
+            for dt in (hexmg.F32, hexmg.F64):
+                grid.set_kernel_choice(l, dt, hexmg.KERNEL_STREAM, 4, 0)
+        grid.set_coarse_cycle(hexmg.F32, 0)
+    U = torch.empty_like(F)
+    code, info = multi.solve(F, U, rtol=1e-9, maxit=200)
+    assert code == 0
+    for r in range(3):
+        u1 = torch.empty_like(F[r])
+        c1, i1 = single.solve(F[r].contiguous(), u1, rtol=1e-9, maxit=200)
+        assert i1[0]["iterations"] == info[r]["iterations"], r
+        assert torch.equal(u1, U[r]), r
+        assert info[r]["rel_res_true"] <= 1e-9
+
+
+def test_mixed32_single_level():
+    """One level (no sweep to fuse into): the restart path alone."""
+    from paper_2201_12931_amd import hexmg
+
+    print("case mixed32 single level", flush=True)
+    dims = (6, 4, 4)
+    g, rho, mask, grid = make_case(dims, 1, density="uniform", precision=hexmg.MIXED32, vcycle_both=0)
+    f = W.cantilever_line_load(g)
+    u_ref = fem.solve_direct(fem.assemble_stiffness(*dims, fem.simp_modulus(rho)), f, fem.free_dof_mask(mask))
+    u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+    code, info = grid.solve(gpu(f), u, rtol=1e-10, maxit=40)
+    assert code == 0 and info[0]["rel_res_true"] <= 1e-10
+    assert rel(u.cpu().numpy(), u_ref) < 1e-8
+
+
+def test_vcycle_dtype_not_held_is_rejected():
+    from paper_2201_12931_amd import hexmg
+
+    g, rho, mask, grid = make_case((16, 8, 8), 3, vcycle_both=0)  # binary64 grid
+    r = torch.zeros(g.n_dof, dtype=torch.float32, device="cuda")
+    with pytest.raises(hexmg.HexmgError) as e:
+        grid.vcycle(r, torch.empty_like(r))
+    assert e.value.code == hexmg.ERR_INVALID
 
 
 def test_uniaxial_bar_custom_supports():
