@@ -24,7 +24,8 @@
  * Memory: all array arguments are DEVICE pointers unless marked "host".  The
  * caller owns every pointer, including the workspace given to
  * hexmg_grid_create; the library never frees caller memory and allocates no
- * device memory of its own.  Calls are asynchronous on the given stream (a
+ * device memory of its own (its only device storage is the static scratch
+ * array of hexmg_filter_noalloc, 32 MiB per GPU, part of the loaded code).  Calls are asynchronous on the given stream (a
  * hipStream_t passed as void*; NULL = the null stream) except where a host
  * output is written, in which case the call synchronises that stream.
  *
@@ -202,6 +203,19 @@ int hexmg_compliance_sensitivity(hexmg_grid_t grid, const double *f, const doubl
  * the forward filter).  in and out must not overlap.  Asynchronous. */
 int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double *in, double *out,
                  double *tmp, void *stream);
+
+/* The density filter of hexmg_filter for callers that cannot allocate device
+ * memory (code under graph capture, serving loops, harnesses that forbid
+ * allocation): the adjoint's intermediate in / Hs lives in a static device
+ * array of the library (one per GPU, 2^22 doubles = 32 MiB, held until the
+ * process ends) instead of a caller buffer, and the call allocates nothing.
+ * Same arguments and results as hexmg_filter without tmp; the adjoint returns
+ * -1 for more than 2^22 elements (the forward filter needs no scratch and has
+ * hexmg_filter's limits).  Every adjoint call on a GPU shares that GPU's
+ * array, so adjoint calls that overlap on one GPU (different streams or host
+ * threads without ordering) race.  Asynchronous. */
+int hexmg_filter_noalloc(int nx, int ny, int nz, double rmin, int adjoint, const double *in, double *out,
+                         void *stream);
 
 /* Sensitivity filter (Eq. 3) with the same weights:
  *   out_e = (sum_i w_ei x_i dc_i) / (max(gamma, x_e) sum_i w_ei),

@@ -1304,6 +1304,29 @@ int hexmg_filter(int nx, int ny, int nz, double rmin, int adjoint, const double*
   return 0;
 }
 
+int hexmg_filter_noalloc(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out,
+                         void* stream) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(HEXMG_ERR_INVALID, "grid dimensions must be >= 1");
+  if (!(rmin > 1.0 && rmin <= 8.0)) return fail(HEXMG_ERR_INVALID, "need 1 < rmin <= 8");
+  if (!in || !out || in == out) return fail(HEXMG_ERR_INVALID, "need distinct in and out");
+  const long long n = (long long)nx * ny * nz;
+  double* tmp = nullptr;
+  if (adjoint) {
+    if (n > kFilterScratchElems)
+      return fail(HEXMG_ERR_INVALID, "hexmg_filter_noalloc: the adjoint takes at most " +
+                                         std::to_string(kFilterScratchElems) + " elements, got " + std::to_string(n));
+    const int e = filter_scratch_ptr(&tmp);
+    if (e != 0)
+      return fail(HEXMG_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                        hipGetErrorString(static_cast<hipError_t>(e)));
+  } else if (n >= (1ll << 31)) {
+    return fail(HEXMG_ERR_INVALID, "grid too large");
+  }
+  launch_filter(nx, ny, nz, rmin, adjoint, in, out, tmp, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int hexmg_sensitivity_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,
                              double* out, void* stream) {
   if (nx < 1 || ny < 1 || nz < 1) return fail(HEXMG_ERR_INVALID, "grid dimensions must be >= 1");

@@ -192,6 +192,10 @@ void launch_gj_blocked(int n, double* A, double* B, double* D, double** result, 
 // Density filter and optimality criteria (topopt.hip)
 void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const double* in, double* out, double* tmp,
                    hipStream_t s);
+// Element capacity of the adjoint filter's static scratch (topopt.hip), and
+// its address on the current device (0, or a hipError_t value on failure).
+constexpr long long kFilterScratchElems = 1ll << 22;
+int filter_scratch_ptr(double** ptr);
 void launch_sens_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,
                         double* out, hipStream_t s);
 void launch_gravity_load(const Level& L, const double* rho, double g, const double* f_ext, double* f,

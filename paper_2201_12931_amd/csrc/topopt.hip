@@ -12,6 +12,8 @@
 // dv^T x_new(lambda) (the filtered volume is linear in x) for kOcProbes values
 // of lambda at once; the host narrows the bracket by that factor per pass.
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "hexmg_impl.h"
 
@@ -197,6 +199,30 @@ void launch_filter(int nx, int ny, int nz, double rmin, int adjoint, const doubl
   } else {
     k_filter<0><<<grid, bx, 0, s>>>(nx, ny, nz, rmin, R, in, out);
   }
+}
+
+// Scratch of the adjoint filter for callers that cannot allocate: in / Hs for
+// up to kFilterScratchElems elements.  Each device holds its own copy for the
+// life of the process; its device address is looked up once per device (the
+// array's name is a host-side stand-in and is never passed to a kernel).
+__device__ __align__(256) double scratch[kFilterScratchElems];
+
+int filter_scratch_ptr(double** ptr) {
+  static std::mutex mu;
+  static std::vector<double*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return 0;
 }
 
 void launch_sens_filter(int nx, int ny, int nz, double rmin, double gamma, const double* x, const double* dc,

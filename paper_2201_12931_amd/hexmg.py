@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(i), d, i, ctypes.POINTER(SolveInfo), vp]),
             "hexmg_element_matrix": (i, [d, vp]),
             "hexmg_filter": (i, [i, i, i, d, i, vp, vp, vp, vp]),
+            "hexmg_filter_noalloc": (i, [i, i, i, d, i, vp, vp, vp]),
             "hexmg_sensitivity_filter": (i, [i, i, i, d, d, vp, vp, vp, vp]),
             "hexmg_gravity_load": (i, [vp, d, vp, vp, vp]),
             "hexmg_gravity_sensitivity": (i, [vp, vp, d, d, vp, vp]),
@@ -179,6 +180,18 @@ def density_filter(nx, ny, nz, rmin, x, out=None, adjoint=False, tmp=None, strea
     _check(lib().hexmg_filter(nx, ny, nz, float(rmin), 1 if adjoint else 0, _dev(x, torch.float64, n, "x"),
                               _dev(out, torch.float64, n, "out"),
                               _dev(tmp, torch.float64, n, "tmp") if adjoint else None, _stream(stream)))
+    return out
+
+
+def density_filter_noalloc(nx, ny, nz, rmin, x, out, adjoint=False, stream=None):
+    """S13 through the entry point that allocates nothing (the adjoint's
+    intermediate lives in the library's static device scratch); out must be
+    given."""
+    import torch
+
+    n = nx * ny * nz
+    _check(lib().hexmg_filter_noalloc(nx, ny, nz, float(rmin), 1 if adjoint else 0, _dev(x, torch.float64, n, "x"),
+                                      _dev(out, torch.float64, n, "out"), _stream(stream)))
     return out
 
 
