@@ -58,6 +58,9 @@ def apply_bytes(g, word) -> float:
 # known size), keyed by workload, kernel family, kernel choice and a digest of
 # the kernel source they were taken on: any change to the kernel voids them.
 TRAFFIC = {
+    # level-0 binary32 Jacobi sweep, 768x384x384, 2 rows x 4 waves, z-chunk 4
+    # (profiles/stream_smooth_f32_L0_cantilever_768x384x384_rf_traffic.md)
+    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "c69a7e4e8d357be5"): 9094194944.0,
 }
 
 
@@ -86,6 +89,20 @@ def time_events(fn, reps, stream):
     ev[-1].synchronize()
     t = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))
     return ev[0].elapsed_time(ev[-1]) / reps, t[len(t) // 2], t[0]
+
+
+def copy_probe(mib, dev):
+    """Three device-to-device copies of mib MiB (calibration of HBM byte counters)."""
+    if not mib:
+        return
+    import torch
+
+    src = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_baseline(workload_dofs: int, workload_name: str):
@@ -133,7 +150,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cantilever_768x384x384_rf")
-    ap.add_argument("--precision", default="mixed32", choices=["mixed32", "mixed"],
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "mixed32"],
                     help="solver precision of the timed step (the other forms are timed once each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ku-reps", type=int, default=20)
@@ -203,6 +220,14 @@ def main():
     info_main = infos[-1]
     print(f"bench: timed steps done, {ms_per_step:.2f} ms per step", file=sys.stderr, flush=True)
     if args.only_step:
+        # for profiler runs: a few binary32 K u launches (public entry) and the
+        # copy calibration, then the step time
+        u32 = torch.randn(g.n_dof, dtype=torch.float32, device=dev)
+        y32 = torch.empty_like(u32)
+        for _ in range(3):
+            main_grid.apply_K(u32, y32)
+        del u32, y32
+        copy_probe(args.copy_probe, dev)
         print(json.dumps({"metric": METRIC, "ms_per_step": ms_per_step, "steps": args.steps,
                           "config": {"workload": args.workload, "precision": args.precision}}), flush=True)
         main_grid.close()
@@ -231,7 +256,9 @@ def main():
     main_grid.apply_K(u64, y64)
     ms64, med64, min64 = time_events(lambda: main_grid.apply_K(u64, y64), args.ku_reps, stream)
     del u64, y64
-    choices = {f"L{l}": {"f32": main_grid.kernel_choice(l, hexmg.F32), "f64": main_grid.kernel_choice(l, hexmg.F64)}
+    # per level, precision and mode (K u, sweep, residual): (kind, z-chunk, shape)
+    choices = {f"L{l}": {dt: {m: main_grid.kernel_choice(l, d, i) for i, m in enumerate(("apply", "smooth", "residual"))}
+                         for dt, d in (("f32", hexmg.F32), ("f64", hexmg.F64))}
                for l in range(levels)}
     choices["coarse_cycle"] = main_grid.coarse_cycle_choice(hexmg.F32)
     main_grid.close()
@@ -256,13 +283,7 @@ def main():
         torch.cuda.empty_cache()
         print(f"bench: {name} step {step_s[name] * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
-    if args.copy_probe:
-        src = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_probe(args.copy_probe, dev)
 
     # dominant kernel: the family with the largest device time over the profiled steps
     dom = max(kernel_ms, key=lambda k: kernel_ms[k][1])
@@ -270,7 +291,7 @@ def main():
     avg_ms = t_dom / max(n_dom, 1)
     dom_bytes = family_bytes(g, dom)
     achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
-    dom_choice = choices["L0"]["f32" if dom.endswith("f32") else "f64"]
+    dom_choice = choices["L0"]["f32" if dom.endswith("f32") else "f64"][dom.split("_")[0]]
     c64 = solves["fp64"]["compliance"]
     out = {
         "metric": METRIC,
@@ -322,7 +343,7 @@ def main():
             "timing": "per-dispatch HIP events over %d untimed repeats of the step" % args.steps,
         },
         "roofline_ku": {
-            "kernel": "K u binary32, level 0, public entry (%s, z-chunk %d, shape %d)" % choices["L0"]["f32"],
+            "kernel": "K u binary32, level 0, public entry (%s, z-chunk %d, shape %d)" % choices["L0"]["f32"]["apply"],
             "bound": "hbm",
             "achieved": apply_bytes(g, 4) / (ms32 * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS,

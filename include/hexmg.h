@@ -73,6 +73,12 @@ extern "C" {
 #define HEXMG_AVG_DENSITY 0 /* coarse rho = mean of the 8 children, then E(rho) (Sec. 4.2.2) */
 #define HEXMG_AVG_MODULUS 1 /* coarse E = mean of the 8 children's E */
 
+/* Storage of the Galerkin coarse stencils read by binary32 V-cycles (hexmg_grid_desc.stencil_storage) */
+#define HEXMG_STENCIL_F32 0  /* binary32 (default) */
+#define HEXMG_STENCIL_BF16 1 /* bfloat16: half the bytes, 8 significand bits, binary32's exponent range */
+#define HEXMG_STENCIL_F16 2  /* binary16: half the bytes, 11 significand bits, each node's row scaled by a
+                                power of two (kept per node) so that its largest coefficient is in [2^14, 2^15) */
+
 /* Coarse operators */
 #define HEXMG_COARSE_REDISCRETIZE 0 /* coarse element stiffness from the homogenized density (Sec. 4.2.2, default) */
 #define HEXMG_COARSE_GALERKIN 1     /* A_{l+1} = P^T A_l P with the supports (Eq. 23), stored as 27-point stencils */
@@ -87,7 +93,8 @@ typedef struct {
   double E0, Emin, nu, penal; /* 1, 1e-9, 0.3, 3 in the paper's examples */
   int precision;        /* HEXMG_FP64 | HEXMG_MIXED | HEXMG_MIXED32 */
   int smooth_sweeps;    /* damped-Jacobi sweeps before and after the coarse correction */
-  double omega;         /* Jacobi damping, 0 < omega <= 1 */
+  double omega;         /* Jacobi damping, 0 < omega <= 1, or 0 = automatic: 0.6 with
+                           re-discretized coarse operators, 0.5 with Galerkin ones */
   int coarse_avg;       /* HEXMG_AVG_DENSITY | HEXMG_AVG_MODULUS */
   int max_nrhs;         /* most right-hand sides per call (sizes the workspace) */
   int kernel;           /* HEXMG_KERNEL_AUTO | HEXMG_KERNEL_STREAM | HEXMG_KERNEL_GATHER */
@@ -104,10 +111,14 @@ typedef struct {
                            twice the V-cycle memory) and hexmg_vcycle accepts either */
   int rr_every;         /* HEXMG_MIXED32 only: replace the recursive residual by the binary64
                            one every rr_every iterations (0 = only when rtol is met) */
+  int stencil_storage;  /* HEXMG_COARSE_GALERKIN with a binary32 V-cycle: HEXMG_STENCIL_F32 |
+                           HEXMG_STENCIL_BF16 | HEXMG_STENCIL_F16.  The 16-bit forms are rounded
+                           from the binary64 stencils (which set-up and binary64 V-cycles use),
+                           so the binary32 V-cycle runs with a perturbed but fixed coarse operator */
 } hexmg_grid_desc;
 
 /* Fill *desc with the defaults (E0 1, Emin 1e-9, nu 0.3, penal 3, FP64, 2 sweeps,
- * omega 0.6, density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0,
+ * omega automatic (0), density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0,
  * re-discretized coarse operators, V-cycle vectors in the solver's precision only,
  * residual replacement every 8 iterations)
  * for the given grid.  Host only. */
@@ -177,14 +188,24 @@ int hexmg_solve(hexmg_grid_t grid, const double *f, double *u, int nrhs, double 
 /* S15: solve several grids (distinct objects, each after a successful
  * hexmg_set_density) together: grid i solves nrhs[i] <= its max_nrhs
  * right-hand sides f[i] -> u[i] (device, [nrhs[i]][N_i] doubles) exactly as
- * hexmg_solve would.  The grids advance in lockstep, each on a stream of its
- * own (created on first use, default priority, destroyed with the grid) that
- * is ordered after the work already queued on `stream`; every kernel covers
- * all right-hand sides of its grid, and the host waits once per round for all
- * grids.  infos: host, sum(nrhs) entries in grid order (may be NULL).
- * Synchronises `stream`.  Status as hexmg_solve (worst over the batch). */
+ * hexmg_solve would (same kernels, same arithmetic, bit for bit).  All grids
+ * run on `stream` in lockstep: each PCG step and each V-cycle step (sweep,
+ * residual, restriction, coarsest solve, prolongation) of all grids is one
+ * kernel launch whose workgroups look up their grid in a task table passed
+ * with the launch (grids of different depth share the launches of the levels
+ * they have; grids that chose different tile shapes for a level, or whose
+ * Poisson ratios differ, take separate launches of that step).  Every kernel
+ * covers all right-hand sides of its grid; a converged grid or right-hand side
+ * drops out.  The host waits once per iteration for all grids.  infos: host,
+ * sum(nrhs) entries in grid order (may be NULL).  Synchronises `stream`.
+ * Status as hexmg_solve (worst over the batch). */
 int hexmg_batch_solve(hexmg_grid_t *grids, int ngrids, const double *const *f, double *const *u,
                       const int *nrhs, double rtol, int maxit, hexmg_solve_info *infos, void *stream);
+
+/* Diagnostics of the last hexmg_batch_solve the grid took part in: the kernel
+ * launches (and runtime calls) it issued for the whole batch, and how many the
+ * grids would have issued one by one.  Either pointer may be NULL.  Host only. */
+int hexmg_batch_stats(hexmg_grid_t grid, size_t *launches, size_t *recorded);
 
 /* S11-S12: compliance c_r = f_r^T u_r (Eq. 6) per right-hand side into
  * c_host (host, nrhs doubles, may be NULL) and the adjoint sensitivity (Eq. 7,
@@ -258,17 +279,30 @@ int hexmg_apply_passive(long long n, const uint8_t *passive, double *x, void *st
  * device, Ne doubles (dc <= 0, dv >= 0; an element with dv = 0 is outside the
  * volume constraint and keeps its x, e.g. a passive one); x_new: device, Ne
  * doubles, distinct from the inputs.  lambda_host (host, may be NULL)
- * receives lambda.
- * Synchronises the stream once per bisection pass (32 multipliers per pass). */
+ * receives lambda, change_host (host, may be NULL) the largest |x_new - x|
+ * (the change that Alg. 4's stop test reads) and volume_host (host, may be
+ * NULL) dv^T x_new, the constrained volume of the new design.
+ * Synchronises the stream once per bisection pass (32 multipliers per pass),
+ * and once more when change_host or volume_host is given. */
 int hexmg_oc_update(hexmg_grid_t grid, const double *x, const double *dc, const double *dv, double volfrac,
-                    double move, double eta, double *x_new, double *lambda_host, void *stream);
+                    double move, double eta, double *x_new, double *lambda_host, double *change_host,
+                    double *volume_host, void *stream);
+
+/* Derivative of the volume of the design elements for the OC update when the
+ * sensitivity filter is used (the volume is the mean of x over the elements
+ * that are not passive): dv_e = 1 / (number of elements with passive_e == 0)
+ * for those, 0 for passive ones (which hexmg_oc_update then leaves alone).
+ * passive: device, nx*ny*nz bytes (0 design, 1 solid, 2 void); dv: device,
+ * nx*ny*nz doubles.  Asynchronous. */
+int hexmg_volume_weights(hexmg_grid_t grid, const uint8_t *passive, double *dv, void *stream);
 
 /* The library's unit element stiffness K0 (24x24, row-major, local DOF 3a+c)
  * for Poisson ratio nu, written to Ke_host.  Host only; needs no GPU. */
 int hexmg_element_matrix(double nu, double *Ke_host);
 
-/* The element-product kernel of the damped-Jacobi sweep on `level` for dtype
- * (HEXMG_F64/F32): *kernel = HEXMG_KERNEL_STREAM or HEXMG_KERNEL_GATHER and,
+/* The element-product kernel of `level` for dtype (HEXMG_F64/F32) in mode
+ * (0 K u, 1 damped-Jacobi sweep, 2 residual): *kernel = HEXMG_KERNEL_STREAM
+ * or HEXMG_KERNEL_GATHER and,
  * for the streaming kernel, the planes per z-chunk and the tile shape index
  * (rows per thread / waves per workgroup; any output pointer may be NULL).
  * With HEXMG_KERNEL_AUTO the choice is made by timing the candidates
@@ -276,7 +310,7 @@ int hexmg_element_matrix(double nu, double *Ke_host);
  * of one plane requests all its inputs before any arithmetic) on the
  * grid's stream during the first successful hexmg_set_density, separately
  * for K u, the sweep and the residual. */
-int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int *kernel, int *zchunk, int *shape);
+int hexmg_kernel_choice(hexmg_grid_t grid, int level, int dtype, int mode, int *kernel, int *zchunk, int *shape);
 
 /* Overrides the element-product kernel of `level` for dtype (all three
  * modes): kernel

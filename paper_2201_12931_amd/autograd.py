@@ -10,7 +10,9 @@
   includes the self-weight of the design, f = f_ext + f_g(rho); the derivative
   gains the load term 2 u^T df/drho.
 
-All run entirely in the HIP library; tensors only carry device memory.
+All run entirely in the HIP library; tensors only carry device memory.  A
+state solve that does not converge raises ``SolveNotConverged`` instead of
+returning a compliance and gradient of an inexact state.
 """
 from __future__ import annotations
 
@@ -18,6 +20,27 @@ import numpy as np
 import torch
 
 from . import hexmg
+
+
+class SolveNotConverged(RuntimeError):
+    """The state solve behind a compliance evaluation stopped at maxit (or broke
+    down): its c and dc would not be the compliance and gradient of the design."""
+
+    def __init__(self, code, info):
+        worst = max(info, key=lambda r: r["rel_res_recursive"])
+        super().__init__(f"state solve did not converge (status {code}): "
+                         f"{worst['iterations']} iterations, recursive residual {worst['rel_res_recursive']:.3g}, "
+                         f"true residual {worst['rel_res_true']:.3g}")
+        self.code, self.info = code, info
+
+
+def _solve(grid, f, rtol, maxit):
+    u = torch.empty_like(f)
+    code, info = grid.solve(f, u, rtol=rtol, maxit=maxit)
+    grid.last_info = info
+    if code != hexmg.OK:
+        raise SolveNotConverged(code, info)
+    return u, info
 
 
 class DensityFilter(torch.autograd.Function):
@@ -41,13 +64,11 @@ class Compliance(torch.autograd.Function):
     def forward(ctx, rho, grid, f, rtol=1e-6, maxit=500):
         rho = rho.detach().contiguous()
         grid.set_density(rho)
-        u = torch.empty_like(f)
-        code, info = grid.solve(f, u, rtol=rtol, maxit=maxit)
+        u, info = _solve(grid, f, rtol, maxit)
         c = grid.compliance_sensitivity(f, u)
         ctx.grid, ctx.version = grid, grid.density_version
         ctx.save_for_backward(rho, f, u)
         ctx.info = info
-        grid.last_info = info
         return torch.as_tensor(c, dtype=torch.float64, device=rho.device).reshape(f.shape[:-1] if f.dim() > 1 else ())
 
     @staticmethod
@@ -71,12 +92,10 @@ class SelfWeightCompliance(torch.autograd.Function):
         rho = rho.detach().contiguous()
         grid.set_density(rho)
         f = grid.gravity_load(gz, f_ext)
-        u = torch.empty_like(f)
-        code, info = grid.solve(f, u, rtol=rtol, maxit=maxit)
+        u, info = _solve(grid, f, rtol, maxit)
         c = grid.compliance_sensitivity(f, u)
         ctx.grid, ctx.version, ctx.gz = grid, grid.density_version, gz
         ctx.save_for_backward(rho, f, u)
-        grid.last_info = info
         return torch.as_tensor(c[0], dtype=torch.float64, device=rho.device)
 
     @staticmethod

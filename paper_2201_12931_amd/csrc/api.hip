@@ -4,9 +4,79 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 
 #include "hexmg_impl.h"
+
+namespace hexmg {
+
+// Launches of several grids recorded during hexmg_batch_solve.  Each record
+// holds its grid, its place in that grid's PCG iteration (stage: a stage not
+// above the grid's previous one starts the grid's next chunk, i.e. its next
+// iteration) and its single launch; a launch of a batchable kernel also holds
+// its task and a signature (kernel and template arguments).  flush() launches
+// everything in (chunk, stage) order: each grid's own launches keep their
+// order, and the records of one (chunk, stage) and signature from several grids
+// go out as one launch over all of them.
+struct BatchRecorder {
+  struct Rec {
+    int grid = 0, chunk = 0, stage = 0, blocks = 0;
+    unsigned long long sig = 0;  // 0: launched on its own
+    std::function<hipError_t(hipStream_t)> one;
+    std::function<hipError_t(const std::vector<const Rec*>&, hipStream_t)> group;
+    std::vector<unsigned char> task;
+  };
+  std::vector<Rec> recs;
+  std::vector<int> last, chunk;
+  size_t launches = 0, records = 0;  // launches issued / records taken (statistics)
+  explicit BatchRecorder(int ngrids) : last(ngrids, -1), chunk(ngrids, 0) {}
+  void add(int grid, int stage, Rec r) {
+    if (stage <= last[grid]) ++chunk[grid];
+    last[grid] = stage;
+    r.grid = grid;
+    r.chunk = chunk[grid];
+    r.stage = stage;
+    recs.push_back(std::move(r));
+  }
+  hipError_t flush(hipStream_t s) {
+    std::vector<const Rec*> order;
+    order.reserve(recs.size());
+    for (const Rec& r : recs) order.push_back(&r);
+    std::stable_sort(order.begin(), order.end(), [](const Rec* a, const Rec* b) {
+      if (a->chunk != b->chunk) return a->chunk < b->chunk;
+      if (a->stage != b->stage) return a->stage < b->stage;
+      if (a->sig != b->sig) return a->sig < b->sig;
+      return a->grid < b->grid;
+    });
+    hipError_t err = hipSuccess;
+    for (size_t i = 0; i < order.size();) {
+      const Rec* a = order[i];
+      size_t j = i + 1;
+      if (a->sig != 0)
+        while (j < order.size() && order[j]->chunk == a->chunk && order[j]->stage == a->stage &&
+               order[j]->sig == a->sig)
+          ++j;
+      hipError_t e = hipSuccess;
+      if (j - i == 1) {
+        e = a->one(s);
+      } else {
+        std::vector<const Rec*> grp(order.begin() + i, order.begin() + j);
+        e = a->group(grp, s);
+      }
+      ++launches;
+      if (e != hipSuccess && err == hipSuccess) err = e;
+      i = j;
+    }
+    records += recs.size();
+    recs.clear();
+    std::fill(last.begin(), last.end(), -1);
+    std::fill(chunk.begin(), chunk.end(), 0);
+    return err;
+  }
+};
+
+}  // namespace hexmg
 
 using namespace hexmg;
 
@@ -24,6 +94,83 @@ int fail(int code, const std::string& msg) {
     hipError_t e_ = (x);                                                                    \
     if (e_ != hipSuccess) return fail(HEXMG_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// ---- launching or recording (hexmg_batch_solve) ------------------------------
+// Places of the launches in a PCG iteration; a V-cycle's descent at level l
+// (0 first sweep, 1.. further sweeps, 90 residual, 95 restriction), its
+// coarsest solve, its ascent at level l (0 prolongation, 1.. sweeps), and the
+// CG steps after it.
+constexpr int kStStart = 10, kStInit = 30, kStRestart = 40, kStReplace = 50;
+constexpr int kStCoarse = 5000, kStEnd = 9000;
+inline int st_down(int l, int step) { return 1000 + 100 * l + step; }
+inline int st_up(int l, int step) { return 6000 + 100 * (kMaxLevels - l) + step; }
+
+// A kernel launch (fn(stream) launches it): now, or recorded while batching.
+template <typename F>
+void emit_launch(hexmg_grid* g, int stage, hipStream_t s, F fn) {
+  if (!g->rec) {
+    fn(s);
+    return;
+  }
+  BatchRecorder::Rec r;
+  r.one = [fn](hipStream_t st) {
+    fn(st);
+    return hipGetLastError();
+  };
+  g->rec->add(g->rec_grid, stage, std::move(r));
+}
+// A runtime call returning its status (event records, copies): now, or recorded.
+template <typename F>
+hipError_t emit_api(hexmg_grid* g, int stage, hipStream_t s, F fn) {
+  if (!g->rec) return fn(s);
+  BatchRecorder::Rec r;
+  r.one = fn;
+  g->rec->add(g->rec_grid, stage, std::move(r));
+  return hipSuccess;
+}
+// A launch of a batchable kernel: task A with `blocks` workgroups; sig
+// identifies kernel and template arguments; one(stream) is its single launch,
+// many(batch, stream) launches a Batch<A>.
+template <typename A, typename One, typename Many>
+void emit_task(hexmg_grid* g, int stage, hipStream_t s, unsigned long long sig, const A& task, int blocks, One one,
+               Many many) {
+  if (!g->rec) {
+    one(s);
+    return;
+  }
+  BatchRecorder::Rec r;
+  r.sig = sig;
+  r.blocks = blocks;
+  r.task.resize(sizeof(A));
+  std::memcpy(r.task.data(), &task, sizeof(A));
+  r.one = [one](hipStream_t st) {
+    one(st);
+    return hipGetLastError();
+  };
+  r.group = [many](const std::vector<const BatchRecorder::Rec*>& rs, hipStream_t st) {
+    for (size_t i = 0; i < rs.size(); i += kMaxBatch) {
+      Batch<A> b;
+      b.n = (int)std::min<size_t>(kMaxBatch, rs.size() - i);
+      b.begin[0] = 0;
+      for (int t = 0; t < b.n; ++t) {
+        std::memcpy(&b.a[t], rs[i + t]->task.data(), sizeof(A));
+        b.begin[t + 1] = b.begin[t] + rs[i + t]->blocks;
+      }
+      many(b, st);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  g->rec->add(g->rec_grid, stage, std::move(r));
+}
+// signature of a batchable launch: kernel kind, element sizes, mode/shape/flags
+inline unsigned long long batch_sig(int kind, int a = 0, int b = 0, int c = 0, int d = 0, int e = 0) {
+  return (unsigned long long)(kind + 1) | ((unsigned long long)(a & 0xff) << 8) |
+         ((unsigned long long)(b & 0xff) << 16) | ((unsigned long long)(c & 0xff) << 24) |
+         ((unsigned long long)(d & 0xff) << 32) | ((unsigned long long)(e & 0xff) << 40);
+}
+enum BatchKind { kBkStream, kBkRestrict, kBkProlong, kBkGemv, kBkUpdateR, kBkRrCheck, kBkUpdatePx };
 
 const char* kFamilies[] = {"apply_f64", "apply_f32", "smooth_f64", "smooth_f32", "residual_f64",
                            "residual_f32"};
@@ -65,7 +212,8 @@ int validate(const hexmg_grid_desc* d) {
   if (d->vcycle_both != 0 && d->vcycle_both != 1) return fail(HEXMG_ERR_INVALID, "vcycle_both must be 0 or 1");
   if (d->rr_every < 0) return fail(HEXMG_ERR_INVALID, "rr_every must be >= 0");
   if (d->smooth_sweeps < 1 || d->smooth_sweeps > 64) return fail(HEXMG_ERR_INVALID, "smooth_sweeps in [1,64]");
-  if (!(d->omega > 0.0 && d->omega <= 1.0)) return fail(HEXMG_ERR_INVALID, "need 0 < omega <= 1");
+  if (!(d->omega == 0.0 || (d->omega > 0.0 && d->omega <= 1.0)))
+    return fail(HEXMG_ERR_INVALID, "need omega = 0 (automatic) or 0 < omega <= 1");
   if (d->coarse_avg != HEXMG_AVG_DENSITY && d->coarse_avg != HEXMG_AVG_MODULUS)
     return fail(HEXMG_ERR_INVALID, "bad coarse_avg");
   if (d->max_nrhs < 1) return fail(HEXMG_ERR_INVALID, "max_nrhs must be >= 1");
@@ -73,6 +221,9 @@ int validate(const hexmg_grid_desc* d) {
     return fail(HEXMG_ERR_INVALID, "bad kernel");
   if (d->coarse_op != HEXMG_COARSE_REDISCRETIZE && d->coarse_op != HEXMG_COARSE_GALERKIN)
     return fail(HEXMG_ERR_INVALID, "bad coarse_op");
+  if (d->stencil_storage != HEXMG_STENCIL_F32 && d->stencil_storage != HEXMG_STENCIL_BF16 &&
+      d->stencil_storage != HEXMG_STENCIL_F16)
+    return fail(HEXMG_ERR_INVALID, "bad stencil_storage");
   return 0;
 }
 
@@ -89,6 +240,7 @@ void make_levels(const hexmg_grid_desc* d, std::vector<Level>& lv) {
     L.nn = L.nxn * L.nyn * L.nzn;
     L.ne = L.nx * L.ny * L.nz;
     L.mask = nullptr;
+    L.rowany = nullptr;
     lv.push_back(L);
   }
 }
@@ -104,6 +256,7 @@ size_t carve(hexmg_grid* g, char* base) {
   g->wd64.assign(L, nullptr);
   g->wd32.assign(L, nullptr);
   g->mask.assign(L, nullptr);
+  g->rowany.assign(L, nullptr);
   g->vf64.assign(L, nullptr);
   g->vu64.assign(L, nullptr);
   g->vt64.assign(L, nullptr);
@@ -124,6 +277,7 @@ size_t carve(hexmg_grid* g, char* base) {
     g->E64[l] = c.take<double>(lv.ne);
     g->E32[l] = c.take<float>(lv.ne);
     g->mask[l] = c.take<uint8_t>(lv.nn);
+    g->rowany[l] = c.take<uint8_t>((size_t)row_segments(lv) * lv.nyn * lv.nzn);
     if (v64) {
       g->wd64[l] = c.take<double>(N);
       g->vf64[l] = c.take<double>(N * R);
@@ -157,6 +311,13 @@ size_t carve(hexmg_grid* g, char* base) {
   g->p32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
   g->q32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
   g->partials = c.take<double>((size_t)kMaxDotParts * R);  // >= kReduceBlocks
+  {  // the most workgroups a level-0 streaming launch can have (z-chunk 1)
+    int np = 0;
+    for (bool f32 : {false, true})
+      for (int sh = 0; sh < stream_shapes(f32); ++sh) np = std::max(np, stream_blocks(g->lv[0], f32, sh, 1));
+    g->big_parts_n = np > kMaxDotParts ? np : 0;
+    g->big_parts = np > kMaxDotParts ? c.take<double>((size_t)np * R) : nullptr;
+  }
   g->partials2 = c.take<double>(kReduceBlocks * R);
   g->scalars = c.take<double>(kScalars * R);
   g->flags = c.take<int>(kReduceBlocks + 1);
@@ -167,11 +328,19 @@ size_t carve(hexmg_grid* g, char* base) {
   g->galerkin = g->desc.coarse_op == HEXMG_COARSE_GALERKIN && L > 1;
   g->S64.assign(L, nullptr);
   g->S32.assign(L, nullptr);
+  g->S16.assign(L, nullptr);
+  g->Sexp.assign(L, nullptr);
   g->Gc = c.take<double>(8 * 576);
   if (g->galerkin) {
+    // binary64 stencils for the set-up (and binary64 V-cycles); the binary32
+    // V-cycle's copy in its storage precision
+    const int store = g->desc.stencil_storage;
     for (int l = 1; l < L; ++l) {
-      g->S64[l] = c.take<double>(243ull * g->lv[l].nn);
-      g->S32[l] = c.take<float>(243ull * g->lv[l].nn);
+      const size_t nq = 243ull * g->lv[l].nn;
+      g->S64[l] = c.take<double>(nq);
+      if (store == HEXMG_STENCIL_F32) g->S32[l] = c.take<float>(nq);  // binary32 K u at any precision
+      if (v32 && store != HEXMG_STENCIL_F32) g->S16[l] = c.take<uint16_t>(nq);
+      if (v32 && store == HEXMG_STENCIL_F16) g->Sexp[l] = c.take<int8_t>(g->lv[l].nn);
     }
   }
   return c.off + 256;
@@ -207,26 +376,74 @@ int stream_zchunk(const Level& L, bool f32, int shape) {
 // maskin: u may be non-zero at fixed DOFs (the public K u); every vector
 // inside the solver is zero there, so the streaming kernel can skip masking it.
 template <typename T>
-void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
-                   const T* wd, T* y, int nrhs, hipStream_t s, bool maskin = false, const int* act = nullptr,
-                   const LaunchTimer& t = {}, double* dotp = nullptr) {
+void launch_choice_now(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
+                       const T* wd, T* y, int nrhs, hipStream_t s, bool maskin = false, const int* act = nullptr,
+                       const LaunchTimer& t = {}, double* dotp = nullptr) {
   const bool f32 = sizeof(T) == 4;
   const T* Ke = f32 ? (const T*)g->Ke32 : (const T*)g->Ke64;
   const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
   const Level& L = g->lv[level];
   if (g->galerkin && level > 0) {
-    const T* S;
-    if constexpr (sizeof(T) == 4)
-      S = g->S32[level];
-    else
-      S = g->S64[level];
-    launch_stencil<T>(mode, L, S, u, f, wd, y, nrhs, act, s, t);
+    if constexpr (sizeof(T) == 4) {
+      if (g->S16[level])
+        launch_stencil16(g->desc.stencil_storage, mode, L, g->S16[level], g->Sexp[level], u, f, wd, y, nrhs, act, s,
+                         t);
+      else
+        launch_stencil<T>(mode, L, g->S32[level], u, f, wd, y, nrhs, act, s, t);
+    } else {
+      launch_stencil<T>(mode, L, g->S64[level], u, f, wd, y, nrhs, act, s, t);
+    }
   } else if (ch.kernel == HEXMG_KERNEL_GATHER) {
     launch_gather<T>(mode, L, Ke, E, u, f, wd, y, nrhs, act, s, t);
   } else {
     const HaarCoef<T>& q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
     launch_stream<T>(mode, maskin, ch.shape, L, q, E, u, f, wd, y, ch.zchunk, nrhs, act, s, t, dotp);
   }
+}
+
+// The element-product launch of (mode, level) with kernel choice ch; while the
+// grid is batched it is recorded (at stage g->stage), the streaming kernel as a
+// batchable task.
+template <typename T>
+void launch_choice(hexmg_grid* g, const hexmg_grid::Choice& ch, int mode, int level, const T* u, const T* f,
+                   const T* wd, T* y, int nrhs, hipStream_t s, bool maskin = false, const int* act = nullptr,
+                   const LaunchTimer& t = {}, double* dotp = nullptr) {
+  if (!g->rec) {
+    launch_choice_now<T>(g, ch, mode, level, u, f, wd, y, nrhs, s, maskin, act, t, dotp);
+    return;
+  }
+  const bool f32 = sizeof(T) == 4;
+  const Level L = g->lv[level];
+  if (ch.kernel == HEXMG_KERNEL_STREAM && !(g->galerkin && level > 0) && !maskin) {
+    const HaarCoef<T> q = *reinterpret_cast<const HaarCoef<T>*>(f32 ? (const void*)&g->hq32 : (const void*)&g->hq64);
+    const T* E = f32 ? (const T*)g->E32[level] : (const T*)g->E64[level];
+    StreamTask<T> task{};
+    task.L = L;
+    task.E = E;
+    task.u = u;
+    task.f = f;
+    task.wd = wd;
+    task.y = y;
+    task.act = act;
+    task.dotp = dotp;
+    task.zchunk = ch.zchunk;
+    stream_grid(L, f32, ch.shape, ch.zchunk, &task.gx, &task.gy, &task.nchunks);
+    const int shape = ch.shape, zc = ch.zchunk;
+    const bool pre = zc == 1, dot = dotp != nullptr;
+    emit_task<StreamTask<T>>(
+        g, g->stage, s, batch_sig(kBkStream, sizeof(T), mode, shape, pre, dot) | ((unsigned long long)g->rec_class << 48),
+        task,
+        task.gx * task.gy * task.nchunks * nrhs,
+        [=](hipStream_t st) {
+          launch_stream<T>(mode, false, shape, L, q, E, u, f, wd, y, zc, nrhs, act, st, LaunchTimer{}, dotp);
+        },
+        [=](const Batch<StreamTask<T>>& b, hipStream_t st) { launch_stream_batch<T>(mode, shape, pre, dot, b, q, st); });
+    return;
+  }
+  const hexmg_grid::Choice c = ch;
+  emit_launch(g, g->stage, s, [=](hipStream_t st) {
+    launch_choice_now<T>(g, c, mode, level, u, f, wd, y, nrhs, st, maskin, act, LaunchTimer{}, dotp);
+  });
 }
 
 // Times the candidate kernels of one level in one precision in each of the
@@ -304,7 +521,7 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
             hipStream_t s, bool maskin = false, const int* act = nullptr, double* dotp = nullptr) {
   const bool f32 = sizeof(T) == 4;
   hipEvent_t a = nullptr, b = nullptr;
-  const bool prof = g->profile && level == 0;
+  const bool prof = g->profile && level == 0 && !g->rec;
   if (prof) {
     a = take_event(g);
     b = take_event(g);
@@ -416,23 +633,43 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   const Level& L = g->lv[l];
   if (l == g->L - 1) {
     wait_coarse(g, s);
-    launch_coarse_gemv<T>(g->nc, g->Ainv, f, out, nrhs, act, s);
+    const int nc = g->nc;
+    const double* Ainv = g->Ainv;
+    GemvTask<T> task{nc, Ainv, f, out, act, gemv_blocks(nc)};
+    emit_task<GemvTask<T>>(
+        g, kStCoarse, s, batch_sig(kBkGemv, sizeof(T)), task, task.gx * nrhs,
+        [=](hipStream_t st) { launch_coarse_gemv<T>(nc, Ainv, f, out, nrhs, act, st); },
+        [](const Batch<GemvTask<T>>& b, hipStream_t st) { launch_coarse_gemv_batch<T>(b, st); });
     return;
   }
   const long long N = 3ll * L.nn;
   const int nu = g->desc.smooth_sweeps;
   T* buf[2] = {v.t[l], out};
   int cur = 0;
-  if (!first_done) launch_jacobi_first<T>(N, v.wd[l], f, buf[0], nrhs, act, s);
+  if (!first_done) {
+    const T* wdl = v.wd[l];
+    T* t0 = buf[0];
+    emit_launch(g, st_down(l, 0), s,
+                [=](hipStream_t st) { launch_jacobi_first<T>(N, wdl, f, t0, nrhs, act, st); });
+  }
   for (int it = 1; it < nu; ++it) {
+    g->stage = st_down(l, it);
     gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act);
     cur = 1 - cur;
   }
+  g->stage = st_down(l, 90);
   gather<T>(g, kResidual, l, buf[cur], f, v.wd[l], v.r[l], nrhs, s, maskin, act);
   // the next level's first sweep is formed inside the restriction (not on the coarsest level)
   const bool fuse = l + 1 < g->L - 1;
-  launch_restrict<T>(L, g->lv[l + 1], v.r[l], v.f[l + 1], nrhs, act, s, fuse ? v.wd[l + 1] : nullptr,
-                     fuse ? v.t[l + 1] : nullptr);
+  {
+    const Level F = L, C = g->lv[l + 1];
+    RestrictTask<T> task{F, C, v.r[l], v.f[l + 1], act, fuse ? v.wd[l + 1] : nullptr, fuse ? v.t[l + 1] : nullptr,
+                         restrict_blocks(C)};
+    emit_task<RestrictTask<T>>(
+        g, st_down(l, 95), s, batch_sig(kBkRestrict, sizeof(T)), task, task.gx * nrhs,
+        [=](hipStream_t st) { launch_restrict<T>(F, C, task.r, task.fc, nrhs, act, st, task.wdc, task.tc); },
+        [](const Batch<RestrictTask<T>>& b, hipStream_t st) { launch_restrict_batch<T>(b, st); });
+  }
   int& tail = sizeof(T) == 4 ? g->tail32 : g->tail64;
   const int blocks = sizeof(T) == 4 ? g->tail_blocks32 : g->tail_blocks64;
   bool done = false;
@@ -445,8 +682,16 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
     }
   }
   if (!done) vcycle_level<T>(g, v, l + 1, v.f[l + 1], v.u[l + 1], nrhs, act, s, fuse);
-  launch_prolong_add<T>(L, g->lv[l + 1], v.u[l + 1], buf[cur], nrhs, act, s);
+  {
+    const Level F = L, C = g->lv[l + 1];
+    ProlongTask<T> task{F, C, v.u[l + 1], buf[cur], act, prolong_blocks(F)};
+    emit_task<ProlongTask<T>>(
+        g, st_up(l, 0), s, batch_sig(kBkProlong, sizeof(T)), task, task.gx * nrhs,
+        [=](hipStream_t st) { launch_prolong_add<T>(F, C, task.ec, task.u, nrhs, act, st); },
+        [](const Batch<ProlongTask<T>>& b, hipStream_t st) { launch_prolong_add_batch<T>(b, st); });
+  }
   for (int it = 0; it < nu; ++it) {
+    g->stage = st_up(l, 1 + it);
     gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act, it == nu - 1 ? dotp : nullptr);
     cur = 1 - cur;
   }
@@ -461,7 +706,21 @@ int sweep_dot_parts(const hexmg_grid* g) {
   const hexmg_grid::Choice& ch = (sizeof(T) == 4 ? g->choice32 : g->choice64)[0][kSmooth];
   if (ch.kernel != HEXMG_KERNEL_STREAM) return 0;
   const int nb = stream_blocks(g->lv[0], sizeof(T) == 4, ch.shape, ch.zchunk);
-  return nb <= kMaxDotParts ? nb : 0;
+  return nb <= kMaxDotParts || nb <= g->big_parts_n ? nb : 0;
+}
+
+// Where a level-0 launch with nb workgroups writes its per-workgroup partials:
+// straight into the consumer's buffer, or (more than a vector kernel's block
+// sums itself) into big_parts, summed by one more small launch (sum_big).
+double* parts_target(hexmg_grid* g, int nb, double* consumer) {
+  return nb <= kMaxDotParts ? consumer : g->big_parts;
+}
+// returns the number of partials the consumer then sums per right-hand side
+int sum_big(hexmg_grid* g, int nb, double* consumer, int nrhs, const int* act, int stage, hipStream_t s) {
+  if (nb <= kMaxDotParts) return nb;
+  const double* parts = g->big_parts;
+  emit_launch(g, stage, s, [=](hipStream_t st) { launch_sum_parts(parts, nb, consumer, nrhs, act, st); });
+  return 1;
 }
 
 // Times the rest of the V-cycle from each level ls >= 1 launched step by step
@@ -549,25 +808,35 @@ int precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials,
   if (g->desc.precision == HEXMG_FP64) {
     VView<double> v = view64(g);
     const int nd = fuse_dot ? sweep_dot_parts<double>(g) : 0;
-    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s, first_done, false, nd ? rz_partials : nullptr);
-    if (nd) return nd;
-    launch_dot_partial(N, r, z, rz_partials, nrhs, act, s);
+    vcycle_level<double>(g, v, 0, r, z, nrhs, act, s, first_done, false,
+                         nd ? parts_target(g, nd, rz_partials) : nullptr);
+    if (nd) return sum_big(g, nd, rz_partials, nrhs, act, kStEnd, s);
+    emit_launch(g, kStEnd, s, [=](hipStream_t st) { launch_dot_partial(N, r, z, rz_partials, nrhs, act, st); });
     return kReduceBlocks;
   }
   VView<float> v = view32(g);
   const int nd = fuse_dot && !write_z ? sweep_dot_parts<float>(g) : 0;
+  float* f32 = g->vf32[0];
+  float* u32 = g->vu32[0];
   if (g->L == 1) {  // the coarsest level is the whole grid: no sweep to fuse into
-    if (!first_done) launch_f64_to_f32(N, r, g->vf32[0], nrhs, act, s);
-    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s);
+    if (!first_done)
+      emit_launch(g, st_down(0, 0), s, [=](hipStream_t st) { launch_f64_to_f32(N, r, f32, nrhs, act, st); });
+    vcycle_level<float>(g, v, 0, f32, u32, nrhs, act, s);
   } else {
-    if (!first_done) launch_jacobi_first_from64(N, g->wd32[0], r, g->vf32[0], g->vt32[0], nrhs, act, s);
-    vcycle_level<float>(g, v, 0, g->vf32[0], g->vu32[0], nrhs, act, s, true, false, nd ? rz_partials : nullptr);
+    if (!first_done) {
+      const float* wd = g->wd32[0];
+      float* t32 = g->vt32[0];
+      emit_launch(g, st_down(0, 0), s,
+                  [=](hipStream_t st) { launch_jacobi_first_from64(N, wd, r, f32, t32, nrhs, act, st); });
+    }
+    vcycle_level<float>(g, v, 0, f32, u32, nrhs, act, s, true, false,
+                        nd ? parts_target(g, nd, rz_partials) : nullptr);
   }
-  if (nd) return nd;
+  if (nd) return sum_big(g, nd, rz_partials, nrhs, act, kStEnd, s);
   if (write_z)
-    launch_to64_dot(N, g->vu32[0], r, z, rz_partials, nrhs, act, s);
+    emit_launch(g, kStEnd, s, [=](hipStream_t st) { launch_to64_dot(N, u32, r, z, rz_partials, nrhs, act, st); });
   else
-    launch_dot_mixed(N, g->vu32[0], r, rz_partials, nrhs, act, s);
+    emit_launch(g, kStEnd, s, [=](hipStream_t st) { launch_dot_mixed(N, u32, r, rz_partials, nrhs, act, st); });
   return kReduceBlocks;
 }
 
@@ -601,7 +870,7 @@ int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc* d) {
   d->penal = 3.0;
   d->precision = HEXMG_FP64;
   d->smooth_sweeps = 2;
-  d->omega = 0.6;
+  d->omega = 0.0;  // automatic: by coarse operator at grid creation
   d->coarse_avg = HEXMG_AVG_DENSITY;
   d->max_nrhs = 1;
   d->kernel = HEXMG_KERNEL_AUTO;
@@ -636,7 +905,10 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   g->L = d->levels;
   make_levels(d, g->lv);
   carve(g, static_cast<char*>(workspace));
-  for (int l = 0; l < g->L; ++l) g->lv[l].mask = g->mask[l];
+  for (int l = 0; l < g->L; ++l) {
+    g->lv[l].mask = g->mask[l];
+    g->lv[l].rowany = g->rowany[l];
+  }
   g->tuned = d->kernel != HEXMG_KERNEL_AUTO;
   g->choice64.assign(g->L, {});
   g->choice32.assign(g->L, {});
@@ -698,6 +970,7 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
     launch_mask_default(g->lv[0], g->mask[0], s);
   }
   for (int l = 1; l < g->L; ++l) launch_mask_inject(g->lv[l - 1], g->lv[l], g->mask[l - 1], g->mask[l], s);
+  for (int l = 0; l < g->L; ++l) launch_row_any(g->lv[l], g->rowany[l], s);
   g->desc.fixed_mask = nullptr;  // copied; do not keep the caller's pointer
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
     return cleanup(fail(HEXMG_ERR_DEVICE, "grid set-up kernels failed"));
@@ -798,13 +1071,20 @@ int hexmg_set_density(hexmg_grid_t g, const double* rho, void* stream) {
     launch_galerkin_first(g->lv[0], g->lv[1], g->E64[0], g->Gc, g->Ke64, g->S64[1], g->S32[1], s);
     for (int l = 1; l + 1 < g->L; ++l)
       launch_galerkin_coarsen(g->lv[l], g->lv[l + 1], g->S64[l], g->S64[l + 1], g->S32[l + 1], s);
+    for (int l = 1; l < g->L; ++l)
+      if (g->S16[l]) launch_stencil_to16(d.stencil_storage, g->lv[l], g->S64[l], g->S16[l], g->Sexp[l], s);
     if (int e = fork_coarsest()) return e;
   }
+  // omega 0 = automatic: 0.6 with re-discretized coarse operators, 0.5 with
+  // Galerkin ones (on black-and-white designs the Galerkin hierarchy has
+  // lambda_max(D^-1 A) of 4-6, where 0.6 lets damped Jacobi amplify the
+  // highest modes)
+  const double omega = d.omega > 0.0 ? d.omega : (g->galerkin ? 0.5 : 0.6);
   if (g->galerkin) {
-    launch_diag(g->lv[0], g->Ke64, g->E64[0], d.omega, g->wd64[0], g->wd32[0], s);
-    for (int l = 1; l < g->L; ++l) launch_stencil_diag(g->lv[l], g->S64[l], d.omega, g->wd64[l], g->wd32[l], s);
+    launch_diag(g->lv[0], g->Ke64, g->E64[0], omega, g->wd64[0], g->wd32[0], s);
+    for (int l = 1; l < g->L; ++l) launch_stencil_diag(g->lv[l], g->S64[l], omega, g->wd64[l], g->wd32[l], s);
   } else {
-    for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], d.omega, g->wd64[l], g->wd32[l], s);
+    for (int l = 0; l < g->L; ++l) launch_diag(g->lv[l], g->Ke64, g->E64[l], omega, g->wd64[l], g->wd32[l], s);
   }
   if (early) HIP_TRY(hipStreamWaitEvent(s, g->ev_read, 0));
   HIP_TRY(hipGetLastError());
@@ -836,6 +1116,8 @@ int hexmg_apply_K(hexmg_grid_t g, int level, int dtype, const void* u, void* y, 
   hipStream_t s = (hipStream_t)stream;
   g->last_stream = s;
   if (nrhs > 65535) return fail(HEXMG_ERR_INVALID, "nrhs must be <= 65535");
+  if (dtype == HEXMG_F32 && g->galerkin && level > 0 && !g->S32[level] && !g->S16[level])
+    return fail(HEXMG_ERR_INVALID, "this grid holds no binary32 stencils (16-bit storage needs a binary32 V-cycle)");
   if (dtype == HEXMG_F64)
     gather<double>(g, kApply, level, (const double*)u, nullptr, nullptr, (double*)y, nrhs, s, true);
   else if (dtype == HEXMG_F32)
@@ -921,10 +1203,17 @@ struct PcgRun {
   hipEvent_t wait_event() const { return ev[(phase == kFinish ? final_slot : target) % 3]; }
   // the scalars of slot k reach the host by a copy (final phase) or, for a CG
   // iteration, written by the iteration's last kernel itself
-  int post(int k, bool copy) {
-    if (copy)
-      HIP_TRY(hipMemcpyAsync(slot(k), g->scalars, (size_t)kScalars * nb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(ev[k % 3], s));
+  int post(int k, bool copy, int stage) {
+    if (copy) {
+      double* dst = slot(k);
+      const double* src = g->scalars;
+      const size_t bytes = (size_t)kScalars * nb * sizeof(double);
+      HIP_TRY(emit_api(g, stage, s, [=](hipStream_t st) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+      }));
+    }
+    hipEvent_t e = ev[k % 3];
+    HIP_TRY(emit_api(g, stage + 1, s, [=](hipStream_t st) { return hipEventRecord(e, st); }));
     return 0;
   }
   // iteration k (1-based): q = A p, alpha, the r update (its x update follows
@@ -940,29 +1229,35 @@ struct PcgRun {
     int npq = 0;
     if (ch.kernel == HEXMG_KERNEL_STREAM) {
       const int nbk = stream_blocks(g->lv[0], f32, ch.shape, ch.zchunk);
-      if (nbk <= kMaxDotParts) npq = nbk;
+      if (nbk <= kMaxDotParts || nbk <= g->big_parts_n) npq = nbk;
     }
+    g->stage = kStEnd + 200;
+    double* pq_target = npq ? parts_target(g, npq, g->partials) : nullptr;
     if (f32)
-      gather<float>(g, kApply, 0, g->p32, nullptr, nullptr, g->q32, nb, s, false, g->active,
-                    npq ? g->partials : nullptr);
+      gather<float>(g, kApply, 0, g->p32, nullptr, nullptr, g->q32, nb, s, false, g->active, pq_target);
     else
-      gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active,
-                     npq ? g->partials : nullptr);
+      gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active, pq_target);
+    if (npq) npq = sum_big(g, npq, g->partials, nb, g->active, kStEnd + 205, s);
     if (!npq) {
+      const long long n = N();
+      const int b = nb;
+      double *p = g->p, *q = g->q, *parts = g->partials;
+      float* q32 = g->q32;
+      const int* act = g->active;
       if (f32)
-        launch_dot_mixed(N(), g->q32, g->p, g->partials, nb, g->active, s);
+        emit_launch(g, kStEnd + 210, s, [=](hipStream_t st) { launch_dot_mixed(n, q32, p, parts, b, act, st); });
       else
-        launch_dot_partial(N(), g->p, g->q, g->partials, nb, g->active, s);
+        emit_launch(g, kStEnd + 210, s, [=](hipStream_t st) { launch_dot_partial(n, p, q, parts, b, act, st); });
       npq = kReduceBlocks;
     }
     // r -= alpha q with the next preconditioner's first sweep (x += alpha p follows in the p update)
     const bool sweep = g->L > 1;
     if (g->desc.precision == HEXMG_FP64) {
-      launch_update_r_first<double, double>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2,
-                                            (k - 1) & 1, g->wd64[0], nullptr, sweep ? g->vt64[0] : nullptr, nb, s);
+      emit_update_r<double, double>(npq, (k - 1) & 1, g->q, g->wd64[0], nullptr, sweep ? g->vt64[0] : nullptr,
+                                    nullptr);
     } else if (!f32) {
-      launch_update_r_first<float, double>(N(), g->partials, npq, sc, g->active, g->q, g->r, g->partials2,
-                                           (k - 1) & 1, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr, nb, s);
+      emit_update_r<float, double>(npq, (k - 1) & 1, g->q, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr,
+                                   nullptr);
     } else {
       // binary32 A p; every rr_every-th iteration of a right-hand side its
       // residual is replaced by the binary64 M f - A x (x brought up to date
@@ -972,20 +1267,68 @@ struct PcgRun {
       const int every = g->desc.rr_every;
       bool replace = false;
       for (int r = 0; r < nb && every > 0; ++r) replace = replace || (k - its_off[r]) % every == 0;
-      if (replace) launch_replace_flags(sc, g->active, g->repl, nb, every, s);
-      launch_update_r_first<float, float>(N(), g->partials, npq, sc, g->active, g->q32, g->r, g->partials2,
-                                          (k - 1) & 1, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr, nb, s,
-                                          replace ? g->repl : nullptr);
+      const int b = nb;
+      const long long n = N();
+      int* repl = g->repl;
+      const int* act = g->active;
+      if (replace)
+        emit_launch(g, kStEnd + 220, s,
+                    [=](hipStream_t st) { launch_replace_flags(sc, act, repl, b, every, st); });
+      emit_update_r<float, float>(npq, (k - 1) & 1, g->q32, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr,
+                                  replace ? g->repl : nullptr);
       if (replace) {
-        launch_flush_x(N(), sc, g->p, u, nb, s, g->repl);
+        double* p = g->p;
+        double* x = u;
+        emit_launch(g, kStEnd + 310, s, [=](hipStream_t st) { launch_flush_x(n, sc, p, x, b, st, repl); });
+        g->stage = kStEnd + 320;
         gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s, false, g->repl);
-        launch_replace_r(g->lv[0], f, g->q, g->r, g->partials2, g->wd32[0], g->vf32[0],
-                         sweep ? g->vt32[0] : nullptr, sc, g->repl, nb, s);
+        const Level L0 = g->lv[0];
+        const double *ff = f, *q = g->q;
+        double *r = g->r, *p2 = g->partials2;
+        const float* wd = g->wd32[0];
+        float *f32v = g->vf32[0], *t32 = sweep ? g->vt32[0] : nullptr;
+        emit_launch(g, kStEnd + 330, s, [=](hipStream_t st) {
+          launch_replace_r(L0, ff, q, r, p2, wd, f32v, t32, sc, repl, b, st);
+        });
       }
     }
-    launch_rr_check(g->partials2, sc, g->active, slot(k), nb, s);
+    {
+      RrCheckTask task{g->partials2, sc, g->active, slot(k)};
+      const int b = nb;
+      emit_task<RrCheckTask>(
+          g, kStEnd + 400, s, batch_sig(kBkRrCheck), task, nb,
+          [=](hipStream_t st) { launch_rr_check(task.rr_partials, task.sc, task.active, task.host_slot, b, st); },
+          [](const Batch<RrCheckTask>& bt, hipStream_t st) { launch_rr_check_batch(bt, st); });
+    }
     issued = k;
-    return post(k, false);
+    return post(k, false, kStEnd + 500);
+  }
+  // r -= alpha q (TQ: q's type) fused with the first sweep, as a batchable task
+  template <typename TW, typename TQ>
+  void emit_update_r(int npq, int parity, const TQ* q, const TW* wd, float* f32, TW* t, const int* repl) {
+    UpdateRTask<TW, TQ> task{N(), g->partials, npq, parity, g->scalars, g->active, q, g->r, g->partials2, wd, f32, t,
+                             repl};
+    const int b = nb;
+    emit_task<UpdateRTask<TW, TQ>>(
+        g, kStEnd + 300, s, batch_sig(kBkUpdateR, sizeof(TW), sizeof(TQ)), task, kReduceBlocks * nb,
+        [=](hipStream_t st) {
+          launch_update_r_first<TW, TQ>(task.n, task.pq_partials, task.npq, task.sc, task.active, task.q, task.r,
+                                        task.rr_partials, task.parity, task.wdinv, task.f32, task.t, b, st,
+                                        task.repl);
+        },
+        [](const Batch<UpdateRTask<TW, TQ>>& bt, hipStream_t st) { launch_update_r_first_batch<TW, TQ>(bt, st); });
+  }
+  template <typename TZ>
+  void emit_update_px(int nrz, int parity, const TZ* z, float* p32) {
+    UpdatePxTask<TZ> task{N(), g->partials, nrz, parity, g->scalars, g->active, z, g->p, u, p32};
+    const int b = nb;
+    emit_task<UpdatePxTask<TZ>>(
+        g, kStEnd + 100, s, batch_sig(kBkUpdatePx, sizeof(TZ)), task, kReduceBlocks * nb,
+        [=](hipStream_t st) {
+          launch_update_px<TZ>(task.n, task.rz_partials, task.nrz, task.sc, task.active, task.z, task.p, task.x,
+                               task.parity, b, st, task.p32);
+        },
+        [](const Batch<UpdatePxTask<TZ>>& bt, hipStream_t st) { launch_update_px_batch<TZ>(bt, st); });
   }
   // z = M^{-1} r (its first sweep already formed), beta, x += alpha p (iteration k)
   // and p = z + beta p, then iteration k+1
@@ -994,11 +1337,10 @@ struct PcgRun {
     g->prof_tag = k + 1 - tag_off;
     if (g->desc.precision == HEXMG_FP64) {
       const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, true, true, true);
-      launch_update_px<double>(N(), g->partials, nrz, g->scalars, g->active, g->z, g->p, u, (k - 1) & 1, nb, s);
+      emit_update_px<double>(nrz, (k - 1) & 1, g->z, nullptr);
     } else {
       const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, false, true, true);
-      launch_update_px<float>(N(), g->partials, nrz, g->scalars, g->active, g->vu32[0], g->p, u, (k - 1) & 1, nb,
-                              s, m32() ? g->p32 : nullptr);
+      emit_update_px<float>(nrz, (k - 1) & 1, g->vu32[0], m32() ? g->p32 : nullptr);
     }
     return issue_iteration(k + 1);
   }
@@ -1008,14 +1350,26 @@ struct PcgRun {
     prev_rr.assign(nb, 0.0);
     its_off.assign(nb, 0);
     limit = maxit;
-    HIP_TRY(hipEventRecord(t0, s));
-    launch_pcg_start(L0, f, g->r, u, g->partials, nb, s);  // r0 = M f, x0 = 0, ||r0||^2 partials
-    launch_pcg_init(rtol > 0.0 ? rtol * rtol : -1.0, g->partials, sc, g->active, nb, s);
+    {
+      hipEvent_t e0 = t0;
+      HIP_TRY(emit_api(g, kStStart, s, [=](hipStream_t st) { return hipEventRecord(e0, st); }));
+    }
+    const int b = nb;
+    const long long n = N();
+    double *r = g->r, *x = u, *parts = g->partials, *p = g->p;
+    float* p32 = g->p32;
+    int* act = g->active;
+    const double* ff = f;
+    const double rt2 = rtol > 0.0 ? rtol * rtol : -1.0;
+    emit_launch(g, kStStart + 1, s, [=](hipStream_t st) {
+      launch_pcg_start(L0, ff, r, x, parts, b, st);  // r0 = M f, x0 = 0, ||r0||^2 partials
+    });
+    emit_launch(g, kStInit, s, [=](hipStream_t st) { launch_pcg_init(rt2, parts, sc, act, b, st); });
     if (maxit == 0) return enqueue_finish(0);
     g->prof_tag = 1;
     precondition(g, g->r, g->p, g->partials, nb, g->active, s);  // p0 = z0 = M^{-1} r0
-    launch_reduce_final(g->partials, sc + kRz0, kScalars, nb, s);
-    if (m32()) launch_f64_to_f32(N(), g->p, g->p32, nb, g->active, s);
+    emit_launch(g, kStEnd + 10, s, [=](hipStream_t st) { launch_reduce_final(parts, sc + kRz0, kScalars, b, st); });
+    if (m32()) emit_launch(g, kStEnd + 20, s, [=](hipStream_t st) { launch_f64_to_f32(n, p, p32, b, act, st); });
     if (int e = issue_iteration(1)) return e;
     if (maxit >= 2)
       if (int e = issue_next()) return e;
@@ -1043,14 +1397,28 @@ struct PcgRun {
     ++restarts;
     tag_off = issued - last_its;
     limit = issued + (maxit - its_min);
-    launch_pcg_restart(sc, g->active, nb, maxit, s);
+    const int b = nb, mx = maxit;
+    const long long n = N();
+    int* act = g->active;
+    emit_launch(g, kStRestart, s, [=](hipStream_t st) { launch_pcg_restart(sc, act, b, mx, st); });
     const bool sweep = g->L > 1;
-    launch_replace_r(g->lv[0], f, g->q, g->r, g->partials2, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr,
-                     sc, g->active, nb, s);
+    {
+      const Level L0 = g->lv[0];
+      const double *ff = f, *q = g->q;
+      double *r = g->r, *p2 = g->partials2;
+      const float* wd = g->wd32[0];
+      float *f32v = g->vf32[0], *t32 = sweep ? g->vt32[0] : nullptr;
+      emit_launch(g, kStReplace, s,
+                  [=](hipStream_t st) { launch_replace_r(L0, ff, q, r, p2, wd, f32v, t32, sc, act, b, st); });
+    }
     g->prof_tag = k1 - tag_off;
     precondition(g, g->r, g->p, g->partials, nb, g->active, s, true, true);  // p = z = M^{-1} r
-    launch_reduce_final(g->partials, sc + kRz0 + ((k1 - 1) & 1), kScalars, nb, s);
-    launch_f64_to_f32(N(), g->p, g->p32, nb, g->active, s);
+    double *parts = g->partials, *p = g->p;
+    float* p32 = g->p32;
+    const int par = (k1 - 1) & 1;
+    emit_launch(g, kStEnd + 10, s,
+                [=](hipStream_t st) { launch_reduce_final(parts, sc + kRz0 + par, kScalars, b, st); });
+    emit_launch(g, kStEnd + 20, s, [=](hipStream_t st) { launch_f64_to_f32(n, p, p32, b, act, st); });
     if (int e = issue_iteration(k1)) return e;
     if (k1 + 1 <= limit)
       if (int e = issue_next()) return e;
@@ -1060,16 +1428,28 @@ struct PcgRun {
     return 0;
   }
   int enqueue_finish(int read) {
-    const Level& L0 = g->lv[0];
+    const Level L0 = g->lv[0];
     double* sc = g->scalars;
-    launch_flush_x(N(), sc, g->p, u, nb, s);  // the last iteration's x += alpha p
-    HIP_TRY(hipEventRecord(t1, s));
+    const int b = nb;
+    const long long n = N();
+    double *p = g->p, *x = u, *q = g->q, *pa = g->partials, *pb = g->partials2;
+    const double* ff = f;
+    emit_launch(g, kStEnd + 600, s, [=](hipStream_t st) {
+      launch_flush_x(n, sc, p, x, b, st);  // the last iteration's x += alpha p
+    });
+    {
+      hipEvent_t e1 = t1;
+      HIP_TRY(emit_api(g, kStEnd + 610, s, [=](hipStream_t st) { return hipEventRecord(e1, st); }));
+    }
     g->prof_tag = 0;
+    g->stage = kStEnd + 620;
     gather<double>(g, kApply, 0, u, nullptr, nullptr, g->q, nb, s);  // true residual in binary64
-    launch_pcg_final(L0, f, g->q, u, g->partials, g->partials2, sc, nb, s);  // ||M f - A x||^2, f . x
+    emit_launch(g, kStEnd + 630, s, [=](hipStream_t st) {
+      launch_pcg_final(L0, ff, q, x, pa, pb, sc, b, st);  // ||M f - A x||^2, f . x
+    });
     final_slot = read + 2;  // a slot no result in flight is written to
     phase = kFinish;
-    return post(final_slot, true);
+    return post(final_slot, true, kStEnd + 640);
   }
   // Whether the iteration after `target` (already in flight) is expected to
   // meet the stop test for every active right-hand side: ||r||^2 shrinking by
@@ -1157,6 +1537,42 @@ int drive(std::vector<PcgRun>& runs) {
   }
 }
 
+// Drives runs of distinct grids on one stream with their launches batched:
+// every round records the next launches of every pending run (each run still
+// decides on its own, from its own scalars) and then launches them together,
+// one launch per place in the iteration and kernel signature for all grids.
+int drive_batched(std::vector<PcgRun>& runs, BatchRecorder& rec, hipStream_t s) {
+  for (size_t i = 0; i < runs.size(); ++i) {
+    runs[i].g->rec = &rec;
+    runs[i].g->rec_grid = (int)i;
+  }
+  int e = 0;
+  for (auto& r : runs)
+    if (!e) e = r.begin();
+  bool pending = true;
+  while (!e) {
+    const hipError_t he = rec.flush(s);
+    if (he != hipSuccess) {
+      e = fail(HEXMG_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(he));
+      break;
+    }
+    if (!pending) break;
+    pending = false;
+    for (auto& r : runs) {
+      if (r.phase == PcgRun::kDone) continue;
+      pending = true;
+      if (hipEventSynchronize(r.wait_event()) != hipSuccess) {
+        e = fail(HEXMG_ERR_DEVICE, "event wait failed");
+        break;
+      }
+      if ((e = r.advance())) break;
+    }
+  }
+  if (e) rec.recs.clear();
+  for (auto& r : runs) r.g->rec = nullptr;
+  return e;
+}
+
 int combine_status(int worst, int st) {
   if (st < 0) return st;
   if (worst >= 0 && st > worst) return st;
@@ -1211,59 +1627,63 @@ int hexmg_batch_solve(hexmg_grid_t* grids, int ngrids, const double* const* f, d
       if (grids[j] == grids[i]) return fail(HEXMG_ERR_INVALID, "a grid appears twice in the batch");
   }
   hipStream_t s = (hipStream_t)stream;
-  // Fork: each grid runs on a stream of its own (default priority), after the
-  // work already queued on the caller's stream; join at the end.
-  hipEvent_t fork = nullptr;
-  HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-  HIP_TRY(hipEventRecord(fork, s));
-  std::vector<PcgRun> runs(ngrids);
-  // The grids run concurrently on their own streams; two cooperative launches
-  // resident at once could each hold workgroups the other's grid barrier waits
-  // for, so the coarse part of the cycle is launched step by step here.
-  struct Tail { int t64, t32; };
-  std::vector<Tail> saved(ngrids);
+  // All grids run on the caller's stream; their launches are batched (see
+  // drive_batched).  Batched launches of the streaming kernel share the block
+  // coefficients of K0, so grids whose Poisson ratios differ go in separate
+  // launches (a class per distinct ratio).  The cooperative coarse-cycle launch
+  // is not batched: the coarse part of the cycle is launched step by step.
+  struct Saved { int t64, t32; };
+  std::vector<Saved> saved(ngrids);
+  std::vector<double> nus;
   for (int i = 0; i < ngrids; ++i) {
-    saved[i] = {grids[i]->tail64, grids[i]->tail32};
-    grids[i]->tail64 = grids[i]->tail32 = 0;
-  }
-  int e = 0, off = 0;
-  for (int i = 0; i < ngrids && !e; ++i) {
     hexmg_grid* g = grids[i];
-    if (!g->own_stream && hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking) != hipSuccess)
-      e = fail(HEXMG_ERR_DEVICE, "stream creation failed");
-    if (!e && hipStreamWaitEvent(g->own_stream, fork, 0) != hipSuccess) e = fail(HEXMG_ERR_DEVICE, "stream wait failed");
+    saved[i] = {g->tail64, g->tail32};
+    g->tail64 = g->tail32 = 0;
+    g->last_stream = s;
+    size_t k = 0;
+    while (k < nus.size() && nus[k] != g->desc.nu) ++k;
+    if (k == nus.size()) nus.push_back(g->desc.nu);
+    g->rec_class = (int)k;
+  }
+  int worst = 0, e = 0;
+  // right-hand sides beyond max_nrhs are not batched: nrhs[i] <= max_nrhs (checked above)
+  std::vector<PcgRun> runs(ngrids);
+  int off = 0;
+  for (int i = 0; i < ngrids && !e; ++i) {
     PcgRun& r = runs[i];
-    r.g = g;
+    r.g = grids[i];
     r.f = f[i];
     r.u = u[i];
     r.nb = nrhs[i];
     r.rtol = rtol;
     r.maxit = maxit;
-    r.s = g->own_stream;
+    r.s = s;
     r.info = infos ? infos + off : nullptr;
     off += nrhs[i];
-    if (!e) e = r.init();
+    e = r.init();
   }
-  if (!e) e = drive(runs);
-  int worst = 0;
-  for (auto& r : runs) {
-    if (!e && r.s) {
-      if (hipEventRecord(r.ev[0], r.s) != hipSuccess || hipStreamWaitEvent(s, r.ev[0], 0) != hipSuccess)
-        e = fail(HEXMG_ERR_DEVICE, "join failed");
-    }
-    worst = combine_status(worst, r.status);
-  }
+  BatchRecorder rec(ngrids);
+  if (!e) e = drive_batched(runs, rec, s);
+  for (auto& r : runs) worst = combine_status(worst, r.status);
   if (!e) (void)hipStreamSynchronize(s);
   for (auto& r : runs) r.release();
   for (int i = 0; i < ngrids; ++i) {
     grids[i]->tail64 = saved[i].t64;
     grids[i]->tail32 = saved[i].t32;
+    grids[i]->batch_launches = rec.launches;
+    grids[i]->batch_records = rec.records;
   }
-  (void)hipEventDestroy(fork);
   if (e) return e;
   if (worst == HEXMG_ERR_BREAKDOWN) return fail(worst, "PCG breakdown in the batch");
   if (worst == HEXMG_NOT_CONVERGED) g_err = "not converged within maxit";
   return worst;
+}
+
+int hexmg_batch_stats(hexmg_grid_t g, size_t* launches, size_t* recorded) {
+  if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
+  if (launches) *launches = g->batch_launches;
+  if (recorded) *recorded = g->batch_records;
+  return 0;
 }
 
 int hexmg_compliance_sensitivity(hexmg_grid_t g, const double* f, const double* u, int nrhs,
@@ -1365,8 +1785,16 @@ int hexmg_apply_passive(long long n, const uint8_t* passive, double* x, void* st
   return 0;
 }
 
+int hexmg_volume_weights(hexmg_grid_t g, const uint8_t* passive, double* dv, void* stream) {
+  if (!g || !passive || !dv) return fail(HEXMG_ERR_INVALID, "null argument");
+  launch_volume_weights(g->lv[0].ne, passive, g->flags, dv, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int hexmg_oc_update(hexmg_grid_t g, const double* x, const double* dc, const double* dv, double volfrac,
-                    double move, double eta, double* x_new, double* lambda_host, void* stream) {
+                    double move, double eta, double* x_new, double* lambda_host, double* change_host,
+                    double* volume_host, void* stream) {
   if (!g || !x || !dc || !dv || !x_new) return fail(HEXMG_ERR_INVALID, "null argument");
   if (x_new == x || x_new == dc || x_new == dv) return fail(HEXMG_ERR_INVALID, "x_new must not overlap the inputs");
   if (!(volfrac > 0.0 && volfrac < 1.0) || !(move > 0.0 && move <= 1.0) || !(eta > 0.0 && eta <= 1.0))
@@ -1404,8 +1832,14 @@ int hexmg_oc_update(hexmg_grid_t g, const double* x, const double* dc, const dou
     ++passes;
   }
   const double lam = std::exp(0.5 * (lo + hi));
-  launch_oc_apply(n, x, dc, dv, eta, move, std::exp(-eta * 0.5 * (lo + hi)), x_new, s);
+  launch_oc_apply(n, x, dc, dv, eta, move, std::exp(-eta * 0.5 * (lo + hi)), x_new, g->oc_partials, g->oc_vol, s);
   HIP_TRY(hipGetLastError());
+  if (change_host || volume_host) {
+    HIP_TRY(hipMemcpyAsync(g->host_scalars, g->oc_vol, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (change_host) *change_host = g->host_scalars[0];
+    if (volume_host) *volume_host = g->host_scalars[1];
+  }
   if (lambda_host) *lambda_host = lam;
   return 0;
 }
@@ -1417,11 +1851,12 @@ int hexmg_element_matrix(double nu, double* Ke) {
   return 0;
 }
 
-int hexmg_kernel_choice(hexmg_grid_t g, int level, int dtype, int* kernel, int* zchunk, int* shape) {
+int hexmg_kernel_choice(hexmg_grid_t g, int level, int dtype, int mode, int* kernel, int* zchunk, int* shape) {
   if (!g) return fail(HEXMG_ERR_INVALID, "null grid");
   if (level < 0 || level >= g->L) return fail(HEXMG_ERR_INVALID, "bad level");
   if (dtype != HEXMG_F64 && dtype != HEXMG_F32) return fail(HEXMG_ERR_INVALID, "bad dtype");
-  const hexmg_grid::Choice& c = (dtype == HEXMG_F64 ? g->choice64[level] : g->choice32[level])[kSmooth];
+  if (mode < 0 || mode > 2) return fail(HEXMG_ERR_INVALID, "mode must be 0 (K u), 1 (sweep) or 2 (residual)");
+  const hexmg_grid::Choice& c = (dtype == HEXMG_F64 ? g->choice64[level] : g->choice32[level])[mode];
   if (kernel) *kernel = c.kernel;
   if (zchunk) *zchunk = c.zchunk;
   if (shape) *shape = c.shape;

@@ -14,6 +14,18 @@
 // G_c = P_c^T K0 P_c (24x24, constant, computed on the host), except where a
 // child touches a fixed fine DOF: there the masked product is formed on the
 // fly.  Deeper levels take the triple product of the stencils.
+//
+// Storage of the binary32 V-cycle's stencils: binary32, or 16 bits per
+// coefficient (half the bytes of the HBM-bound stencil sweep).  bfloat16 keeps
+// binary32's exponent range; binary16 keeps 3 more significand bits but not the
+// range (the coefficients span Emin..E0 times 2^l), so each node's 243
+// coefficients are stored scaled by a power of two that brings the row's
+// largest magnitude into [2^14, 2^15), and the sweep applies 2^-s to the row
+// sums.  Both are rounded to nearest from the binary64 stencil (bfloat16
+// through binary32).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
 #include "hexmg_impl.h"
 #include "node_ops.h"
 
@@ -42,7 +54,7 @@ __device__ inline void store_block(const Level& C, int m, int m2, int o, const d
       if (o == 13 && ci == cj && ((mk >> ci) & 1)) v = 1.0;
       const long long idx = (long long)(9 * o + 3 * ci + cj) * C.nn + m;
       S64[idx] = v;
-      S32[idx] = (float)v;
+      if (S32) S32[idx] = (float)v;  // absent when the binary32 V-cycle reads 16-bit coefficients
     }
 }
 
@@ -163,12 +175,59 @@ __global__ void k_galerkin_coarsen(Level F, Level C, const double* __restrict__ 
   store_block(C, m, m2, o, blk, S64, S32);
 }
 
+// One node's 243 binary64 coefficients to 16 bits: bfloat16 (STORE ==
+// HEXMG_STENCIL_BF16) or binary16 scaled by 2^s[n] (HEXMG_STENCIL_F16).
+template <int STORE>
+__global__ void k_stencil_to16(Level L, const double* __restrict__ S64, uint16_t* __restrict__ S16,
+                               int8_t* __restrict__ sexp) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= L.nn) return;
+  if (STORE == HEXMG_STENCIL_BF16) {
+    for (int q = 0; q < 243; ++q) {
+      const long long idx = (long long)q * L.nn + n;
+      S16[idx] = __bfloat16_as_ushort(__float2bfloat16((float)S64[idx]));
+    }
+    return;
+  }
+  double amax = 0.0;
+  for (int q = 0; q < 243; ++q) amax = fmax(amax, fabs(S64[(long long)q * L.nn + n]));
+  int e = 0;
+  if (amax > 0.0) (void)frexp(amax, &e);  // amax in [2^(e-1), 2^e)
+  const int sc = min(max(15 - e, -126), 126);  // amax * 2^sc in [2^14, 2^15)
+  sexp[n] = (int8_t)max(min(sc, 127), -127);
+  for (int q = 0; q < 243; ++q) {
+    const long long idx = (long long)q * L.nn + n;
+    const _Float16 h = (_Float16)ldexp(S64[idx], sexp[n]);
+    S16[idx] = __builtin_bit_cast(uint16_t, h);
+  }
+}
+
+__device__ inline float stencil_coef(const float* S, long long i) { return S[i]; }
+__device__ inline double stencil_coef(const double* S, long long i) { return S[i]; }
+
+// 16-bit coefficients (bfloat16 or binary16, by storage type tag)
+struct Bf16Tag {};
+struct F16Tag {};
+template <typename Tag>
+struct Stored16 {
+  const uint16_t* p;
+};
+__device__ inline float stencil_coef(Stored16<Bf16Tag> S, long long i) {
+  return __uint_as_float((unsigned)S.p[i] << 16);
+}
+__device__ inline float stencil_coef(Stored16<F16Tag> S, long long i) {
+  return __half2float(__ushort_as_half(S.p[i]));
+}
+
 // y = A u from the stencil (MODE as the element kernels: 0 A u, 1 Jacobi
-// sweep, 2 residual); grid (ceil(nn / kBlock), nrhs).
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stencil(Level L, const T* __restrict__ S, const T* __restrict__ u,
-                                                    const T* __restrict__ f, const T* __restrict__ wdinv,
-                                                    T* __restrict__ y, const int* __restrict__ act) {
+// sweep, 2 residual); grid (ceil(nn / kBlock), nrhs).  SP: the coefficient
+// array (T*, or Stored16<tag> for the 16-bit storages); sexp: the binary16
+// rows' scale exponents (null otherwise).
+template <typename T, typename SP, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(Level L, SP S, const int8_t* __restrict__ sexp,
+                                                    const T* __restrict__ u, const T* __restrict__ f,
+                                                    const T* __restrict__ wdinv, T* __restrict__ y,
+                                                    const int* __restrict__ act) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= L.nn || (act && !act[blockIdx.y])) return;
   const long long off = 3ll * L.nn * blockIdx.y;
@@ -185,11 +244,17 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Level L, const T* __restrict
     if (ii < 0 || ii >= L.nxn || jj < 0 || jj >= L.nyn || kk < 0 || kk >= L.nzn) continue;
     const T* un = u + 3ll * (n + dx + L.nxn * (dy + L.nyn * dz));
     const T v0 = un[0], v1 = un[1], v2 = un[2];
-    const T* s = S + (long long)(9 * o) * L.nn + n;
+    const long long s0 = (long long)(9 * o) * L.nn + n;
     const long long st = L.nn;
-    a0 += s[0] * v0 + s[st] * v1 + s[2 * st] * v2;
-    a1 += s[3 * st] * v0 + s[4 * st] * v1 + s[5 * st] * v2;
-    a2 += s[6 * st] * v0 + s[7 * st] * v1 + s[8 * st] * v2;
+    a0 += stencil_coef(S, s0) * v0 + stencil_coef(S, s0 + st) * v1 + stencil_coef(S, s0 + 2 * st) * v2;
+    a1 += stencil_coef(S, s0 + 3 * st) * v0 + stencil_coef(S, s0 + 4 * st) * v1 + stencil_coef(S, s0 + 5 * st) * v2;
+    a2 += stencil_coef(S, s0 + 6 * st) * v0 + stencil_coef(S, s0 + 7 * st) * v1 + stencil_coef(S, s0 + 8 * st) * v2;
+  }
+  if (sexp) {  // binary16 rows were stored scaled by 2^s
+    const int e = -sexp[n];
+    a0 = ldexp(a0, e);
+    a1 = ldexp(a1, e);
+    a2 = ldexp(a2, e);
   }
   const long long b = 3ll * n;
   if (MODE == kApply) {
@@ -251,16 +316,42 @@ void launch_galerkin_coarsen(const Level& F, const Level& C, const double* Sf, d
   k_galerkin_coarsen<<<dim3(blocks_for(C.nn), 27), kBlock, 0, s>>>(F, C, Sf, S64, S32);
 }
 
+namespace {
+template <typename T, typename SP>
+void launch_stencil_sp(int mode, const Level& L, SP S, const int8_t* sexp, const T* u, const T* f, const T* wd,
+                       T* y, int nrhs, const int* act, hipStream_t s, const LaunchTimer& t) {
+  const dim3 g(blocks_for(L.nn), nrhs);
+  if (mode == kApply)
+    launch_timed(k_stencil<T, SP, kApply>, g, dim3(kBlock), s, t, L, S, sexp, u, f, wd, y, act);
+  else if (mode == kSmooth)
+    launch_timed(k_stencil<T, SP, kSmooth>, g, dim3(kBlock), s, t, L, S, sexp, u, f, wd, y, act);
+  else
+    launch_timed(k_stencil<T, SP, kResidual>, g, dim3(kBlock), s, t, L, S, sexp, u, f, wd, y, act);
+}
+}  // namespace
+
 template <typename T>
 void launch_stencil(int mode, const Level& L, const T* S, const T* u, const T* f, const T* wd, T* y, int nrhs,
                     const int* act, hipStream_t s, const LaunchTimer& t) {
-  const dim3 g(blocks_for(L.nn), nrhs);
-  if (mode == kApply)
-    launch_timed(k_stencil<T, kApply>, g, dim3(kBlock), s, t, L, S, u, f, wd, y, act);
-  else if (mode == kSmooth)
-    launch_timed(k_stencil<T, kSmooth>, g, dim3(kBlock), s, t, L, S, u, f, wd, y, act);
+  launch_stencil_sp<T, const T*>(mode, L, S, nullptr, u, f, wd, y, nrhs, act, s, t);
+}
+
+void launch_stencil16(int store, int mode, const Level& L, const uint16_t* S16, const int8_t* sexp, const float* u,
+                      const float* f, const float* wd, float* y, int nrhs, const int* act, hipStream_t s,
+                      const LaunchTimer& t) {
+  if (store == HEXMG_STENCIL_BF16)
+    launch_stencil_sp<float, Stored16<Bf16Tag>>(mode, L, Stored16<Bf16Tag>{S16}, nullptr, u, f, wd, y, nrhs, act,
+                                                 s, t);
   else
-    launch_timed(k_stencil<T, kResidual>, g, dim3(kBlock), s, t, L, S, u, f, wd, y, act);
+    launch_stencil_sp<float, Stored16<F16Tag>>(mode, L, Stored16<F16Tag>{S16}, sexp, u, f, wd, y, nrhs, act, s, t);
+}
+
+void launch_stencil_to16(int store, const Level& L, const double* S64, uint16_t* S16, int8_t* sexp,
+                         hipStream_t s) {
+  if (store == HEXMG_STENCIL_BF16)
+    k_stencil_to16<HEXMG_STENCIL_BF16><<<blocks_for(L.nn), kBlock, 0, s>>>(L, S64, S16, sexp);
+  else
+    k_stencil_to16<HEXMG_STENCIL_F16><<<blocks_for(L.nn), kBlock, 0, s>>>(L, S64, S16, sexp);
 }
 template void launch_stencil<double>(int, const Level&, const double*, const double*, const double*, const double*,
                                      double*, int, const int*, hipStream_t, const LaunchTimer&);

@@ -25,7 +25,12 @@ struct Level {
   int nn;             // node count
   int ne;             // element count
   const uint8_t* mask;  // per-node support bits (device)
+  // per 62-column segment s (nodes 62 s - 1 .. 62 s + 62, the columns of a
+  // streaming tile with its halo) of node row (j, k): 1 if a node there has a
+  // fixed DOF; at rowany[s + segs * (j + nyn * k)], segs = ceil(nxn / 62)
+  const uint8_t* rowany;
 };
+__host__ __device__ inline int row_segments(const Level& L) { return (L.nxn + 61) / 62; }
 
 // Haar-basis block coefficients of the unit element (already divided by 64):
 // normal block diag-off d1 and off b1, rank-one shear g, bilinear 2x2 (a2, b2),
@@ -71,8 +76,138 @@ void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarC
                    const LaunchTimer& t = {}, double* dotp = nullptr);
 // workgroups of one right-hand side's launch of the streaming kernel
 int stream_blocks(const Level& L, bool f32, int shape, int zchunk);
+
+// ---------------------------------------------------------------------------
+// Launches that cover several grids (hexmg_batch_solve).  A batched launch
+// carries a table of tasks (one per grid, each the arguments of that grid's own
+// launch) by value in its kernel arguments; workgroup b belongs to the task t
+// with begin[t] <= b < begin[t + 1] and does what workgroup b - begin[t] of the
+// grid's own launch would do, so every grid's arithmetic is that of its single
+// launch.
+constexpr int kMaxBatch = 24;
+template <typename A>
+struct Batch {
+  int n = 0;
+  int begin[kMaxBatch + 1] = {};
+  A a[kMaxBatch];
+};
+__device__ inline int batch_task(const int* begin, int n, int b) {
+  int lo = 0, hi = n - 1;  // largest t with begin[t] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+template <typename T>
+struct StreamTask {
+  Level L;
+  const T* E;
+  const T* u;
+  const T* f;
+  const T* wd;
+  T* y;
+  const int* act;
+  double* dotp;
+  int zchunk, nchunks, gx, gy;
+};
+// mode, shape and pre (z-chunk of one preloaded plane) and dot (partials of the
+// mode's dot product) are common to the batch.
+template <typename T>
+void launch_stream_batch(int mode, int shape, bool pre, bool dot, const Batch<StreamTask<T>>& b,
+                         const HaarCoef<T>& q, hipStream_t s);
+// the launch grid of one grid's streaming-kernel launch: (gx, gy, nchunks)
+void stream_grid(const Level& L, bool f32, int shape, int zchunk, int* gx, int* gy, int* nchunks);
+
+// Tasks of the other batched kernels: the arguments of the single launch and
+// gx, the workgroups per right-hand side of that launch (the vector kernels
+// always use kReduceBlocks).  Launchers in kernels.hip.
+template <typename T>
+struct RestrictTask {
+  Level F, C;
+  const T* r;
+  T* fc;
+  const int* act;
+  const T* wdc;
+  T* tc;
+  int gx;
+};
+template <typename T>
+struct ProlongTask {
+  Level F, C;
+  const T* ec;
+  T* u;
+  const int* act;
+  int gx;
+};
+template <typename T>
+struct GemvTask {
+  int n;
+  const double* Ainv;
+  const T* x;
+  T* y;
+  const int* act;
+  int gx;
+};
+template <typename TW, typename TQ>
+struct UpdateRTask {
+  long long n;
+  const double* pq_partials;
+  int npq, parity;
+  double* sc;
+  const int* active;
+  const TQ* q;
+  double* r;
+  double* rr_partials;
+  const TW* wdinv;
+  float* f32;
+  TW* t;
+  const int* repl;
+};
+struct RrCheckTask {
+  const double* rr_partials;
+  double* sc;
+  int* active;
+  double* host_slot;
+};
+template <typename TZ>
+struct UpdatePxTask {
+  long long n;
+  const double* rz_partials;
+  int nrz, parity;
+  double* sc;
+  const int* active;
+  const TZ* z;
+  double* p;
+  double* x;
+  float* p32;
+};
+template <typename T>
+void launch_restrict_batch(const Batch<RestrictTask<T>>& b, hipStream_t s);
+template <typename T>
+void launch_prolong_add_batch(const Batch<ProlongTask<T>>& b, hipStream_t s);
+template <typename T>
+void launch_coarse_gemv_batch(const Batch<GemvTask<T>>& b, hipStream_t s);
+template <typename TW, typename TQ>
+void launch_update_r_first_batch(const Batch<UpdateRTask<TW, TQ>>& b, hipStream_t s);
+void launch_rr_check_batch(const Batch<RrCheckTask>& b, hipStream_t s);
+template <typename TZ>
+void launch_update_px_batch(const Batch<UpdatePxTask<TZ>>& b, hipStream_t s);
+// the task tables travel in the kernel arguments
+static_assert(sizeof(Batch<StreamTask<double>>) <= 4096, "stream task table too large for kernel arguments");
+static_assert(sizeof(Batch<RestrictTask<double>>) <= 4096, "restriction task table too large for kernel arguments");
+static_assert(sizeof(Batch<UpdateRTask<double, double>>) <= 4096, "update task table too large for kernel arguments");
+// workgroups per right-hand side of the single launches
+int restrict_blocks(const Level& C);
+int prolong_blocks(const Level& F);
+int gemv_blocks(int n);
 // most partials a fused dot product may leave per right-hand side
-constexpr int kMaxDotParts = 8192;
+constexpr int kMaxDotParts = 8192;  // partials a vector kernel's block sums itself
+// out[r] = sum of parts[r * n .. r * n + n) (fixed order; inactive r skipped)
+void launch_sum_parts(const double* parts, int n, double* out, int nrhs, const int* act, hipStream_t s);
 
 constexpr int kReduceBlocks = 1024;  // partial sums per reduction (fixed: deterministic)
 constexpr int kOcProbes = 32;       // Lagrange multipliers evaluated per OC pass
@@ -114,6 +249,8 @@ void launch_coarsest_moduli(const Level& F, const Level& C, int blk, const doubl
 void launch_diag(const Level& L, const double* Ke, const double* E, double omega, double* wdinv64,
                  float* wdinv32, hipStream_t s);
 void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s);
+// rowany of a level from its mask
+void launch_row_any(const Level& L, uint8_t* rowany, hipStream_t s);
 void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8_t* mc, hipStream_t s);
 void launch_or_flags(int n, const int* flags, int* out, hipStream_t s);
 
@@ -207,8 +344,12 @@ struct OcProbes {
 };
 void launch_oc_probe(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
                      const OcProbes& lam_pow, double* partials, double* vol, hipStream_t s);
+// x_new at the final multiplier; out[0] = max |x_new - x|, out[1] = dv . x_new
+// (partials: 2 kReduceBlocks doubles of scratch)
 void launch_oc_apply(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
-                     double lam_pow, double* xn, hipStream_t s);
+                     double lam_pow, double* xn, double* partials, double* out, hipStream_t s);
+// dv_e = [passive_e == 0] / (number of such elements); count: one int of scratch
+void launch_volume_weights(long long n, const uint8_t* passive, int* count, double* dv, hipStream_t s);
 
 // Galerkin coarse operators (galerkin.hip): 27-point block stencils,
 // coefficient (9 o + 3 ci + cj) of node n at S[(9 o + 3 ci + cj) * nn + n].
@@ -219,6 +360,14 @@ void launch_galerkin_coarsen(const Level& F, const Level& C, const double* Sf, d
 template <typename T>
 void launch_stencil(int mode, const Level& L, const T* S, const T* u, const T* f, const T* wd, T* y, int nrhs,
                     const int* act, hipStream_t s, const LaunchTimer& t = {});
+// The binary32 stencil sweep with 16-bit coefficients (store = HEXMG_STENCIL_BF16
+// or HEXMG_STENCIL_F16; sexp: binary16 rows' scale exponents), and the
+// conversion of a binary64 stencil into that storage.
+void launch_stencil16(int store, int mode, const Level& L, const uint16_t* S16, const int8_t* sexp, const float* u,
+                      const float* f, const float* wd, float* y, int nrhs, const int* act, hipStream_t s,
+                      const LaunchTimer& t = {});
+void launch_stencil_to16(int store, const Level& L, const double* S64, uint16_t* S16, int8_t* sexp,
+                         hipStream_t s);
 void launch_stencil_diag(const Level& L, const double* S, double omega, double* wd64, float* wd32, hipStream_t s);
 void launch_dense_from_stencil(const Level& C, const double* S, double* A, hipStream_t s);
 void galerkin_child_matrices(const double* Ke, double* G);  // host: 8 x 576
@@ -272,6 +421,10 @@ enum ScalarSlot {
 
 }  // namespace hexmg
 
+namespace hexmg {
+struct BatchRecorder;  // api.hip
+}
+
 // The opaque grid object behind hexmg_grid_t.
 struct hexmg_grid {
   hexmg_grid_desc desc;
@@ -284,6 +437,7 @@ struct hexmg_grid {
   std::vector<double*> wd64;     // omega / diag(A_l)
   std::vector<float*> wd32;
   std::vector<uint8_t*> mask;
+  std::vector<uint8_t*> rowany;  // per level: fixed DOFs in a tile's row segment (see Level)
   // V-cycle vectors per level: f (rhs), u (solution), t (ping-pong), r (residual)
   std::vector<double*> vf64, vu64, vt64, vr64;
   std::vector<float*> vf32, vu32, vt32, vr32;
@@ -299,6 +453,8 @@ struct hexmg_grid {
   bool galerkin = false;
   std::vector<double*> S64;
   std::vector<float*> S32;
+  std::vector<uint16_t*> S16;  // 16-bit coefficients (stencil_storage != HEXMG_STENCIL_F32)
+  std::vector<int8_t*> Sexp;   // binary16 rows' scale exponents
   double* Gc = nullptr;
   std::vector<double> Gc_host;
   hexmg::HaarCoef<double> hq64;
@@ -317,6 +473,8 @@ struct hexmg_grid {
   float *p32, *q32;  // binary32 p and A p of HEXMG_MIXED32 (else null)
   double* partials;
   double* partials2;
+  double* big_parts = nullptr;  // per-workgroup partials of level-0 launches beyond kMaxDotParts workgroups
+  int big_parts_n = 0;          // its capacity per right-hand side
   double* scalars;
   int* flags;     // per-block status flags (kReduceBlocks) + 1 result
   int* active;    // per right-hand side: 1 while its CG iteration runs
@@ -344,6 +502,14 @@ struct hexmg_grid {
   struct Rec { int family; hipEvent_t a, b; int tag; };
   std::vector<Rec> recs;
   int prof_tag = 0;
+  // hexmg_batch_solve: while rec is set, this grid's PCG and V-cycle launches
+  // are recorded, each with its place in the iteration (stage), and launched
+  // later together with the other grids' launches of the same place
+  hexmg::BatchRecorder* rec = nullptr;
+  int rec_grid = 0;  // this grid's index in the batch
+  int stage = 0;     // place of the next recorded element-product launch
+  int rec_class = 0; // batched streaming-kernel launches only combine grids of one class (equal K0)
+  size_t batch_launches = 0, batch_records = 0;  // of the last batched solve this grid took part in
   std::vector<hipEvent_t> event_pool;
   double prof_ms[8];
   int prof_count[8];

@@ -98,22 +98,47 @@ __global__ void k_jacobi_first_from64(long long n, const float* __restrict__ wdi
 
 // Coarse right-hand side f_c = M_c P^T r (see restrict_node); with wdc set,
 // also the coarse level's first Jacobi sweep from zero, tc = wdc * f_c.
+// (bx, rhs): the workgroup's place in a launch of (ceil(C.nn / kBlock), nrhs).
+template <typename T>
+__device__ __forceinline__ void restrict_block(const Level& F, const Level& C, const T* __restrict__ r,
+                                               T* __restrict__ fc, const int* __restrict__ act,
+                                               const T* __restrict__ wdc, T* __restrict__ tc, int bx, int rhs) {
+  const int m = bx * kBlock + threadIdx.x;
+  if (m >= C.nn || (act && !act[rhs])) return;
+  restrict_node<T>(F, C, r + 3ll * F.nn * rhs, fc + 3ll * C.nn * rhs, wdc, wdc ? tc + 3ll * C.nn * rhs : tc, m);
+}
 template <typename T>
 __global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restrict__ fc,
                            const int* __restrict__ act, const T* __restrict__ wdc, T* __restrict__ tc) {
-  const int m = blockIdx.x * kBlock + threadIdx.x;
-  if (m >= C.nn || (act && !act[blockIdx.y])) return;
-  restrict_node<T>(F, C, r + 3ll * F.nn * blockIdx.y, fc + 3ll * C.nn * blockIdx.y, wdc,
-                   wdc ? tc + 3ll * C.nn * blockIdx.y : tc, m);
+  restrict_block<T>(F, C, r, fc, act, wdc, tc, blockIdx.x, blockIdx.y);
+}
+template <typename T>
+__global__ void k_restrict_batch(Batch<RestrictTask<T>> tb) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const RestrictTask<T>& a = tb.a[t];
+  const int local = (int)blockIdx.x - tb.begin[t];
+  restrict_block<T>(a.F, a.C, a.r, a.fc, a.act, a.wdc, a.tc, local % a.gx, local / a.gx);
 }
 
 // Fine correction u += M P e_c (see prolong_node).
 template <typename T>
+__device__ __forceinline__ void prolong_block(const Level& F, const Level& C, const T* __restrict__ ec,
+                                              T* __restrict__ u, const int* __restrict__ act, int bx, int rhs) {
+  const int n = bx * kBlock + threadIdx.x;
+  if (n >= F.nn || (act && !act[rhs])) return;
+  prolong_node<T>(F, C, ec + 3ll * C.nn * rhs, u + 3ll * F.nn * rhs, n);
+}
+template <typename T>
 __global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u,
                               const int* __restrict__ act) {
-  const int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= F.nn || (act && !act[blockIdx.y])) return;
-  prolong_node<T>(F, C, ec + 3ll * C.nn * blockIdx.y, u + 3ll * F.nn * blockIdx.y, n);
+  prolong_block<T>(F, C, ec, u, act, blockIdx.x, blockIdx.y);
+}
+template <typename T>
+__global__ void k_prolong_add_batch(Batch<ProlongTask<T>> tb) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const ProlongTask<T>& a = tb.a[t];
+  const int local = (int)blockIdx.x - tb.begin[t];
+  prolong_block<T>(a.F, a.C, a.ec, a.u, a.act, local % a.gx, local / a.gx);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,6 +262,20 @@ __global__ void k_mask_default(Level L, uint8_t* __restrict__ mask) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= L.nn) return;
   mask[n] = (n % L.nxn == 0) ? 7 : 0;
+}
+
+// one thread per (segment, node row): any fixed DOF among the 64 columns a
+// streaming tile of that segment reads
+__global__ void k_row_any(Level L, uint8_t* __restrict__ rowany) {
+  const int segs = row_segments(L);
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)segs * L.nyn * L.nzn) return;
+  const int sg = (int)(t % segs);
+  const long long row = t / segs;  // j + nyn * k
+  const uint8_t* m = L.mask + row * L.nxn;
+  int any = 0;
+  for (int i = max(62 * sg - 1, 0); i < min(62 * sg + 63, L.nxn); ++i) any |= m[i];
+  rowany[t] = any != 0;
 }
 
 __global__ void k_mask_inject(Level F, Level C, const uint8_t* __restrict__ mf, uint8_t* __restrict__ mc) {
@@ -601,11 +640,23 @@ __global__ void k_symmetrize(int n, const double* __restrict__ A, double* __rest
 }
 
 template <typename T>
+__device__ __forceinline__ void gemv_block(int n, const double* __restrict__ Ainv, const T* __restrict__ x,
+                                           T* __restrict__ y, const int* __restrict__ act, int bx, int rhs) {
+  const int row = bx * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= n || (act && !act[rhs])) return;  // uniform per wave
+  gemv_row<T>(n, Ainv, x + (long long)n * rhs, y + (long long)n * rhs, row, threadIdx.x & 63);
+}
+template <typename T>
 __global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const T* __restrict__ x,
                               T* __restrict__ y, const int* __restrict__ act) {
-  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (row >= n || (act && !act[blockIdx.y])) return;  // uniform per wave
-  gemv_row<T>(n, Ainv, x + (long long)n * blockIdx.y, y + (long long)n * blockIdx.y, row, threadIdx.x & 63);
+  gemv_block<T>(n, Ainv, x, y, act, blockIdx.x, blockIdx.y);
+}
+template <typename T>
+__global__ void k_coarse_gemv_batch(Batch<GemvTask<T>> tb) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const GemvTask<T>& a = tb.a[t];
+  const int local = (int)blockIdx.x - tb.begin[t];
+  gemv_block<T>(a.n, a.Ainv, a.x, a.y, a.act, local % a.gx, local / a.gx);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,6 +685,19 @@ __global__ void k_reduce_final(const double* __restrict__ partials, double* __re
   for (int i = threadIdx.x; i < kReduceBlocks; i += kBlock) s += partials[i];
   s = block_sum(s);
   if (threadIdx.x == 0) out[(long long)stride * blockIdx.x] = s;
+}
+
+// block r: out[r] = sum of parts[r][0 .. n) in a fixed order (the partials of
+// a streaming-kernel launch with more workgroups than a vector kernel's block
+// should sum on its own); skipped for an inactive right-hand side.
+__global__ void k_sum_parts(const double* __restrict__ parts, int n, double* __restrict__ out,
+                            const int* __restrict__ act) {
+  if (act && !act[blockIdx.x]) return;
+  parts += (long long)n * blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += parts[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // grid (kReduceBlocks, nrhs): r = M f (fixed DOFs zeroed), x = 0 and the
@@ -727,15 +791,17 @@ __global__ void k_pcg_final_sums(const double* __restrict__ pa, const double* __
 // set get only alpha and the pending flag (their residual is replaced right
 // after, see k_replace_r).
 template <typename TW, typename TQ>
-__global__ void k_update_r_first(long long n, const double* __restrict__ pq_partials, int npq,
-                                 double* __restrict__ sc, const int* __restrict__ active,
-                                 const TQ* __restrict__ q, double* __restrict__ r,
-                                 double* __restrict__ rr_partials, int parity, const TW* __restrict__ wdinv,
-                                 float* __restrict__ f32, TW* __restrict__ t, const int* __restrict__ repl) {
-  const int rhs = blockIdx.y;
+__device__ __forceinline__ void update_r_first_block(long long n, const double* __restrict__ pq_partials, int npq,
+                                                     double* __restrict__ sc, const int* __restrict__ active,
+                                                     const TQ* __restrict__ q, double* __restrict__ r,
+                                                     double* __restrict__ rr_partials, int parity,
+                                                     const TW* __restrict__ wdinv, float* __restrict__ f32,
+                                                     TW* __restrict__ t, const int* __restrict__ repl, int bx,
+                                                     int rhs) {
+  constexpr int gx = kReduceBlocks;
   rr_partials += (long long)kReduceBlocks * rhs;
   if (!active[rhs]) {
-    if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
+    if (threadIdx.x == 0) rr_partials[bx] = 0.0;
     return;
   }
   double pqs = 0.0;
@@ -744,13 +810,13 @@ __global__ void k_update_r_first(long long n, const double* __restrict__ pq_part
   double* s = sc + kScalars * rhs;
   const double alpha = s[kRz0 + parity] / pq;
   const bool ok = pq > 0.0 && pq < 1e308;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     s[kPq] = pq;
     s[kAlpha] = alpha;
     s[kXPend] = ok ? 1.0 : 0.0;
   }
   if (!ok || (repl && repl[rhs])) {  // breakdown: keep the previous iterate; the check flags it
-    if (threadIdx.x == 0) rr_partials[blockIdx.x] = 0.0;
+    if (threadIdx.x == 0) rr_partials[bx] = 0.0;
     return;
   }
   const long long off = n * rhs;
@@ -760,7 +826,7 @@ __global__ void k_update_r_first(long long n, const double* __restrict__ pq_part
   if (t) t += off;
   double acc = 0.0;
 #pragma unroll 4
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+  for (long long i = (long long)bx * kBlock + threadIdx.x; i < n; i += (long long)gx * kBlock) {
     const double ri = r[i] - alpha * (double)q[i];
     r[i] = ri;
     acc += ri * ri;
@@ -773,16 +839,33 @@ __global__ void k_update_r_first(long long n, const double* __restrict__ pq_part
     }
   }
   acc = block_sum(acc);
-  if (threadIdx.x == 0) rr_partials[blockIdx.x] = acc;
+  if (threadIdx.x == 0) rr_partials[bx] = acc;
 }
+template <typename TW, typename TQ>
+__global__ void k_update_r_first(long long n, const double* __restrict__ pq_partials, int npq,
+                                 double* __restrict__ sc, const int* __restrict__ active,
+                                 const TQ* __restrict__ q, double* __restrict__ r,
+                                 double* __restrict__ rr_partials, int parity, const TW* __restrict__ wdinv,
+                                 float* __restrict__ f32, TW* __restrict__ t, const int* __restrict__ repl) {
+  update_r_first_block<TW, TQ>(n, pq_partials, npq, sc, active, q, r, rr_partials, parity, wdinv, f32, t, repl,
+                               blockIdx.x, blockIdx.y);
+}
+template <typename TW, typename TQ>
+__global__ void k_update_r_first_batch(Batch<UpdateRTask<TW, TQ>> tb) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const UpdateRTask<TW, TQ>& a = tb.a[t];
+  const int local = (int)blockIdx.x - tb.begin[t];
+  update_r_first_block<TW, TQ>(a.n, a.pq_partials, a.npq, a.sc, a.active, a.q, a.r, a.rr_partials, a.parity,
+                               a.wdinv, a.f32, a.t, a.repl, local % kReduceBlocks, local / kReduceBlocks);
+}
+
 
 // One block per right-hand side: ||r||^2, iteration count, convergence and
 // breakdown test; then the scalars are written to host_slot (pinned host
 // memory, kScalars per right-hand side), where the host reads them without a
 // copy.  A right-hand side that has stopped only republishes its scalars.
-__global__ void k_rr_check(const double* __restrict__ rr_partials, double* __restrict__ sc,
-                           int* __restrict__ active, double* __restrict__ host_slot) {
-  const int rhs = blockIdx.x;
+__device__ __forceinline__ void rr_check_block(const double* __restrict__ rr_partials, double* __restrict__ sc,
+                                               int* __restrict__ active, double* __restrict__ host_slot, int rhs) {
   const double rr = sum_partials(rr_partials + (long long)kReduceBlocks * rhs);
   if (threadIdx.x != 0) return;
   double* s = sc + kScalars * rhs;
@@ -810,6 +893,15 @@ __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __res
   for (int j = 0; j < kScalars; ++j) host_slot[kScalars * rhs + j] = v[j];
   __threadfence_system();
 }
+__global__ void k_rr_check(const double* __restrict__ rr_partials, double* __restrict__ sc,
+                           int* __restrict__ active, double* __restrict__ host_slot) {
+  rr_check_block(rr_partials, sc, active, host_slot, blockIdx.x);
+}
+__global__ void k_rr_check_batch(Batch<RrCheckTask> tb) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const RrCheckTask& a = tb.a[t];
+  rr_check_block(a.rr_partials, a.sc, a.active, a.host_slot, (int)blockIdx.x - tb.begin[t]);
+}
 
 // grid (kReduceBlocks, nrhs): beta from the nrz rz partials (every block sums
 // them in the same order); the previous
@@ -819,10 +911,12 @@ __global__ void k_rr_check(const double* __restrict__ rr_partials, double* __res
 // The x update is skipped when s[kXPend] is 0 (a residual replacement has
 // already applied it); p32 (may be null) receives a binary32 copy of the new p.
 template <typename TZ>
-__global__ void k_update_px(long long n, const double* __restrict__ rz_partials, int nrz, double* __restrict__ sc,
-                            const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
-                            double* __restrict__ x, int parity, float* __restrict__ p32) {
-  const int rhs = blockIdx.y;
+__device__ __forceinline__ void update_px_block(long long n, const double* __restrict__ rz_partials, int nrz,
+                                                double* __restrict__ sc, const int* __restrict__ active,
+                                                const TZ* __restrict__ z, double* __restrict__ p,
+                                                double* __restrict__ x, int parity, float* __restrict__ p32, int bx,
+                                                int rhs) {
+  constexpr int gx = kReduceBlocks;
   if (!active[rhs]) return;
   double rzs = 0.0;
   for (int i = threadIdx.x; i < nrz; i += kBlock) rzs += rz_partials[(long long)nrz * rhs + i];
@@ -830,7 +924,7 @@ __global__ void k_update_px(long long n, const double* __restrict__ rz_partials,
   double* s = sc + kScalars * rhs;
   const double beta = rz / s[kRz0 + parity];
   const double alpha = s[kXPend] != 0.0 ? s[kAlpha] : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     s[kRz0 + 1 - parity] = rz;
     s[kBeta] = beta;
   }
@@ -841,7 +935,7 @@ __global__ void k_update_px(long long n, const double* __restrict__ rz_partials,
   if (p32) {
     p32 += off;
 #pragma unroll 4
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    for (long long i = (long long)bx * kBlock + threadIdx.x; i < n; i += (long long)gx * kBlock) {
       const double pi = p[i];
       x[i] += alpha * pi;
       const double pn = (double)z[i] + beta * pi;
@@ -851,11 +945,25 @@ __global__ void k_update_px(long long n, const double* __restrict__ rz_partials,
     return;
   }
 #pragma unroll 4
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+  for (long long i = (long long)bx * kBlock + threadIdx.x; i < n; i += (long long)gx * kBlock) {
     const double pi = p[i];
     x[i] += alpha * pi;
     p[i] = (double)z[i] + beta * pi;
   }
+}
+template <typename TZ>
+__global__ void k_update_px(long long n, const double* __restrict__ rz_partials, int nrz, double* __restrict__ sc,
+                            const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
+                            double* __restrict__ x, int parity, float* __restrict__ p32) {
+  update_px_block<TZ>(n, rz_partials, nrz, sc, active, z, p, x, parity, p32, blockIdx.x, blockIdx.y);
+}
+template <typename TZ>
+__global__ void k_update_px_batch(Batch<UpdatePxTask<TZ>> tb) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const UpdatePxTask<TZ>& a = tb.a[t];
+  const int local = (int)blockIdx.x - tb.begin[t];
+  update_px_block<TZ>(a.n, a.rz_partials, a.nrz, a.sc, a.active, a.z, a.p, a.x, a.parity, a.p32,
+                      local % kReduceBlocks, local / kReduceBlocks);
 }
 
 // grid (kReduceBlocks, nrhs), residual replacement after q = A x in binary64
@@ -1097,6 +1205,10 @@ void launch_diag(const Level& L, const double* Ke, const double* E, double omega
 void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s) {
   k_mask_default<<<blocks_for(L.nn), kBlock, 0, s>>>(L, mask);
 }
+void launch_row_any(const Level& L, uint8_t* rowany, hipStream_t s) {
+  const long long n = (long long)row_segments(L) * L.nyn * L.nzn;
+  k_row_any<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(L, rowany);
+}
 void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8_t* mc, hipStream_t s) {
   k_mask_inject<<<blocks_for(C.nn), kBlock, 0, s>>>(F, C, mf, mc);
 }
@@ -1133,6 +1245,9 @@ template void launch_coarse_gemv<float>(int, const double*, const float*, float*
 void launch_dot_partial(long long n, const double* x, const double* y, double* partials, int nrhs, const int* act,
                         hipStream_t s) {
   k_dot_partial<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, x, y, partials, act);
+}
+void launch_sum_parts(const double* parts, int n, double* out, int nrhs, const int* act, hipStream_t s) {
+  k_sum_parts<<<nrhs, kBlock, 0, s>>>(parts, n, out, act);
 }
 void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s) {
   k_reduce_final<<<nrhs, kBlock, 0, s>>>(partials, out, stride);
@@ -1210,5 +1325,51 @@ void launch_sensitivity(const Level& L, const double* Ke, const double* rho, con
                         double coef, double pm1, int accumulate, double* dc, hipStream_t s) {
   k_sensitivity<<<blocks_for(L.ne), kBlock, 0, s>>>(L, Ke, rho, u, coef, pm1, accumulate, dc);
 }
+
+// ---------------------------------------------------------------------------
+// Batched launches (several grids; see Batch in hexmg_impl.h).
+int restrict_blocks(const Level& C) { return blocks_for(C.nn); }
+int prolong_blocks(const Level& F) { return blocks_for(F.nn); }
+int gemv_blocks(int n) { return (n + kBlock / 64 - 1) / (kBlock / 64); }
+
+template <typename T>
+void launch_restrict_batch(const Batch<RestrictTask<T>>& b, hipStream_t s) {
+  k_restrict_batch<T><<<b.begin[b.n], kBlock, 0, s>>>(b);
+}
+template void launch_restrict_batch<float>(const Batch<RestrictTask<float>>&, hipStream_t);
+template void launch_restrict_batch<double>(const Batch<RestrictTask<double>>&, hipStream_t);
+
+template <typename T>
+void launch_prolong_add_batch(const Batch<ProlongTask<T>>& b, hipStream_t s) {
+  k_prolong_add_batch<T><<<b.begin[b.n], kBlock, 0, s>>>(b);
+}
+template void launch_prolong_add_batch<float>(const Batch<ProlongTask<float>>&, hipStream_t);
+template void launch_prolong_add_batch<double>(const Batch<ProlongTask<double>>&, hipStream_t);
+
+template <typename T>
+void launch_coarse_gemv_batch(const Batch<GemvTask<T>>& b, hipStream_t s) {
+  k_coarse_gemv_batch<T><<<b.begin[b.n], kBlock, 0, s>>>(b);
+}
+template void launch_coarse_gemv_batch<float>(const Batch<GemvTask<float>>&, hipStream_t);
+template void launch_coarse_gemv_batch<double>(const Batch<GemvTask<double>>&, hipStream_t);
+
+template <typename TW, typename TQ>
+void launch_update_r_first_batch(const Batch<UpdateRTask<TW, TQ>>& b, hipStream_t s) {
+  k_update_r_first_batch<TW, TQ><<<b.begin[b.n], kBlock, 0, s>>>(b);
+}
+template void launch_update_r_first_batch<double, double>(const Batch<UpdateRTask<double, double>>&, hipStream_t);
+template void launch_update_r_first_batch<float, double>(const Batch<UpdateRTask<float, double>>&, hipStream_t);
+template void launch_update_r_first_batch<float, float>(const Batch<UpdateRTask<float, float>>&, hipStream_t);
+
+void launch_rr_check_batch(const Batch<RrCheckTask>& b, hipStream_t s) {
+  k_rr_check_batch<<<b.begin[b.n], kBlock, 0, s>>>(b);
+}
+
+template <typename TZ>
+void launch_update_px_batch(const Batch<UpdatePxTask<TZ>>& b, hipStream_t s) {
+  k_update_px_batch<TZ><<<b.begin[b.n], kBlock, 0, s>>>(b);
+}
+template void launch_update_px_batch<double>(const Batch<UpdatePxTask<double>>&, hipStream_t);
+template void launch_update_px_batch<float>(const Batch<UpdatePxTask<float>>&, hipStream_t);
 
 }  // namespace hexmg

@@ -163,15 +163,18 @@ __device__ inline double select_bit(int m, int c, double a, double b) { return (
 // DOT (K u and the sweep, without MASKIN): also one partial per workgroup
 // into dotp, of u . (A u) for K u and of f . y (the right-hand side times the
 // new iterate) for the sweep.
-template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT>
-__global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
-                                                      const T* __restrict__ ug, const T* __restrict__ fg,
-                                                      const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
-                                                      int nchunks, const int* __restrict__ act,
-                                                      double* __restrict__ dotp) {
-  if (act && !act[blockIdx.z / nchunks]) return;  // right-hand side already converged (uniform per block)
-  {  // blockIdx.z = z-chunk + nchunks * right-hand side; vectors are [nrhs][3 nn]
-    const long long off = 3ll * L.nn * (blockIdx.z / nchunks);
+// One workgroup's tile: (bx, by, bz) is its place in the grid's launch of
+// gx * gy * (nchunks * nrhs) workgroups (the launch grid itself, or its slot
+// in a batched launch over several grids).
+template <typename T, int MODE, int R, int W, bool MASKIN, int PRE, bool DOT>
+__device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q, const T* __restrict__ Eg,
+                                            const T* __restrict__ ug, const T* __restrict__ fg,
+                                            const T* __restrict__ wg, T* __restrict__ yg, int zchunk, int nchunks,
+                                            const int* __restrict__ act, double* __restrict__ dotp, int bx, int by,
+                                            int bz, int gx, int gy) {
+  if (act && !act[bz / nchunks]) return;  // right-hand side already converged (uniform per block)
+  {  // bz = z-chunk + nchunks * right-hand side; vectors are [nrhs][3 nn]
+    const long long off = 3ll * L.nn * (bz / nchunks);
     ug += off;
     yg += off;
     if (MODE != kApply) fg += off;
@@ -179,10 +182,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   constexpr int kOutRows = W * R - 1;
-  const int i = blockIdx.x * 62 - 1 + lane;           // node column of this lane
-  const int jt0 = blockIdx.y * kOutRows - 1;          // first (halo) row of the tile
+  const int i = bx * 62 - 1 + lane;           // node column of this lane
+  const int jt0 = by * kOutRows - 1;          // first (halo) row of the tile
   const int j0 = jt0 + w * R;                         // first row of this wave
-  const int kc0 = (blockIdx.z % nchunks) * zchunk;
+  const int kc0 = (bz % nchunks) * zchunk;
   const int kc1 = min(kc0 + zchunk, L.nzn);           // output planes [kc0, kc1)
   const bool lane_out = lane >= 1 && lane <= 62 && i < L.nxn;
   const bool col_in = i >= 0 && i < L.nxn;
@@ -216,12 +219,23 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
   // Software pipeline: the raw u (and, with MASKIN, the support bits) of plane
   // kk+1 and the moduli of element layer kk are requested while plane kk is
   // being processed.
-  T un[R + 1][3], uc[R + 1][3], uo[R][3];
-  int mn[R + 1], mc[R + 1];
-  T En[R], Ec[R];
+  // Plane buffers alternate by parity (A holds the planes kc0-1, kc0+1, ...,
+  // B the others), so the pipeline never copies a plane between registers.
+  T uA[R + 1][3], uB[R + 1][3], uo[R][3];
+  int mA[R + 1], mB[R + 1];
+  T EA[R], EB[R];
   __shared__ T xch[2][W][3][64];  // [parity][wave][xyz][lane]: node values for the next wave
   // Only planes kc0-1..kc1 and element layers kc0-1..kc1-1 are needed; the
   // pipeline's requests outside them are given empty resources (no traffic).
+  // Whether node row jr of plane kk holds a fixed DOF among this tile's 64
+  // columns (uniform per wave: rows and planes are; a scalar load).  Rows
+  // without one skip their support-bit loads and the selects that use them.
+  const int segs = row_segments(L);
+  auto row_fixed = [&](int kk, int jr) -> bool {
+    const int ju = __builtin_amdgcn_readfirstlane(jr);
+    if (kk < 0 || kk >= L.nzn || ju < 0 || ju >= L.nyn) return false;
+    return __builtin_amdgcn_readfirstlane((int)L.rowany[bx + segs * (ju + L.nyn * kk)]) != 0;
+  };
   auto load_plane = [&](int kk, T (&u)[R + 1][3], int (&m)[R + 1]) {
     const bool pin = kk >= 0 && kk < L.nzn && kk <= kc1;
     const Rsrc ru = plane_rsrc(ug + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
@@ -230,7 +244,8 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     if (MASKIN) {
       const Rsrc rm = plane_rsrc(L.mask + plane * (pin ? kk : 0), pin ? mbytes : 0);
 #pragma unroll
-      for (int r = 0; r <= R; ++r) m[r] = __builtin_amdgcn_raw_buffer_load_b8(rm, offm[r], 0, 0);
+      for (int r = 0; r <= R; ++r)
+        m[r] = (pin && row_fixed(kk, j0 + r)) ? (int)__builtin_amdgcn_raw_buffer_load_b8(rm, offm[r], 0, 0) : 0;
     }
   };
   auto load_layer = [&](int ke, T (&E)[R]) {
@@ -240,8 +255,12 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     for (int r = 0; r < R; ++r) E[r] = load1(re, offe[r], T(0));
   };
 
-  T Fp[R][4][3];   // face modes of the previous plane (forward transform)
-  T Tp[R][4][3];   // top-face modes of the previous element layer (adjoint)
+  // Face modes of the previous plane (forward transform) and top-face modes of
+  // the previous element layer (adjoint), also alternating by parity: an
+  // iteration reads one set and writes the other, which the next iteration
+  // reads (an in-place update would cost a register move per mode).
+  T FpA[R][4][3], FpB[R][4][3];
+  T TpA[R][4][3], TpB[R][4][3];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -249,8 +268,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       uo[r][c] = T(0);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        Fp[r][m][c] = T(0);
-        Tp[r][m][c] = T(0);
+        FpA[r][m][c] = T(0);
+        FpB[r][m][c] = T(0);
+        TpA[r][m][c] = T(0);
+        TpB[r][m][c] = T(0);
       }
     }
   }
@@ -265,7 +286,9 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     {
       const Rsrc rm = plane_rsrc(L.mask + po, out_plane ? mbytes : 0);
 #pragma unroll
-      for (int r = 0; r < R; ++r) mo[r] = __builtin_amdgcn_raw_buffer_load_b8(rm, offmo[r], 0, 0);
+      for (int r = 0; r < R; ++r)
+        mo[r] = (out_plane && row_fixed(kk - 1, j0 + r)) ? (int)__builtin_amdgcn_raw_buffer_load_b8(rm, offmo[r], 0, 0)
+                                                          : 0;
     }
     if (MODE != kApply) {
       const Rsrc rf = plane_rsrc(fg + 3 * po, out_plane ? vbytes : 0);
@@ -281,8 +304,11 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 
   // Iteration kk: x and y stages of plane kk; for kk >= kc0 also element layer
   // kk-1 and the output of plane kk-1.
+  // Fin/Tin: the previous plane's face modes and the previous layer's top-face
+  // modes; Fout/Tout receive this plane's and this layer's.
   auto body = [&](int kk, const T (&uc)[R + 1][3], const int (&mc)[R + 1], const T (&Ec)[R], const int (&mo)[R],
-                  const T (&fo)[R][3], const T (&wo)[R][3]) {
+                  const T (&fo)[R][3], const T (&wo)[R][3], const T (&Fin)[R][4][3], T (&Fout)[R][4][3],
+                  const T (&Tin)[R][4][3], T (&Tout)[R][4][3]) {
     const bool out_plane = kk - 1 >= kc0 && kk - 1 < kc1;
     const Rsrc ry = plane_rsrc(yg + 3 * plane * (out_plane ? kk - 1 : 0), out_plane ? vbytes : 0);
     // u of plane kk (fixed DOFs masked when the input may be non-zero there)
@@ -316,9 +342,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
     // node update of plane kk-1 for row r
     auto finish = [&](int r, const T (&Ku)[3]) {
       T v[3];
+      const bool fixed_row = __any(mo[r] != 0);  // wave-uniform: skip the selects on free rows
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T Au = select_bit(mo[r], c, uo[r][c], Ku[c]);
+        const T Au = fixed_row ? select_bit(mo[r], c, uo[r][c], Ku[c]) : Ku[c];
         if (MODE == kApply) {
           v[c] = Au;
           if (DOT && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;
@@ -350,12 +377,12 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
           for (int xm = 0; xm < 2; ++xm) {
             const T fs = xhi[xm][c] + xlo[xm][c];  // y sum
             const T fd = xhi[xm][c] - xlo[xm][c];  // y difference
-            v[xm][c] = fs + Fp[r][xm][c];
-            v[xm + 4][c] = fs - Fp[r][xm][c];
-            v[xm + 2][c] = fd + Fp[r][xm + 2][c];
-            v[xm + 6][c] = fd - Fp[r][xm + 2][c];
-            Fp[r][xm][c] = fs;
-            Fp[r][xm + 2][c] = fd;
+            v[xm][c] = fs + Fin[r][xm][c];
+            v[xm + 4][c] = fs - Fin[r][xm][c];
+            v[xm + 2][c] = fd + Fin[r][xm + 2][c];
+            v[xm + 6][c] = fd - Fin[r][xm + 2][c];
+            Fout[r][xm][c] = fs;
+            Fout[r][xm + 2][c] = fd;
           }
         }
         T t[8][3];
@@ -369,10 +396,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
         for (int c = 0; c < 3; ++c) {
 #pragma unroll
           for (int xm = 0; xm < 2; ++xm) {
-            const T Fs = Tp[r][xm][c] + (t[xm][c] - t[xm + 4][c]);
-            const T Fd = Tp[r][xm + 2][c] + (t[xm + 2][c] - t[xm + 6][c]);
-            Tp[r][xm][c] = t[xm][c] + t[xm + 4][c];
-            Tp[r][xm + 2][c] = t[xm + 2][c] + t[xm + 6][c];
+            const T Fs = Tin[r][xm][c] + (t[xm][c] - t[xm + 4][c]);
+            const T Fd = Tin[r][xm + 2][c] + (t[xm + 2][c] - t[xm + 6][c]);
+            Tout[r][xm][c] = t[xm][c] + t[xm + 4][c];
+            Tout[r][xm + 2][c] = t[xm + 2][c] + t[xm + 6][c];
             e[xm][c] = (r > 0) ? carry[xm][c] + (Fs - Fd) : Fs - Fd;
             carry[xm][c] = Fs + Fd;
           }
@@ -408,7 +435,8 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       }
       finish(0, Ku);
     } else {
-      // first plane of the chunk: only its face modes are needed
+      // first plane of the chunk: only its face modes are needed (the layer
+      // below it contributes nothing: Tout stays zero)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         T (&xlo)[2][3] = (r & 1) ? xb : xa;
@@ -418,8 +446,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
         for (int c = 0; c < 3; ++c)
 #pragma unroll
           for (int xm = 0; xm < 2; ++xm) {
-            Fp[r][xm][c] = xhi[xm][c] + xlo[xm][c];
-            Fp[r][xm + 2][c] = xhi[xm][c] - xlo[xm][c];
+            Fout[r][xm][c] = xhi[xm][c] + xlo[xm][c];
+            Fout[r][xm + 2][c] = xhi[xm][c] - xlo[xm][c];
+            Tout[r][xm][c] = T(0);
+            Tout[r][xm + 2][c] = T(0);
           }
       }
     }
@@ -449,27 +479,36 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
 #pragma unroll
     for (int t = 0; t < Z + 2; ++t) {
       const int kk = kc0 - 1 + t, o = t >= 2 ? t - 2 : 0;
-      if (kk <= kc1) body(kk, up[t], mp[t], Ep[t], mo[o], fo[o], wo[o]);
+      if (kk <= kc1) {
+        if (t & 1)
+          body(kk, up[t], mp[t], Ep[t], mo[o], fo[o], wo[o], FpB, FpA, TpB, TpA);
+        else
+          body(kk, up[t], mp[t], Ep[t], mo[o], fo[o], wo[o], FpA, FpB, TpA, TpB);
+      }
     }
   } else {
-    load_plane(kc0 - 1, un, mn);
-    load_layer(kc0 - 2, En);
-    for (int kk = kc0 - 1; kk <= kc1; ++kk) {
-      // rotate the pipeline and request the next plane / layer
-#pragma unroll
-      for (int r = 0; r <= R; ++r) {
-        if (MASKIN) mc[r] = mn[r];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) uc[r][c] = un[r][c];
+    // two planes per trip: A is processed while B's plane is requested, then
+    // the other way round
+    load_plane(kc0 - 1, uA, mA);
+    load_layer(kc0 - 2, EA);
+    for (int kk = kc0 - 1; kk <= kc1; kk += 2) {
+      {
+        load_plane(kk + 1, uB, mB);
+        load_layer(kk, EB);
+        int mo[R];
+        T fo[R][3], wo[R][3];
+        load_out(kk, mo, fo, wo);
+        body(kk, uA, mA, EA, mo, fo, wo, FpA, FpB, TpA, TpB);
       }
-#pragma unroll
-      for (int r = 0; r < R; ++r) Ec[r] = En[r];
-      load_plane(kk + 1, un, mn);
-      load_layer(kk, En);
-      int mo[R];
-      T fo[R][3], wo[R][3];
-      load_out(kk, mo, fo, wo);
-      body(kk, uc, mc, Ec, mo, fo, wo);
+      if (kk + 1 > kc1) break;
+      {
+        load_plane(kk + 2, uA, mA);
+        load_layer(kk + 1, EA);
+        int mo[R];
+        T fo[R][3], wo[R][3];
+        load_out(kk + 1, mo, fo, wo);
+        body(kk + 1, uB, mB, EB, mo, fo, wo, FpB, FpA, TpB, TpA);
+      }
     }
   }
   if (DOT) {  // one partial per workgroup, in a fixed order
@@ -482,11 +521,34 @@ __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q,
       double t = 0.0;
 #pragma unroll
       for (int k = 0; k < W; ++k) t += wsum[k];
-      const int parts = gridDim.x * gridDim.y * nchunks;
-      const int rhs = blockIdx.z / nchunks;
-      dotp[(long long)parts * rhs + blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * (blockIdx.z % nchunks))] = t;
+      const int parts = gx * gy * nchunks;
+      const int rhs = bz / nchunks;
+      dotp[(long long)parts * rhs + bx + gx * (by + gy * (bz % nchunks))] = t;
     }
   }
+}
+
+template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT>
+__global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
+                                                      const T* __restrict__ ug, const T* __restrict__ fg,
+                                                      const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
+                                                      int nchunks, const int* __restrict__ act,
+                                                      double* __restrict__ dotp) {
+  stream_tile<T, MODE, R, W, MASKIN, PRE, DOT>(L, q, Eg, ug, fg, wg, yg, zchunk, nchunks, act, dotp, blockIdx.x,
+                                               blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
+}
+
+// Several grids in one launch: workgroup b belongs to the task t with
+// begin[t] <= b < begin[t + 1] and takes that task's tile b - begin[t] in the
+// order of its own launch grid (x fastest).
+template <typename T, int MODE, int R, int W, int MINW, int PRE, bool DOT>
+__global__ __launch_bounds__(64 * W, MINW) void k_stream_batch(Batch<StreamTask<T>> tb, HaarCoef<T> q) {
+  const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
+  const StreamTask<T>& a = tb.a[t];
+  const int local = (int)blockIdx.x - tb.begin[t];
+  const int bx = local % a.gx, by = (local / a.gx) % a.gy, bz = local / (a.gx * a.gy);
+  stream_tile<T, MODE, R, W, false, PRE, DOT>(a.L, q, a.E, a.u, a.f, a.wd, a.y, a.zchunk, a.nchunks, a.act, a.dotp,
+                                              bx, by, bz, a.gx, a.gy);
 }
 
 template <typename T, int R, int W, int MINW, bool MASKIN, int PRE>
@@ -583,6 +645,57 @@ template void launch_stream<float>(int, bool, int, const Level&, const HaarCoef<
 template void launch_stream<double>(int, bool, int, const Level&, const HaarCoef<double>&, const double*,
                                     const double*, const double*, const double*, double*, int, int, const int*,
                                     hipStream_t, const LaunchTimer&, double*);
+
+namespace {
+template <typename T, int R, int W, int MINW>
+void launch_stream_batch_impl(int mode, bool pre, bool dot, const Batch<StreamTask<T>>& b, const HaarCoef<T>& q,
+                              hipStream_t s) {
+  const dim3 grid(b.begin[b.n]), block(64 * W);
+  if (mode == kApply) {
+    if (pre && dot) k_stream_batch<T, kApply, R, W, MINW, 1, true><<<grid, block, 0, s>>>(b, q);
+    else if (pre) k_stream_batch<T, kApply, R, W, MINW, 1, false><<<grid, block, 0, s>>>(b, q);
+    else if (dot) k_stream_batch<T, kApply, R, W, MINW, 0, true><<<grid, block, 0, s>>>(b, q);
+    else k_stream_batch<T, kApply, R, W, MINW, 0, false><<<grid, block, 0, s>>>(b, q);
+  } else if (mode == kSmooth) {
+    if (pre && dot) k_stream_batch<T, kSmooth, R, W, MINW, 1, true><<<grid, block, 0, s>>>(b, q);
+    else if (pre) k_stream_batch<T, kSmooth, R, W, MINW, 1, false><<<grid, block, 0, s>>>(b, q);
+    else if (dot) k_stream_batch<T, kSmooth, R, W, MINW, 0, true><<<grid, block, 0, s>>>(b, q);
+    else k_stream_batch<T, kSmooth, R, W, MINW, 0, false><<<grid, block, 0, s>>>(b, q);
+  } else {
+    if (pre) k_stream_batch<T, kResidual, R, W, MINW, 1, false><<<grid, block, 0, s>>>(b, q);
+    else k_stream_batch<T, kResidual, R, W, MINW, 0, false><<<grid, block, 0, s>>>(b, q);
+  }
+}
+}  // namespace
+
+template <typename T>
+void launch_stream_batch(int mode, int shape, bool pre, bool dot, const Batch<StreamTask<T>>& b,
+                         const HaarCoef<T>& q, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (shape == 0) launch_stream_batch_impl<T, 2, 4, 2>(mode, pre, dot, b, q, s);
+    else if (shape == 1) launch_stream_batch_impl<T, 3, 4, 2>(mode, pre, dot, b, q, s);
+    else if (shape == 2) launch_stream_batch_impl<T, 4, 4, 1>(mode, pre, dot, b, q, s);
+    else if (shape == 3) launch_stream_batch_impl<T, 3, 8, 1>(mode, pre, dot, b, q, s);
+    else if (shape == 4) launch_stream_batch_impl<T, 2, 8, 1>(mode, pre, dot, b, q, s);
+    else if (shape == 5) launch_stream_batch_impl<T, 1, 8, 2>(mode, pre, dot, b, q, s);
+    else launch_stream_batch_impl<T, 1, 4, 2>(mode, pre, dot, b, q, s);
+  } else {
+    if (shape == 0) launch_stream_batch_impl<T, 1, 8, 2>(mode, pre, dot, b, q, s);
+    else if (shape == 1) launch_stream_batch_impl<T, 2, 4, 1>(mode, pre, dot, b, q, s);
+    else launch_stream_batch_impl<T, 1, 4, 2>(mode, pre, dot, b, q, s);
+  }
+}
+template void launch_stream_batch<float>(int, int, bool, bool, const Batch<StreamTask<float>>&,
+                                         const HaarCoef<float>&, hipStream_t);
+template void launch_stream_batch<double>(int, int, bool, bool, const Batch<StreamTask<double>>&,
+                                          const HaarCoef<double>&, hipStream_t);
+
+void stream_grid(const Level& L, bool f32, int shape, int zchunk, int* gx, int* gy, int* nchunks) {
+  const int rows = stream_out_rows(f32, shape);
+  *gx = (L.nxn + 61) / 62;
+  *gy = (L.nyn + rows - 1) / rows;
+  *nchunks = (L.nzn + zchunk - 1) / zchunk;
+}
 
 int stream_blocks(const Level& L, bool f32, int shape, int zchunk) {
   const int rows = stream_out_rows(f32, shape);

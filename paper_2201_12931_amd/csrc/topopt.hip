@@ -171,19 +171,95 @@ __global__ void k_oc_probe_final(const double* __restrict__ partials, double* __
   vol[p] = s;
 }
 
-__global__ void k_oc_apply(long long n, const double* __restrict__ x, const double* __restrict__ dc,
-                           const double* __restrict__ dv, double eta, double move, double lam_pow,
-                           double* __restrict__ xn) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= n) return;
-  const double xe = x[e];
-  if (dv[e] == 0.0) {  // outside the volume constraint: left to the caller (passive)
-    xn[e] = xe;
-    return;
+// Number of design elements (passive == 0) per block: count[b].
+__global__ __launch_bounds__(kBlock) void k_count_design(long long n, const uint8_t* __restrict__ passive,
+                                                         int* __restrict__ count) {
+  __shared__ int part[kBlock / 64];
+  int c = 0;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock)
+    c += passive[e] == 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) t += part[q];
+    count[blockIdx.x] = t;
   }
-  const double B = -dc[e] / dv[e];
-  const double se = xe * pow(B > 0.0 ? B : 0.0, eta);
-  xn[e] = fmin(fmin(1.0, xe + move), fmax(fmax(0.0, xe - move), se * lam_pow));
+}
+
+// dv_e = [passive_e == 0] / (number of design elements); every block sums the
+// kReduceBlocks counts itself.
+__global__ __launch_bounds__(kBlock) void k_volume_weights(long long n, const uint8_t* __restrict__ passive,
+                                                           const int* __restrict__ count, double* __restrict__ dv) {
+  __shared__ long long tot;
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int b = 0; b < kReduceBlocks; ++b) t += count[b];
+    tot = t;
+  }
+  __syncthreads();
+  const double w = tot > 0 ? 1.0 / (double)tot : 0.0;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock)
+    dv[e] = passive[e] == 0 ? w : 0.0;
+}
+
+// x_new at the final multiplier, one grid-stride pass (kReduceBlocks blocks);
+// each block also writes the largest |x_new - x| and the partial sum of
+// dv x_new over its elements to partials[2 b], partials[2 b + 1].
+__global__ __launch_bounds__(kBlock) void k_oc_apply(long long n, const double* __restrict__ x,
+                                                     const double* __restrict__ dc, const double* __restrict__ dv,
+                                                     double eta, double move, double lam_pow,
+                                                     double* __restrict__ xn, double* __restrict__ partials) {
+  __shared__ double part[kBlock / 64][2];
+  double ch = 0.0, vol = 0.0;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
+    const double xe = x[e], ve = dv[e];
+    double y = xe;  // outside the volume constraint: left to the caller (passive)
+    if (ve != 0.0) {
+      const double B = -dc[e] / ve;
+      const double se = xe * pow(B > 0.0 ? B : 0.0, eta);
+      y = fmin(fmin(1.0, xe + move), fmax(fmax(0.0, xe - move), se * lam_pow));
+    }
+    xn[e] = y;
+    ch = fmax(ch, fabs(y - xe));
+    vol += ve * y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ch = fmax(ch, __shfl_down(ch, off, 64));
+    vol += __shfl_down(vol, off, 64);
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    part[w][0] = ch;
+    part[w][1] = vol;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double c = 0.0, v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) {
+      c = fmax(c, part[q][0]);
+      v += part[q][1];
+    }
+    partials[2ll * blockIdx.x] = c;
+    partials[2ll * blockIdx.x + 1] = v;
+  }
+}
+
+// out[0] = largest change, out[1] = dv . x_new (fixed order over the blocks)
+__global__ void k_oc_apply_final(const double* __restrict__ partials, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double c = 0.0, v = 0.0;
+  for (int b = 0; b < kReduceBlocks; ++b) {
+    c = fmax(c, partials[2 * b]);
+    v += partials[2 * b + 1];
+  }
+  out[0] = c;
+  out[1] = v;
 }
 
 }  // namespace
@@ -251,9 +327,15 @@ void launch_oc_probe(long long n, const double* x, const double* dc, const doubl
   k_oc_probe_final<<<1, 64, 0, s>>>(partials, vol);
 }
 
+void launch_volume_weights(long long n, const uint8_t* passive, int* count, double* dv, hipStream_t s) {
+  k_count_design<<<kReduceBlocks, kBlock, 0, s>>>(n, passive, count);
+  k_volume_weights<<<kReduceBlocks, kBlock, 0, s>>>(n, passive, count, dv);
+}
+
 void launch_oc_apply(long long n, const double* x, const double* dc, const double* dv, double eta, double move,
-                     double lam_pow, double* xn, hipStream_t s) {
-  k_oc_apply<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, x, dc, dv, eta, move, lam_pow, xn);
+                     double lam_pow, double* xn, double* partials, double* out, hipStream_t s) {
+  k_oc_apply<<<kReduceBlocks, kBlock, 0, s>>>(n, x, dc, dv, eta, move, lam_pow, xn, partials);
+  k_oc_apply_final<<<1, 64, 0, s>>>(partials, out);
 }
 
 }  // namespace hexmg

@@ -24,6 +24,7 @@ ERR_INVALID, ERR_WORKSPACE, ERR_DEVICE, ERR_NONFINITE, ERR_BREAKDOWN = -1, -2, -
 FP64, MIXED, MIXED32 = 0, 1, 2
 F64, F32 = 0, 1
 AVG_DENSITY, AVG_MODULUS = 0, 1
+STENCIL_F32, STENCIL_BF16, STENCIL_F16 = 0, 1, 2
 KERNEL_STREAM, KERNEL_GATHER, KERNEL_AUTO = 0, 1, 2
 COARSE_REDISCRETIZE, COARSE_GALERKIN = 0, 1
 
@@ -43,7 +44,7 @@ class GridDesc(ctypes.Structure):
         ("precision", ctypes.c_int), ("smooth_sweeps", ctypes.c_int),
         ("omega", ctypes.c_double), ("coarse_avg", ctypes.c_int), ("max_nrhs", ctypes.c_int),
         ("kernel", ctypes.c_int), ("fixed_mask", ctypes.c_void_p), ("coarse_op", ctypes.c_int),
-        ("vcycle_both", ctypes.c_int), ("rr_every", ctypes.c_int),
+        ("vcycle_both", ctypes.c_int), ("rr_every", ctypes.c_int), ("stencil_storage", ctypes.c_int),
     ]
 
 
@@ -81,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "hexmg_compliance_sensitivity": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
             "hexmg_batch_solve": (i, [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(i), d, i, ctypes.POINTER(SolveInfo), vp]),
+            "hexmg_batch_stats": (i, [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
             "hexmg_element_matrix": (i, [d, vp]),
             "hexmg_filter": (i, [i, i, i, d, i, vp, vp, vp, vp]),
             "hexmg_filter_noalloc": (i, [i, i, i, d, i, vp, vp, vp]),
@@ -88,8 +90,10 @@ def lib() -> ctypes.CDLL:
             "hexmg_gravity_load": (i, [vp, d, vp, vp, vp]),
             "hexmg_gravity_sensitivity": (i, [vp, vp, d, d, vp, vp]),
             "hexmg_apply_passive": (i, [ctypes.c_longlong, vp, vp, vp]),
-            "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), vp]),
-            "hexmg_kernel_choice": (i, [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "hexmg_oc_update": (i, [vp, vp, vp, vp, d, d, d, vp, ctypes.POINTER(d), ctypes.POINTER(d),
+                                    ctypes.POINTER(d), vp]),
+            "hexmg_volume_weights": (i, [vp, vp, vp, vp]),
+            "hexmg_kernel_choice": (i, [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_set_kernel_choice": (i, [vp, i, i, i, i, i]),
             "hexmg_coarse_cycle_choice": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "hexmg_set_coarse_cycle": (i, [vp, i, i, i]),
@@ -350,27 +354,50 @@ class Grid:
             None if dc is None else _dev(dc, torch.float64, self.n_elem, "dc"), _stream(stream)))
         return c
 
-    def oc_update(self, x, dc, dv, volfrac, move=0.2, eta=0.5, x_new=None, stream=None):
-        """S14: returns (x_new, lambda)."""
+    def oc_update(self, x, dc, dv, volfrac, move=0.2, eta=0.5, x_new=None, stream=None, stats=False):
+        """S14: returns (x_new, lambda), with stats also the largest change and
+        the volume dv . x_new: (x_new, lambda, change, volume)."""
         import torch
 
         if x_new is None:
             x_new = torch.empty_like(x)
-        lam = ctypes.c_double()
+        lam, ch, vol = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         n = self.n_elem
         _check(lib().hexmg_oc_update(self.handle, _dev(x, torch.float64, n, "x"), _dev(dc, torch.float64, n, "dc"),
                                      _dev(dv, torch.float64, n, "dv"), float(volfrac), float(move), float(eta),
-                                     _dev(x_new, torch.float64, n, "x_new"), ctypes.byref(lam), _stream(stream)))
+                                     _dev(x_new, torch.float64, n, "x_new"), ctypes.byref(lam),
+                                     ctypes.byref(ch) if stats else None, ctypes.byref(vol) if stats else None,
+                                     _stream(stream)))
+        if stats:
+            return x_new, lam.value, ch.value, vol.value
         return x_new, lam.value
 
-    def kernel_choice(self, level, dtype=F32):
+    def volume_weights(self, passive, dv=None, stream=None):
+        """dv_e = [passive_e == 0] / (number of design elements)."""
+        import torch
+
+        if dv is None:
+            dv = torch.empty(self.n_elem, dtype=torch.float64, device=passive.device)
+        _check(lib().hexmg_volume_weights(self.handle, _dev(passive, torch.uint8, self.n_elem, "passive"),
+                                          _dev(dv, torch.float64, self.n_elem, "dv"), _stream(stream)))
+        return dv
+
+    def kernel_choice(self, level, dtype=F32, mode=1):
+        """(kind, z-chunk, shape) of the element-product kernel of a level and
+        precision in mode 0 (K u), 1 (sweep, default) or 2 (residual)."""
         k, z, sh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().hexmg_kernel_choice(self.handle, level, dtype, ctypes.byref(k), ctypes.byref(z),
+        _check(lib().hexmg_kernel_choice(self.handle, level, dtype, mode, ctypes.byref(k), ctypes.byref(z),
                                          ctypes.byref(sh)))
         return ("stream" if k.value == KERNEL_STREAM else "gather"), z.value, sh.value
 
     def set_kernel_choice(self, level, dtype, kernel, zchunk=4, shape=0):
         _check(lib().hexmg_set_kernel_choice(self.handle, level, dtype, kernel, zchunk, shape))
+
+    def batch_stats(self):
+        """(launches issued, launches recorded) of the last batch solve this grid was in."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().hexmg_batch_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def gravity_load(self, gz, f_ext=None, f=None, stream=None):
         """f = f_ext + self-weight of the last set density (-gz rho_e / 8 per node along z)."""

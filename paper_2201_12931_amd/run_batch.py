@@ -5,7 +5,8 @@ load cases solved in lockstep, plus 16 independent cantilevers of uneven sizes
     python -m paper_2201_12931_amd.run_batch [--rtol 1e-6] [--reps 3]
 
 Prints one JSON line with the batched time, the time of the same solves one
-after another, iteration counts and residuals.
+after another, iteration counts, residuals, and the kernel launches of the
+batch against the launches the grids would have issued one by one.
 """
 from __future__ import annotations
 
@@ -57,14 +58,36 @@ def build(precision):
     return problems, grids, fs, us
 
 
+def pin_kernels(grids):
+    """Give every grid, on each level it has, the kernel the first (largest) grid
+    tuned for that level, so that each batched step is one launch for all grids
+    (the streaming kernel with the first grid's tile shape and z-chunk; a level
+    where it chose the node-gather kernel takes the streaming kernel's first
+    shape)."""
+    for dt in (hexmg.F32, hexmg.F64):
+        for l in range(max(g.levels for g in grids)):
+            lead = next(g for g in grids if g.levels > l)
+            kind, zc, shape = lead.kernel_choice(l, dt)
+            if kind != "stream":
+                zc, shape = 4, 0
+            for g in grids:
+                if g.levels > l:
+                    g.set_kernel_choice(l, dt, hexmg.KERNEL_STREAM, zc, shape)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--no-pin", action="store_true",
+                    help="keep each grid's own tuned kernels (steps whose grids chose differently then take "
+                         "several launches)")
     args = ap.parse_args()
     prec = hexmg.FP64 if args.fp64 else hexmg.MIXED
     problems, grids, fs, us = build(prec)
+    if not args.no_pin:
+        pin_kernels(grids)
     hexmg.batch_solve(grids, fs, us, rtol=args.rtol)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -88,6 +111,9 @@ def main():
                       "rel_res_true_max": max(x["rel_res_true"] for x in info)}
                      for (g, L, _, f), info in zip(problems, infos)],
         "status": code,
+        "kernels": "pinned to the largest grid's per level" if not args.no_pin else "tuned per grid",
+        "batch_launches": grids[0].batch_stats()[0],
+        "batch_launches_if_one_by_one": grids[0].batch_stats()[1],
         "total_dofs_x_rhs": dofs,
         "batch_s": t_batch,
         "sequential_s": t_seq,

@@ -98,9 +98,10 @@ def main():
     ap.add_argument("--coarse-avg", choices=["density", "modulus"], default="density")
     ap.add_argument("--filter", choices=["density", "sensitivity"], default="density")
     ap.add_argument("--coarse-op", choices=["rediscretize", "galerkin"], default="rediscretize")
-    ap.add_argument("--omega", type=float, default=0.5,
-                    help="Jacobi damping of the V-cycle smoother (0.5: black-and-white designs push
-                         lambda_max(D^-1 A) to 4-6, where 0.6 no longer smooths)")
+    ap.add_argument("--omega", type=float, default=0.0,
+                    help="Jacobi damping of the V-cycle smoother; 0 = the library's automatic choice "
+                         "(0.6 re-discretized, 0.5 Galerkin: on black-and-white designs the Galerkin "
+                         "hierarchy has lambda_max(D^-1 A) of 4-6, where 0.6 no longer smooths)")
     ap.add_argument("--until", type=float, default=0.0,
                     help="stop once the largest design change is below this (Alg. 4 uses 0.01); 0 = run --iters")
     args = ap.parse_args()

@@ -63,8 +63,7 @@ class TopOpt:
             self.dv = torch.full_like(self.x, 1.0 / self.n)
         else:
             # V = mean of x over the design (non-passive) elements; passive ones keep their value
-            active = (passive == 0).to(torch.float64)
-            self.dv = active / active.sum()
+            self.dv = self.grid.volume_weights(passive)
             hexmg.apply_passive(passive, self.x)
         self.it = 0
 
@@ -90,15 +89,17 @@ class TopOpt:
         return c.detach(), g, rho.detach()
 
     def step(self) -> OCResult:
+        """One OC iteration; the result's volume is that of the new design (the
+        constrained one: filtered with the density filter, of the design
+        elements with passive regions)."""
         c, dc, rho = self.gradient(self.x)
-        x_new, lam = self.grid.oc_update(self.x, dc, self.dv, self.volfrac, self.move, self.eta)
+        x_new, lam, change, vol = self.grid.oc_update(self.x, dc, self.dv, self.volfrac, self.move, self.eta,
+                                                      stats=True)
         if self.passive is not None:
             hexmg.apply_passive(self.passive, x_new)
-        change = float((x_new - self.x).abs().max())
         self.x = x_new
         self.it += 1
         info = self.grid.last_info[0]
-        vol = float(rho.mean()) if self.filter == "density" else float((self.dv * rho).sum())
         return OCResult(self.it, float(c), vol, change, lam, info["iterations"], info["rel_res_true"])
 
     def run(self, max_iters, tol=0.01, callback=None):

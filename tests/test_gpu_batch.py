@@ -73,32 +73,50 @@ def test_multi_rhs_vcycle_and_apply():
         assert np.abs(Y[r].cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-def test_batch_uneven_grids_equal_single_solves():
+@pytest.mark.parametrize("precision,pinned", [("mixed", True), ("mixed", False), ("fp64", True),
+                                              ("mixed32", True)])
+def test_batch_uneven_grids_equal_single_solves(precision, pinned):
+    """Uneven grids (2 to 4 levels, 1 or 2 right-hand sides) solved in one batch
+    equal their single solves bit for bit, with the kernels pinned to one tile
+    shape (each V-cycle and CG step one launch for all grids) or as tuned per
+    grid (steps whose grids chose different kernels take several launches)."""
     from paper_2201_12931_amd import hexmg
 
     _gpu()
+    print(f"case batch {precision} pinned={pinned}", flush=True)
+    prec = {"mixed": hexmg.MIXED, "fp64": hexmg.FP64, "mixed32": hexmg.MIXED32}[precision]
     specs = [((32, 16, 16), 3, 1), ((48, 24, 24), 4, 2), ((16, 8, 8), 2, 1), ((64, 32, 32), 4, 1)]
     grids, fs, us, refs = [], [], [], []
     for n, (dims, levels, nr) in enumerate(specs):
         g = W.Grid(*dims)
         rho = gpu(W.random_field_density(g, seed=300 + n, length_scale=8.0, lo=0.01))
         f = W.point_loads(g, nr, seed=40 + n) if nr > 1 else W.cantilever_line_load(g)[None, :]
-        grid = hexmg.Grid(*dims, levels, precision=hexmg.MIXED, max_nrhs=nr)
+        grid = hexmg.Grid(*dims, levels, precision=prec, max_nrhs=nr)
         grid.set_density(rho)
-        for l in range(levels):
+        for l in range(levels if pinned else 0):
             for dt in (hexmg.F32, hexmg.F64):
                 grid.set_kernel_choice(l, dt, hexmg.KERNEL_STREAM, 4, 0)
         grids.append(grid)
         fs.append(gpu(f))
         us.append(torch.empty_like(fs[-1]))
-    code, infos = hexmg.batch_solve(grids, fs, us, rtol=1e-6)
-    assert code == 0
+    # the binary32 outer product stalls on these fields (residual replacement
+    # and restarts carry it on): there only equality with the single solves is
+    # asked for, within a bounded number of iterations
+    maxit = 120 if precision == "mixed32" else 500
+    code, infos = hexmg.batch_solve(grids, fs, us, rtol=1e-6, maxit=maxit)
+    assert code == 0 or precision == "mixed32"
+    launches, recorded = grids[0].batch_stats()
+    print(f"case batch: status {code}, {launches} launches for {recorded} recorded; iterations "
+          f"{[[x['iterations'] for x in i] for i in infos]}", flush=True)
+    assert 0 < launches < recorded
     for grid, f, u, info in zip(grids, fs, us, infos):
         u1 = torch.empty_like(u)
-        c1, i1 = grid.solve(f, u1, rtol=1e-6)
+        c1, i1 = grid.solve(f, u1, rtol=1e-6, maxit=maxit)
         assert [x["iterations"] for x in i1] == [x["iterations"] for x in info]
+        assert [x["status"] for x in i1] == [x["status"] for x in info]
         assert torch.equal(u1, u)
-        assert all(x["rel_res_true"] < 2e-6 for x in info)
+        if precision != "mixed32":
+            assert all(x["rel_res_true"] < 2e-6 for x in info)
 
 
 def test_batch_rejects_duplicates():

@@ -199,6 +199,36 @@ def test_fullsize_256x128x128_oc_step():
     assert float(dvn @ xn) == pytest.approx(0.12, rel=1e-9)
 
 
+def test_fullsize_256x128x128_fd_check():
+    """The adjoint gradient of the 256x128x128 optimisation workload (density
+    filter r = 1.5, volume 0.12, from uniform 0.12) against central finite
+    differences (step 1e-4) on 64 seeded elements, by difference solves in
+    binary64 (Eq. 7); then 16 more after three OC iterations (a non-uniform
+    design).  Relative error <= 1e-5 on every element."""
+    from paper_2201_12931_amd import hexmg
+    from paper_2201_12931_amd.run_topopt import fd_check
+    from paper_2201_12931_amd.topopt import TopOpt
+
+    _gpu()
+    print("case full-size finite differences 256x128x128", flush=True)
+    g = W.Grid(256, 128, 128)
+    f = gpu(W.cantilever_line_load(g))
+    opt = TopOpt(256, 128, 128, 6, f, volfrac=0.12, precision=hexmg.MIXED)
+    rng = np.random.Generator(np.random.PCG64(2))
+    for n, iters in ((64, 0), (16, 3)):
+        for _ in range(iters):
+            opt.step()
+        x = opt.x.cpu().numpy()
+        rho = hexmg.density_filter(256, 128, 128, 1.5, opt.x).cpu().numpy()
+        cand = np.flatnonzero((rho >= 0.05) & (x >= 1e-4) & (x <= 1.0 - 1e-4))
+        elems = rng.choice(cand, size=n, replace=False)
+        res = fd_check(opt, f, elems)
+        worst = max(r["rel_err"] for r in res)
+        print(f"  after {opt.it} OC iterations: {n} elements, max relative error {worst:.3e}, "
+              f"mixed-precision solver's gradient {max(r['solver_rel_err'] for r in res):.3e}", flush=True)
+        assert worst <= 1e-5
+
+
 def test_fullsize_128x64x64_errors_against_oracle(c1):
     """Error of u, compliance and sensitivity of the three solver precisions at
     rtol 1e-6 against the oracle's MGPCG solved to 1e-12 (binary64, assembled

@@ -34,7 +34,7 @@ def _case(dims, levels, seed=6, **kw):
     mask = W.fixed_mask_face_x0(g)
     grid = hexmg.Grid(*dims, levels, coarse_op=hexmg.COARSE_GALERKIN, **kw)
     grid.set_density(gpu(rho))
-    h = mg.Hierarchy(*dims, rho, mask, levels, coarse_operator="galerkin")
+    h = mg.Hierarchy(*dims, rho, mask, levels, coarse_operator="galerkin", omega=0.5)
     return g, rho, mask, grid, h
 
 
@@ -67,7 +67,7 @@ def test_galerkin_vcycle_parity(sweeps):
     mask = W.fixed_mask_face_x0(g)
     grid = hexmg.Grid(*dims, levels, coarse_op=hexmg.COARSE_GALERKIN, smooth_sweeps=sweeps, vcycle_both=1)
     grid.set_density(gpu(rho))
-    h = mg.Hierarchy(*dims, rho, mask, levels, sweeps=sweeps, coarse_operator="galerkin")
+    h = mg.Hierarchy(*dims, rho, mask, levels, sweeps=sweeps, coarse_operator="galerkin", omega=0.5)
     r = W.random_vector(g.n_dof, seed=24) * h.free[0]
     ref = h.vcycle(r)
     z = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
@@ -101,7 +101,7 @@ def test_galerkin_solve_matches_direct(precision):
     assert rel(u.cpu().numpy(), u_ref) < 1e-8
     # the oracle's Galerkin MGPCG takes the same number of iterations in binary64
     if precision == "fp64":
-        h = mg.Hierarchy(*dims, rho, mask, levels, coarse_operator="galerkin")
+        h = mg.Hierarchy(*dims, rho, mask, levels, coarse_operator="galerkin", omega=0.5)
         _, its, _, _ = mg.mgpcg(h, f * free, rtol=1e-10)
         assert abs(info[0]["iterations"] - its) <= 1
 
@@ -113,3 +113,47 @@ def test_galerkin_rejects_cooperative_cycle():
     assert grid.coarse_cycle_choice(hexmg.F32)[0] == 0
     with pytest.raises(hexmg.HexmgError):
         grid.set_coarse_cycle(hexmg.F32, 1)
+
+
+@pytest.mark.parametrize("store,bound", [("bf16", 2.0 ** -7), ("f16", 2.0 ** -9)])
+def test_galerkin_16bit_stencils(store, bound):
+    """Galerkin coarse stencils stored in 16 bits for the binary32 V-cycle:
+    the coarse products against the oracle's P~^T A P~ within the storage's
+    rounding (norm-wise, relative), and the mixed solve still meets its
+    tolerance in binary64 with the compliance of the direct solve."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case galerkin stencil storage {store}", flush=True)
+    dims, levels = (32, 16, 16), 3
+    st = {"bf16": hexmg.STENCIL_BF16, "f16": hexmg.STENCIL_F16}[store]
+    g, rho, mask, grid, h = _case(dims, levels, precision=hexmg.MIXED, stencil_storage=st)
+    for l in range(1, levels):
+        n = h.A[l].shape[0]
+        u = W.random_vector(n, seed=60 + l)
+        ref = h.A[l] @ u
+        y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+        grid.apply_K(gpu(u.astype(np.float32)), y32, level=l)
+        err = rel(y32.cpu().numpy(), ref)
+        print(f"  level {l}: relative error {err:.3e}", flush=True)
+        assert err < bound, l
+    f = W.cantilever_line_load(g)
+    free = fem.free_dof_mask(mask)
+    c_ref = fem.compliance(f, fem.solve_direct(fem.assemble_stiffness(*dims, fem.simp_modulus(rho)), f, free))
+    u = torch.empty(g.n_dof, dtype=torch.float64, device="cuda")
+    code, info = grid.solve(gpu(f), u, rtol=1e-8, maxit=300)
+    assert code == 0 and info[0]["rel_res_true"] <= 1.5e-8
+    assert info[0]["compliance"] == pytest.approx(c_ref, rel=1e-7)
+    ref32 = hexmg.Grid(*dims, levels, coarse_op=hexmg.COARSE_GALERKIN, precision=hexmg.MIXED)
+    ref32.set_density(gpu(rho))
+    _, info32 = ref32.solve(gpu(f), torch.empty_like(u), rtol=1e-8, maxit=300)
+    print(f"  iterations {info[0]['iterations']} (binary32 stencils {info32[0]['iterations']})", flush=True)
+    assert info[0]["iterations"] <= info32[0]["iterations"] + 3
+
+
+def test_galerkin_16bit_rejects_binary32_apply_without_vcycle():
+    from paper_2201_12931_amd import hexmg
+
+    g, rho, mask, grid, h = _case((16, 8, 8), 3, stencil_storage=hexmg.STENCIL_BF16)  # binary64 grid
+    u = torch.zeros(h.A[1].shape[0], dtype=torch.float32, device="cuda")
+    with pytest.raises(hexmg.HexmgError):
+        grid.apply_K(u, torch.empty_like(u), level=1)

@@ -257,8 +257,10 @@ def test_passive_self_weight_oc_loop_matches_oracle():
     i, k = e % nx, e // (nx * ny)
     passive[k == nz - 1] = 1                    # solid top layer
     passive[(i == nx // 2) & (k < nz - 1)] = 2  # void slot
-    opt = TopOpt(*dims, 3, gpu(f), volfrac=0.3, precision=hexmg.FP64, rtol=1e-10, filter="sensitivity",
-                 passive=gpu(passive), gravity=0.05)
+    # the third design's solve takes the oracle's MGPCG 835 iterations to 1e-10
+    # (voids against the passive slot), so maxit leaves room for it
+    opt = TopOpt(*dims, 3, gpu(f), volfrac=0.3, precision=hexmg.FP64, rtol=1e-10, maxit=2000,
+                 filter="sensitivity", passive=gpu(passive), gravity=0.05)
     H, Hs = T.filter_matrix(*dims, 1.5)
     free = fem.free_dof_mask(mask)
     act = passive == 0
@@ -280,3 +282,53 @@ def test_passive_self_weight_oc_loop_matches_oracle():
     xo = opt.x.cpu().numpy()
     assert np.all(xo[passive == 1] == 1.0) and np.all(xo[passive == 2] == 0.0)
     assert abs(xo[act].mean() - 0.3) < 1e-9
+
+
+def test_compliance_reports_unconverged_solve():
+    """A state solve stopped by maxit raises instead of returning the
+    compliance and gradient of an inexact state."""
+    from paper_2201_12931_amd import hexmg
+    from paper_2201_12931_amd.autograd import Compliance, SolveNotConverged
+
+    _gpu()
+    dims = (16, 8, 8)
+    g = W.Grid(*dims)
+    grid = hexmg.Grid(*dims, 3, precision=hexmg.MIXED)
+    f = gpu(W.cantilever_line_load(g))
+    rho = gpu(W.random_field_density(g, seed=3, length_scale=4.0, lo=0.01))
+    with pytest.raises(SolveNotConverged) as e:
+        Compliance.apply(rho, grid, f, 1e-12, 2)
+    assert e.value.code == hexmg.NOT_CONVERGED
+    assert e.value.info[0]["iterations"] == 2
+    # the same grid still solves when given enough iterations
+    c = Compliance.apply(rho, grid, f, 1e-8, 200)
+    assert np.isfinite(float(c))
+
+
+def test_sensitivity_filter_oc_runs_to_stop_rule_like_oracle():
+    """Alg. 4 to its stop rule (largest design change below 0.01) with the
+    sensitivity filter (Eq. 3) at 32x16x16, volume fraction 0.12: the GPU loop
+    (binary64 MGPCG to 1e-12) follows the oracle's stored history (written by
+    tests/golden/make_oc_history.py) and stops at the same iteration."""
+    import json
+    import os
+
+    from paper_2201_12931_amd import hexmg
+    from paper_2201_12931_amd.topopt import TopOpt
+
+    _gpu()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oc_sensitivity_32x16x16.json")))
+    hist = ref["history"]
+    dims = tuple(ref["dims"])
+    g = W.Grid(*dims)
+    f = gpu(W.cantilever_line_load(g))
+    opt = TopOpt(*dims, ref["levels"], f, volfrac=ref["volfrac"], rmin=ref["rmin"], move=ref["move"], eta=ref["eta"],
+                 gamma=ref["gamma"], precision=hexmg.FP64, rtol=1e-12, maxit=2000, filter="sensitivity")
+    res = opt.run(len(hist) + 20, tol=ref["tol"])
+    print(f"case oc stop rule: gpu {len(res)} iterations, oracle {len(hist)}; "
+          f"c {res[-1].compliance:.10g} vs {hist[-1]['compliance']:.10g}", flush=True)
+    assert len(res) == len(hist)
+    for r, h in zip(res, hist):
+        assert r.compliance == pytest.approx(h["compliance"], rel=1e-7), r.iteration
+        assert abs(r.change - h["change"]) <= 1e-6, r.iteration
+    assert abs(float(opt.x.mean()) - ref["volfrac"]) < 1e-9

@@ -151,6 +151,9 @@ WORKLOADS = {
     # 256x128x128, 20 optimality-criteria iterations from uniform 0.12.
     "topopt_256x128x128": dict(grid=Grid(256, 128, 128), levels=6, rtol=1e-6,
                                density=("uniform", 0.12)),
+    # 256x128x128, random field (length 8, seed 2) in [0.01, 1], 6 levels (size study).
+    "cantilever_256x128x128_rf": dict(grid=Grid(256, 128, 128), levels=6, rtol=1e-6,
+                                      density=("field", 2, 0.01)),
     # 192x96x96, random field (seed 3) in [0.01,1], 8 point-load cases.
     "batched_192x96x96_8rhs": dict(grid=Grid(192, 96, 96), levels=5, rtol=1e-6,
                                    density=("field", 3, 0.01)),
