@@ -285,6 +285,16 @@ def main():
 
     copy_probe(args.copy_probe, dev)
 
+    # the device copy rate on this GPU (a 1 GiB binary32 copy, read + write),
+    # against which the roofline fractions are also reported
+    src = torch.empty((1 << 30) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_ms, _, copy_min = time_events(lambda: dst.copy_(src), 5, stream)
+    copy_gbs = 2.0 * src.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+
     # dominant kernel: the family with the largest device time over the profiled steps
     dom = max(kernel_ms, key=lambda k: kernel_ms[k][1])
     n_dom, t_dom = kernel_ms[dom]
@@ -341,6 +351,8 @@ def main():
             "launches": n_dom,
             "bytes_per_launch": dom_bytes,
             "timing": "per-dispatch HIP events over %d untimed repeats of the step" % args.steps,
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "roofline_ku": {
             "kernel": "K u binary32, level 0, public entry (%s, z-chunk %d, shape %d)" % choices["L0"]["f32"]["apply"],
@@ -351,6 +363,8 @@ def main():
             "frac": apply_bytes(g, 4) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bytes_per_launch": apply_bytes(g, 4),
             "timing": "HIP events on the launching stream, mean of %d launches" % args.ku_reps,
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": apply_bytes(g, 4) / (ms32 * 1e-3) / 1e9 / copy_gbs,
         },
     }
     if not args.no_cpu_baseline:

@@ -240,7 +240,6 @@ void make_levels(const hexmg_grid_desc* d, std::vector<Level>& lv) {
     L.nn = L.nxn * L.nyn * L.nzn;
     L.ne = L.nx * L.ny * L.nz;
     L.mask = nullptr;
-    L.rowany = nullptr;
     lv.push_back(L);
   }
 }
@@ -256,7 +255,6 @@ size_t carve(hexmg_grid* g, char* base) {
   g->wd64.assign(L, nullptr);
   g->wd32.assign(L, nullptr);
   g->mask.assign(L, nullptr);
-  g->rowany.assign(L, nullptr);
   g->vf64.assign(L, nullptr);
   g->vu64.assign(L, nullptr);
   g->vt64.assign(L, nullptr);
@@ -277,7 +275,6 @@ size_t carve(hexmg_grid* g, char* base) {
     g->E64[l] = c.take<double>(lv.ne);
     g->E32[l] = c.take<float>(lv.ne);
     g->mask[l] = c.take<uint8_t>(lv.nn);
-    g->rowany[l] = c.take<uint8_t>((size_t)row_segments(lv) * lv.nyn * lv.nzn);
     if (v64) {
       g->wd64[l] = c.take<double>(N);
       g->vf64[l] = c.take<double>(N * R);
@@ -905,10 +902,7 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
   g->L = d->levels;
   make_levels(d, g->lv);
   carve(g, static_cast<char*>(workspace));
-  for (int l = 0; l < g->L; ++l) {
-    g->lv[l].mask = g->mask[l];
-    g->lv[l].rowany = g->rowany[l];
-  }
+  for (int l = 0; l < g->L; ++l) g->lv[l].mask = g->mask[l];
   g->tuned = d->kernel != HEXMG_KERNEL_AUTO;
   g->choice64.assign(g->L, {});
   g->choice32.assign(g->L, {});
@@ -970,7 +964,6 @@ int hexmg_grid_create(const hexmg_grid_desc* d, void* workspace, size_t bytes, v
     launch_mask_default(g->lv[0], g->mask[0], s);
   }
   for (int l = 1; l < g->L; ++l) launch_mask_inject(g->lv[l - 1], g->lv[l], g->mask[l - 1], g->mask[l], s);
-  for (int l = 0; l < g->L; ++l) launch_row_any(g->lv[l], g->rowany[l], s);
   g->desc.fixed_mask = nullptr;  // copied; do not keep the caller's pointer
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
     return cleanup(fail(HEXMG_ERR_DEVICE, "grid set-up kernels failed"));

@@ -25,12 +25,7 @@ struct Level {
   int nn;             // node count
   int ne;             // element count
   const uint8_t* mask;  // per-node support bits (device)
-  // per 62-column segment s (nodes 62 s - 1 .. 62 s + 62, the columns of a
-  // streaming tile with its halo) of node row (j, k): 1 if a node there has a
-  // fixed DOF; at rowany[s + segs * (j + nyn * k)], segs = ceil(nxn / 62)
-  const uint8_t* rowany;
 };
-__host__ __device__ inline int row_segments(const Level& L) { return (L.nxn + 61) / 62; }
 
 // Haar-basis block coefficients of the unit element (already divided by 64):
 // normal block diag-off d1 and off b1, rank-one shear g, bilinear 2x2 (a2, b2),
@@ -249,8 +244,6 @@ void launch_coarsest_moduli(const Level& F, const Level& C, int blk, const doubl
 void launch_diag(const Level& L, const double* Ke, const double* E, double omega, double* wdinv64,
                  float* wdinv32, hipStream_t s);
 void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s);
-// rowany of a level from its mask
-void launch_row_any(const Level& L, uint8_t* rowany, hipStream_t s);
 void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8_t* mc, hipStream_t s);
 void launch_or_flags(int n, const int* flags, int* out, hipStream_t s);
 
@@ -437,7 +430,6 @@ struct hexmg_grid {
   std::vector<double*> wd64;     // omega / diag(A_l)
   std::vector<float*> wd32;
   std::vector<uint8_t*> mask;
-  std::vector<uint8_t*> rowany;  // per level: fixed DOFs in a tile's row segment (see Level)
   // V-cycle vectors per level: f (rhs), u (solution), t (ping-pong), r (residual)
   std::vector<double*> vf64, vu64, vt64, vr64;
   std::vector<float*> vf32, vu32, vt32, vr32;

@@ -120,13 +120,56 @@ __global__ void k_restrict_batch(Batch<RestrictTask<T>> tb) {
   restrict_block<T>(a.F, a.C, a.r, a.fc, a.act, a.wdc, a.tc, local % a.gx, local / a.gx);
 }
 
-// Fine correction u += M P e_c (see prolong_node).
+// Fine correction u += M P e_c by rows: each wave takes 64 consecutive nodes of
+// one fine node row (j, k), so the row's parities -- which coarse rows
+// contribute, with which weights -- are uniform over the wave, and along x a
+// node takes the mean of its two coarse neighbours (the same node twice where
+// i is even).  A block covers 64 columns of 4 rows: bx = column block +
+// cols * row block, cols = ceil(nxn / 64).
 template <typename T>
 __device__ __forceinline__ void prolong_block(const Level& F, const Level& C, const T* __restrict__ ec,
                                               T* __restrict__ u, const int* __restrict__ act, int bx, int rhs) {
-  const int n = bx * kBlock + threadIdx.x;
-  if (n >= F.nn || (act && !act[rhs])) return;
-  prolong_node<T>(F, C, ec + 3ll * C.nn * rhs, u + 3ll * F.nn * rhs, n);
+  if (act && !act[rhs]) return;
+  const int cols = (F.nxn + 63) >> 6;
+  const int row = __builtin_amdgcn_readfirstlane((bx / cols) * 4 + (int)(threadIdx.x >> 6));  // j + nyn k
+  const int i = (bx % cols) * 64 + (int)(threadIdx.x & 63);
+  if (row >= F.nyn * F.nzn || i >= F.nxn) return;
+  const int j = row % F.nyn, k = row / F.nyn;
+  const T* e = ec + 3ll * C.nn * rhs;
+  u += 3ll * F.nn * rhs;
+  const int I0 = i >> 1, I1 = (i + 1) >> 1, J = j >> 1, K = k >> 1;
+  // x-interpolated coarse row (Jc, Kc) at this node
+  auto xrow = [&](int Jc, int Kc, T (&v)[3]) {
+    const T* a = e + 3ll * (I0 + C.nxn * (Jc + C.nyn * Kc));
+    const T* b = e + 3ll * (I1 + C.nxn * (Jc + C.nyn * Kc));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = T(0.5) * (a[c] + b[c]);
+  };
+  T s[3];
+  xrow(J, K, s);
+  if (j & 1) {  // uniform: halfway between coarse rows J and J + 1
+    T t[3];
+    xrow(J + 1, K, t);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (s[c] + t[c]);
+  }
+  if (k & 1) {  // uniform: halfway between coarse planes K and K + 1
+    T t[3];
+    xrow(J, K + 1, t);
+    if (j & 1) {
+      T t2[3];
+      xrow(J + 1, K + 1, t2);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[c] = T(0.5) * (t[c] + t2[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (s[c] + t[c]);
+  }
+  const long long n = i + (long long)F.nxn * row;
+  const int mk = F.mask[n];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (!((mk >> c) & 1)) u[3 * n + c] += s[c];
 }
 template <typename T>
 __global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u,
@@ -262,20 +305,6 @@ __global__ void k_mask_default(Level L, uint8_t* __restrict__ mask) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= L.nn) return;
   mask[n] = (n % L.nxn == 0) ? 7 : 0;
-}
-
-// one thread per (segment, node row): any fixed DOF among the 64 columns a
-// streaming tile of that segment reads
-__global__ void k_row_any(Level L, uint8_t* __restrict__ rowany) {
-  const int segs = row_segments(L);
-  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= (long long)segs * L.nyn * L.nzn) return;
-  const int sg = (int)(t % segs);
-  const long long row = t / segs;  // j + nyn * k
-  const uint8_t* m = L.mask + row * L.nxn;
-  int any = 0;
-  for (int i = max(62 * sg - 1, 0); i < min(62 * sg + 63, L.nxn); ++i) any |= m[i];
-  rowany[t] = any != 0;
 }
 
 __global__ void k_mask_inject(Level F, Level C, const uint8_t* __restrict__ mf, uint8_t* __restrict__ mc) {
@@ -689,15 +718,33 @@ __global__ void k_reduce_final(const double* __restrict__ partials, double* __re
 
 // block r: out[r] = sum of parts[r][0 .. n) in a fixed order (the partials of
 // a streaming-kernel launch with more workgroups than a vector kernel's block
-// should sum on its own); skipped for an inactive right-hand side.
-__global__ void k_sum_parts(const double* __restrict__ parts, int n, double* __restrict__ out,
-                            const int* __restrict__ act) {
+// should sum on its own); skipped for an inactive right-hand side.  One block
+// of 1024 threads with eight independent chains each keeps enough loads in
+// flight that the ~70 k partials of a large level take a few microseconds.
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void k_sum_parts(const double* __restrict__ parts, int n,
+                                                           double* __restrict__ out, const int* __restrict__ act) {
   if (act && !act[blockIdx.x]) return;
   parts += (long long)n * blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += parts[i];
-  s = block_sum(s);
-  if (threadIdx.x == 0) out[blockIdx.x] = s;
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = 0.0;
+  int i = threadIdx.x;
+  for (; i + 7 * kSumThreads < n; i += 8 * kSumThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += parts[i + u * kSumThreads];
+  }
+  for (; i < n; i += kSumThreads) a[0] += parts[i];
+  double v = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+  __shared__ double part[kSumThreads / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSumThreads / 64; ++w) t += part[w];
+    out[blockIdx.x] = t;
+  }
 }
 
 // grid (kReduceBlocks, nrhs): r = M f (fixed DOFs zeroed), x = 0 and the
@@ -1169,7 +1216,7 @@ template void launch_restrict<float>(const Level&, const Level&, const float*, f
 template <typename T>
 void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, const int* act,
                         hipStream_t s) {
-  k_prolong_add<T><<<dim3(blocks_for(F.nn), nrhs), kBlock, 0, s>>>(F, C, ec, u, act);
+  k_prolong_add<T><<<dim3(prolong_blocks(F), nrhs), kBlock, 0, s>>>(F, C, ec, u, act);
 }
 template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, int, const int*,
                                          hipStream_t);
@@ -1204,10 +1251,6 @@ void launch_diag(const Level& L, const double* Ke, const double* E, double omega
 }
 void launch_mask_default(const Level& L, uint8_t* mask, hipStream_t s) {
   k_mask_default<<<blocks_for(L.nn), kBlock, 0, s>>>(L, mask);
-}
-void launch_row_any(const Level& L, uint8_t* rowany, hipStream_t s) {
-  const long long n = (long long)row_segments(L) * L.nyn * L.nzn;
-  k_row_any<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(L, rowany);
 }
 void launch_mask_inject(const Level& F, const Level& C, const uint8_t* mf, uint8_t* mc, hipStream_t s) {
   k_mask_inject<<<blocks_for(C.nn), kBlock, 0, s>>>(F, C, mf, mc);
@@ -1247,7 +1290,7 @@ void launch_dot_partial(long long n, const double* x, const double* y, double* p
   k_dot_partial<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, x, y, partials, act);
 }
 void launch_sum_parts(const double* parts, int n, double* out, int nrhs, const int* act, hipStream_t s) {
-  k_sum_parts<<<nrhs, kBlock, 0, s>>>(parts, n, out, act);
+  k_sum_parts<<<nrhs, kSumThreads, 0, s>>>(parts, n, out, act);
 }
 void launch_reduce_final(const double* partials, double* out, int stride, int nrhs, hipStream_t s) {
   k_reduce_final<<<nrhs, kBlock, 0, s>>>(partials, out, stride);
@@ -1329,7 +1372,7 @@ void launch_sensitivity(const Level& L, const double* Ke, const double* rho, con
 // ---------------------------------------------------------------------------
 // Batched launches (several grids; see Batch in hexmg_impl.h).
 int restrict_blocks(const Level& C) { return blocks_for(C.nn); }
-int prolong_blocks(const Level& F) { return blocks_for(F.nn); }
+int prolong_blocks(const Level& F) { return ((F.nxn + 63) / 64) * ((F.nyn * F.nzn + 3) / 4); }
 int gemv_blocks(int n) { return (n + kBlock / 64 - 1) / (kBlock / 64); }
 
 template <typename T>

@@ -136,45 +136,47 @@ __device__ inline void restrict_node(const Level& F, const Level& C, const T* __
   }
 }
 
-// Fine correction at fine node n: u += M P e_c (trilinear interpolation).  The
-// eight surrounding coarse nodes are requested at once (weight 0, index
-// clamped, where an axis coordinate is even and only one coarse node counts).
+// Fine correction at fine node n: u += M P e_c (trilinear interpolation),
+// formed axis by axis: along x the mean of the two coarse neighbours (the same
+// node twice where i is even), then halfway between coarse rows where j is
+// odd and between coarse planes where k is odd (the row kernel k_prolong_add
+// takes the same steps, so both round alike).
 template <typename T>
 __device__ inline void prolong_node(const Level& F, const Level& C, const T* __restrict__ ec, T* __restrict__ u,
                                     int n) {
   int i, j, k;
   node_coords(F, n, i, j, k);
-  const int oz = k & 1, oy = j & 1, ox = i & 1;
-  T v[8][3], w[8];
+  const int I0 = i >> 1, I1 = (i + 1) >> 1, J = j >> 1, K = k >> 1;
+  auto xrow = [&](int Jc, int Kc, T (&v)[3]) {
+    const T* a = ec + 3ll * (I0 + C.nxn * (Jc + C.nyn * Kc));
+    const T* b = ec + 3ll * (I1 + C.nxn * (Jc + C.nyn * Kc));
 #pragma unroll
-  for (int cz = 0; cz < 2; ++cz)
+    for (int c = 0; c < 3; ++c) v[c] = T(0.5) * (a[c] + b[c]);
+  };
+  T s[3];
+  xrow(J, K, s);
+  if (j & 1) {
+    T t[3];
+    xrow(J + 1, K, t);
 #pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
+    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (s[c] + t[c]);
+  }
+  if (k & 1) {
+    T t[3];
+    xrow(J, K + 1, t);
+    if (j & 1) {
+      T t2[3];
+      xrow(J + 1, K + 1, t2);
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const int q = cx + 2 * cy + 4 * cz;
-        const T wx = ox ? T(0.5) : (cx ? T(0) : T(1));
-        const T wy = oy ? T(0.5) : (cy ? T(0) : T(1));
-        const T wz = oz ? T(0.5) : (cz ? T(0) : T(1));
-        const int I = min((i >> 1) + cx, C.nxn - 1), J = min((j >> 1) + cy, C.nyn - 1),
-                  K = min((k >> 1) + cz, C.nzn - 1);
-        const T* e = ec + 3ll * (I + C.nxn * (J + C.nyn * K));
-        w[q] = wx * wy * wz;
-        v[q][0] = e[0];
-        v[q][1] = e[1];
-        v[q][2] = e[2];
-      }
-  T s0 = 0, s1 = 0, s2 = 0;
+      for (int c = 0; c < 3; ++c) t[c] = T(0.5) * (t[c] + t2[c]);
+    }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    s0 += w[q] * v[q][0];
-    s1 += w[q] * v[q][1];
-    s2 += w[q] * v[q][2];
+    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (s[c] + t[c]);
   }
   const int mk = F.mask[n];
-  if (!(mk & 1)) u[3ll * n] += s0;
-  if (!(mk & 2)) u[3ll * n + 1] += s1;
-  if (!(mk & 4)) u[3ll * n + 2] += s2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (!((mk >> c) & 1)) u[3ll * n + c] += s[c];
 }
 
 __device__ inline double wave_sum64(double v) {

@@ -227,15 +227,6 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
   __shared__ T xch[2][W][3][64];  // [parity][wave][xyz][lane]: node values for the next wave
   // Only planes kc0-1..kc1 and element layers kc0-1..kc1-1 are needed; the
   // pipeline's requests outside them are given empty resources (no traffic).
-  // Whether node row jr of plane kk holds a fixed DOF among this tile's 64
-  // columns (uniform per wave: rows and planes are; a scalar load).  Rows
-  // without one skip their support-bit loads and the selects that use them.
-  const int segs = row_segments(L);
-  auto row_fixed = [&](int kk, int jr) -> bool {
-    const int ju = __builtin_amdgcn_readfirstlane(jr);
-    if (kk < 0 || kk >= L.nzn || ju < 0 || ju >= L.nyn) return false;
-    return __builtin_amdgcn_readfirstlane((int)L.rowany[bx + segs * (ju + L.nyn * kk)]) != 0;
-  };
   auto load_plane = [&](int kk, T (&u)[R + 1][3], int (&m)[R + 1]) {
     const bool pin = kk >= 0 && kk < L.nzn && kk <= kc1;
     const Rsrc ru = plane_rsrc(ug + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
@@ -244,8 +235,7 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
     if (MASKIN) {
       const Rsrc rm = plane_rsrc(L.mask + plane * (pin ? kk : 0), pin ? mbytes : 0);
 #pragma unroll
-      for (int r = 0; r <= R; ++r)
-        m[r] = (pin && row_fixed(kk, j0 + r)) ? (int)__builtin_amdgcn_raw_buffer_load_b8(rm, offm[r], 0, 0) : 0;
+      for (int r = 0; r <= R; ++r) m[r] = __builtin_amdgcn_raw_buffer_load_b8(rm, offm[r], 0, 0);
     }
   };
   auto load_layer = [&](int ke, T (&E)[R]) {
@@ -286,9 +276,7 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
     {
       const Rsrc rm = plane_rsrc(L.mask + po, out_plane ? mbytes : 0);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        mo[r] = (out_plane && row_fixed(kk - 1, j0 + r)) ? (int)__builtin_amdgcn_raw_buffer_load_b8(rm, offmo[r], 0, 0)
-                                                          : 0;
+      for (int r = 0; r < R; ++r) mo[r] = __builtin_amdgcn_raw_buffer_load_b8(rm, offmo[r], 0, 0);
     }
     if (MODE != kApply) {
       const Rsrc rf = plane_rsrc(fg + 3 * po, out_plane ? vbytes : 0);
@@ -342,10 +330,9 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
     // node update of plane kk-1 for row r
     auto finish = [&](int r, const T (&Ku)[3]) {
       T v[3];
-      const bool fixed_row = __any(mo[r] != 0);  // wave-uniform: skip the selects on free rows
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T Au = fixed_row ? select_bit(mo[r], c, uo[r][c], Ku[c]) : Ku[c];
+        const T Au = select_bit(mo[r], c, uo[r][c], Ku[c]);
         if (MODE == kApply) {
           v[c] = Au;
           if (DOT && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;

@@ -117,3 +117,34 @@ def test_sensitivity_filter_special_cases():
     a = T.sensitivity_filter(H, Hs, x, dc + 2.0 * d2)
     b = T.sensitivity_filter(H, Hs, x, dc) + 2.0 * T.sensitivity_filter(H, Hs, x, d2)
     assert np.allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+def test_stored_oc_history_matches_oracle():
+    """The stored optimisation history (tests/golden/oc_sensitivity_32x16x16.json,
+    written by tests/golden/make_oc_history.py) is the oracle's: its first three
+    iterations recomputed, and its stop rule holds exactly at its last entry."""
+    import json
+    import os
+
+    import workloads as W
+    from oracle import fem, multigrid as mg
+
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oc_sensitivity_32x16x16.json")))
+    hist = ref["history"]
+    assert hist[-1]["change"] < ref["tol"] <= min(h["change"] for h in hist[:-1])
+    dims = tuple(ref["dims"])
+    g = W.Grid(*dims)
+    f = W.cantilever_line_load(g)
+    mask = W.fixed_mask_face_x0(g)
+    H, Hs = T.filter_matrix(*dims, ref["rmin"])
+    n = g.n_elem
+    dv = np.full(n, 1.0 / n)
+    x = np.full(n, ref["volfrac"])
+    for h in hist[:3]:
+        u, _, _, _ = mg.mgpcg(mg.Hierarchy(*dims, x, mask, ref["levels"]), f, rtol=1e-12, maxit=5000)
+        c = fem.compliance(f, u)
+        dc = T.sensitivity_filter(H, Hs, x, fem.sensitivity(*dims, x, u))
+        x_new, _, _ = T.oc_update(x, dc, dv, lambda z: z.mean(), ref["volfrac"])
+        assert c == pytest.approx(h["compliance"], rel=1e-10)
+        assert abs(float(np.abs(x_new - x).max()) - h["change"]) < 1e-12
+        x = x_new
