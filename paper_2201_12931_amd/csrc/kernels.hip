@@ -121,23 +121,42 @@ __global__ void k_restrict_batch(Batch<RestrictTask<T>> tb) {
 }
 
 // Fine correction u += M P e_c by rows: each wave takes 64 consecutive nodes of
-// one fine node row (j, k), so the row's parities -- which coarse rows
-// contribute, with which weights -- are uniform over the wave, and along x a
-// node takes the mean of its two coarse neighbours (the same node twice where
-// i is even).  A block covers 64 columns of 4 rows: bx = column block +
-// cols * row block, cols = ceil(nxn / 64).
+// the four fine node rows (2J + dj, 2K + dk), dj, dk in {0, 1}, so which
+// coarse rows contribute to which row, with which weights, is uniform over the
+// wave, and along x a node takes the mean of its two coarse neighbours (the
+// same node twice where i is even).  The four x-interpolated coarse rows
+// (J + dj, K + dk) serve all four fine rows: the even rows take them as they
+// are, the odd ones the means (in the order of the per-node form, so both
+// forms agree bit for bit).  A block covers 64 columns of 4 row quads: bx =
+// column block + cols * quad block, cols = ceil(nxn / 64).  u and the support
+// bits are requested before the coarse values, and every component is written
+// back (the fixed ones unchanged), so no load waits behind a branch.
 template <typename T>
 __device__ __forceinline__ void prolong_block(const Level& F, const Level& C, const T* __restrict__ ec,
                                               T* __restrict__ u, const int* __restrict__ act, int bx, int rhs) {
   if (act && !act[rhs]) return;
   const int cols = (F.nxn + 63) >> 6;
-  const int row = __builtin_amdgcn_readfirstlane((bx / cols) * 4 + (int)(threadIdx.x >> 6));  // j + nyn k
+  const int nyq = (F.nyn + 1) >> 1, nzq = (F.nzn + 1) >> 1;
+  const int quad = __builtin_amdgcn_readfirstlane((bx / cols) * 4 + (int)(threadIdx.x >> 6));  // J + nyq K
   const int i = (bx % cols) * 64 + (int)(threadIdx.x & 63);
-  if (row >= F.nyn * F.nzn || i >= F.nxn) return;
-  const int j = row % F.nyn, k = row / F.nyn;
+  if (quad >= nyq * nzq || i >= F.nxn) return;
+  const int J = quad % nyq, K = quad / nyq;
+  const bool jo = 2 * J + 1 < F.nyn, ko = 2 * K + 1 < F.nzn;  // uniform: the odd rows exist
   const T* e = ec + 3ll * C.nn * rhs;
   u += 3ll * F.nn * rhs;
-  const int I0 = i >> 1, I1 = (i + 1) >> 1, J = j >> 1, K = k >> 1;
+  const long long row = F.nxn, pl = (long long)F.nxn * F.nyn;
+  const long long n00 = i + row * (2 * J) + pl * (2 * K);
+  long long nn[4] = {n00, n00 + row, n00 + pl, n00 + row + pl};  // (dj, dk) = (0,0) (1,0) (0,1) (1,1)
+  const bool has[4] = {true, jo, ko, jo && ko};
+  int m[4];
+  T uv[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    m[q] = has[q] ? (int)F.mask[nn[q]] : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uv[q][c] = has[q] ? u[3 * nn[q] + c] : T(0);
+  }
+  const int I0 = i >> 1, I1 = (i + 1) >> 1;
   // x-interpolated coarse row (Jc, Kc) at this node
   auto xrow = [&](int Jc, int Kc, T (&v)[3]) {
     const T* a = e + 3ll * (I0 + C.nxn * (Jc + C.nyn * Kc));
@@ -145,31 +164,31 @@ __device__ __forceinline__ void prolong_block(const Level& F, const Level& C, co
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = T(0.5) * (a[c] + b[c]);
   };
-  T s[3];
-  xrow(J, K, s);
-  if (j & 1) {  // uniform: halfway between coarse rows J and J + 1
-    T t[3];
-    xrow(J + 1, K, t);
+  auto put = [&](int q, const T (&s)[3]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (s[c] + t[c]);
+    for (int c = 0; c < 3; ++c) u[3 * nn[q] + c] = ((m[q] >> c) & 1) ? uv[q][c] : uv[q][c] + s[c];
+  };
+  T a[3], b[3], cz[3], d[3], s[3];
+  xrow(J, K, a);
+  put(0, a);
+  if (jo) {
+    xrow(J + 1, K, b);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[c] = T(0.5) * (a[c] + b[c]);  // the mean over coarse rows J, J + 1
+    put(1, b);
   }
-  if (k & 1) {  // uniform: halfway between coarse planes K and K + 1
-    T t[3];
-    xrow(J, K + 1, t);
-    if (j & 1) {
-      T t2[3];
-      xrow(J + 1, K + 1, t2);
+  if (ko) {
+    xrow(J, K + 1, cz);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) t[c] = T(0.5) * (t[c] + t2[c]);
+    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (a[c] + cz[c]);
+    put(2, s);
+    if (jo) {
+      xrow(J + 1, K + 1, d);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (b[c] + T(0.5) * (cz[c] + d[c]));
+      put(3, s);
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) s[c] = T(0.5) * (s[c] + t[c]);
   }
-  const long long n = i + (long long)F.nxn * row;
-  const int mk = F.mask[n];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    if (!((mk >> c) & 1)) u[3 * n + c] += s[c];
 }
 template <typename T>
 __global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u,
@@ -722,6 +741,10 @@ __global__ void k_reduce_final(const double* __restrict__ partials, double* __re
 // of 1024 threads with eight independent chains each keeps enough loads in
 // flight that the ~70 k partials of a large level take a few microseconds.
 constexpr int kSumThreads = 1024;
+// The per-iteration CG vector passes: each of the kReduceBlocks workgroups
+// walks contiguous ranges of kVecChunk elements, kReduceBlocks ranges apart
+// (measured faster than an element-wise grid stride at the same launch).
+constexpr long long kVecChunk = 4096;
 __global__ __launch_bounds__(kSumThreads) void k_sum_parts(const double* __restrict__ parts, int n,
                                                            double* __restrict__ out, const int* __restrict__ act) {
   if (act && !act[blockIdx.x]) return;
@@ -872,17 +895,20 @@ __device__ __forceinline__ void update_r_first_block(long long n, const double* 
   if (f32) f32 += off;
   if (t) t += off;
   double acc = 0.0;
+  for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
+    const long long e = min(b0 + kVecChunk, n);
 #pragma unroll 4
-  for (long long i = (long long)bx * kBlock + threadIdx.x; i < n; i += (long long)gx * kBlock) {
-    const double ri = r[i] - alpha * (double)q[i];
-    r[i] = ri;
-    acc += ri * ri;
-    if constexpr (sizeof(TW) == 4) {
-      const float fv = (float)ri;
-      f32[i] = fv;
-      if (t) t[i] = wdinv[i] * fv;
-    } else {
-      if (t) t[i] = wdinv[i] * ri;
+    for (long long i = b0 + threadIdx.x; i < e; i += kBlock) {
+      const double ri = r[i] - alpha * (double)q[i];
+      r[i] = ri;
+      acc += ri * ri;
+      if constexpr (sizeof(TW) == 4) {
+        const float fv = (float)ri;
+        f32[i] = fv;
+        if (t) t[i] = wdinv[i] * fv;
+      } else {
+        if (t) t[i] = wdinv[i] * ri;
+      }
     }
   }
   acc = block_sum(acc);
@@ -979,23 +1005,26 @@ __device__ __forceinline__ void update_px_block(long long n, const double* __res
   z += off;
   p += off;
   x += off;
-  if (p32) {
-    p32 += off;
+  if (p32) p32 += off;
+  for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
+    const long long e = min(b0 + kVecChunk, n);
+    if (p32) {
 #pragma unroll 4
-    for (long long i = (long long)bx * kBlock + threadIdx.x; i < n; i += (long long)gx * kBlock) {
-      const double pi = p[i];
-      x[i] += alpha * pi;
-      const double pn = (double)z[i] + beta * pi;
-      p[i] = pn;
-      p32[i] = (float)pn;
+      for (long long i = b0 + threadIdx.x; i < e; i += kBlock) {
+        const double pi = p[i];
+        x[i] += alpha * pi;
+        const double pn = (double)z[i] + beta * pi;
+        p[i] = pn;
+        p32[i] = (float)pn;
+      }
+    } else {
+#pragma unroll 4
+      for (long long i = b0 + threadIdx.x; i < e; i += kBlock) {
+        const double pi = p[i];
+        x[i] += alpha * pi;
+        p[i] = (double)z[i] + beta * pi;
+      }
     }
-    return;
-  }
-#pragma unroll 4
-  for (long long i = (long long)bx * kBlock + threadIdx.x; i < n; i += (long long)gx * kBlock) {
-    const double pi = p[i];
-    x[i] += alpha * pi;
-    p[i] = (double)z[i] + beta * pi;
   }
 }
 template <typename TZ>
@@ -1372,7 +1401,9 @@ void launch_sensitivity(const Level& L, const double* Ke, const double* rho, con
 // ---------------------------------------------------------------------------
 // Batched launches (several grids; see Batch in hexmg_impl.h).
 int restrict_blocks(const Level& C) { return blocks_for(C.nn); }
-int prolong_blocks(const Level& F) { return ((F.nxn + 63) / 64) * ((F.nyn * F.nzn + 3) / 4); }
+int prolong_blocks(const Level& F) {
+  return ((F.nxn + 63) / 64) * ((((F.nyn + 1) / 2) * ((F.nzn + 1) / 2) + 3) / 4);
+}
 int gemv_blocks(int n) { return (n + kBlock / 64 - 1) / (kBlock / 64); }
 
 template <typename T>
