@@ -35,10 +35,12 @@ HBM_PEAK_GBS = 8000.0
 # node).
 FAMILY_BYTES = {
     "smooth_f32": (16, 4),    # read u, f, omega/D, write u
+    "smooth1_f32": (12, 4),   # the sweep on the first sweep from zero, formed from f and omega/D: read f, omega/D, write u
     "residual_f32": (12, 4),  # read u, f, write r
     "apply_f32": (8, 4),      # read u, write A u
-    "apply_f64": (16, 8),
+    "apply_f64": (16, 8),     # binary64 solves; the mixed solver's K p reads a binary32 p: (12, 8), set in main()
     "smooth_f64": (32, 8),
+    "smooth1_f64": (24, 8),
     "residual_f64": (24, 8),
 }
 
@@ -60,7 +62,7 @@ def apply_bytes(g, word) -> float:
 TRAFFIC = {
     # level-0 binary32 Jacobi sweep, 768x384x384, 2 rows x 4 waves, z-chunk 4
     # (profiles/stream_smooth_f32_L0_cantilever_768x384x384_rf_traffic.md)
-    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "c69a7e4e8d357be5"): 9094194944.0,
+    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "8353785f36e9b8a0"): 9094580928.0,
 }
 
 
@@ -197,6 +199,8 @@ def main():
             raise RuntimeError(f"solve did not converge: {info[0]}")
         return info[0]
 
+    if args.precision == "mixed":  # K p reads the binary32 search direction
+        FAMILY_BYTES["apply_f64"] = (12, 8)
     main_grid = hexmg.Grid(g.nx, g.ny, g.nz, levels, precision=precs[args.precision])
     if args.coarse_cycle:  # before the first set_density: the timed choice is then skipped
         lv, nb = (int(v) for v in args.coarse_cycle.split(":"))

@@ -53,7 +53,9 @@ extern "C" {
 
 /* precision of the solver (hexmg_grid_desc.precision) */
 #define HEXMG_FP64 0  /* every step in binary64 */
-#define HEXMG_MIXED 1 /* V-cycle in binary32; CG vectors, dots, outer K p and coarsest solve in binary64 */
+#define HEXMG_MIXED 1 /* V-cycle in binary32; the search direction p stored in binary32; x, r,
+                         dots, the outer K p's arithmetic (on p widened) and coarsest solve in
+                         binary64 */
 #define HEXMG_MIXED32 2 /* V-cycle and the outer K p in binary32 (a binary32 copy of p, binary32 q);
                            CG vectors, dots, coarsest solve and compliance in binary64; the
                            recursive residual is replaced by the binary64 M f - A x every
@@ -115,12 +117,18 @@ typedef struct {
                            HEXMG_STENCIL_BF16 | HEXMG_STENCIL_F16.  The 16-bit forms are rounded
                            from the binary64 stencils (which set-up and binary64 V-cycles use),
                            so the binary32 V-cycle runs with a perturbed but fixed coarse operator */
+  int fuse_first;       /* 1 (default): with two or more sweeps and a level-0 streaming sweep kernel
+                           of a shape that has the form (hexmg_kernel_choice), the second
+                           pre-smoothing sweep of each CG iteration's V-cycle forms the first
+                           sweep from zero, (omega/D) r, as it loads its input, so the residual
+                           update writes no first-sweep vector; 0: the residual update writes it.
+                           The two give bit-identical results. */
 } hexmg_grid_desc;
 
 /* Fill *desc with the defaults (E0 1, Emin 1e-9, nu 0.3, penal 3, FP64, 2 sweeps,
  * omega automatic (0), density averaging, max_nrhs 1, automatic kernel choice, fixed face x = 0,
  * re-discretized coarse operators, V-cycle vectors in the solver's precision only,
- * residual replacement every 8 iterations)
+ * residual replacement every 8 iterations, first sweep formed on load)
  * for the given grid.  Host only. */
 int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc *desc);
 

@@ -170,11 +170,12 @@ inline unsigned long long batch_sig(int kind, int a = 0, int b = 0, int c = 0, i
          ((unsigned long long)(b & 0xff) << 16) | ((unsigned long long)(c & 0xff) << 24) |
          ((unsigned long long)(d & 0xff) << 32) | ((unsigned long long)(e & 0xff) << 40);
 }
-enum BatchKind { kBkStream, kBkRestrict, kBkProlong, kBkGemv, kBkUpdateR, kBkRrCheck, kBkUpdatePx };
+enum BatchKind { kBkStream, kBkRestrict, kBkProlong, kBkGemv, kBkUpdateR, kBkRrCheck, kBkUpdatePx, kBkStreamU32 };
 
+// smooth1: the sweep on the first sweep from zero, formed on load (kSmoothFirst)
 const char* kFamilies[] = {"apply_f64", "apply_f32", "smooth_f64", "smooth_f32", "residual_f64",
-                           "residual_f32"};
-constexpr int kNumFamilies = 6;
+                           "residual_f32", "smooth1_f64", "smooth1_f32"};
+constexpr int kNumFamilies = 8;
 
 struct Carver {
   char* base;
@@ -221,6 +222,7 @@ int validate(const hexmg_grid_desc* d) {
     return fail(HEXMG_ERR_INVALID, "bad kernel");
   if (d->coarse_op != HEXMG_COARSE_REDISCRETIZE && d->coarse_op != HEXMG_COARSE_GALERKIN)
     return fail(HEXMG_ERR_INVALID, "bad coarse_op");
+  if (d->fuse_first != 0 && d->fuse_first != 1) return fail(HEXMG_ERR_INVALID, "fuse_first must be 0 or 1");
   if (d->stencil_storage != HEXMG_STENCIL_F32 && d->stencil_storage != HEXMG_STENCIL_BF16 &&
       d->stencil_storage != HEXMG_STENCIL_F16)
     return fail(HEXMG_ERR_INVALID, "bad stencil_storage");
@@ -302,10 +304,11 @@ size_t carve(hexmg_grid* g, char* base) {
   g->r = c.take<double>(N0 * R);
   // binary64 z only for binary64 solves (mixed precision keeps z in binary32)
   g->z = g->desc.precision == HEXMG_FP64 ? c.take<double>(N0 * R) : nullptr;
-  g->p = c.take<double>(N0 * R);
+  // the search direction: binary64 (binary64 solves; the binary32 outer K p
+  // keeps a binary32 copy), binary32 alone in the mixed form
+  g->p = g->desc.precision != HEXMG_MIXED ? c.take<double>(N0 * R) : nullptr;
   g->q = c.take<double>(N0 * R);
-  // binary32 copy of p and binary32 q for the binary32 outer K p
-  g->p32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
+  g->p32 = g->desc.precision != HEXMG_FP64 ? c.take<float>(N0 * R) : nullptr;
   g->q32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
   g->partials = c.take<double>((size_t)kMaxDotParts * R);  // >= kReduceBlocks
   {  // the most workgroups a level-0 streaming launch can have (z-chunk 1)
@@ -457,9 +460,25 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
   HIP_TRY(hipMemsetAsync(u, 0, bytes, s));
   if (f) HIP_TRY(hipMemsetAsync(f, 0, bytes, s));
   const bool f32 = sizeof(T) == 4;
+  // the mixed form's binary64 K p reads the binary32 direction: its own kernels are timed
+  const bool u32in = !f32 && modes == 1 && g->desc.precision == HEXMG_MIXED;
+  if (u32in) HIP_TRY(hipMemsetAsync(g->p32, 0, 3ull * L.nn * sizeof(float), s));
+  auto run = [&](const hexmg_grid::Choice& c, int mode) {
+    if constexpr (sizeof(T) == 8) {
+      if (u32in) {
+        const HaarCoef<double> q = *reinterpret_cast<const HaarCoef<double>*>(&g->hq64);
+        if (c.kernel == HEXMG_KERNEL_STREAM)
+          launch_apply_u32(c.shape, L, q, g->E64[level], g->p32, y, c.zchunk, 1, nullptr, s);
+        else
+          launch_gather_apply_u32(L, g->Ke64, g->E64[level], g->p32, y, 1, nullptr, s);
+        return;
+      }
+    }
+    launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
+  };
   std::vector<hexmg_grid::Choice> cand;
   for (int sh = 0; sh < stream_shapes(f32); ++sh)
-    for (int zc : {1, 2, 4, 8, 16, 32, 64})
+    for (int zc : {1, 2, 4, 8, 16, 32, 64, 128})
       if ((zc <= L.nzn || zc == 2) && (long long)((L.nzn + zc - 1) / zc) * g->desc.max_nrhs <= 65535)
         cand.push_back({HEXMG_KERNEL_STREAM, zc, sh});
   cand.push_back({HEXMG_KERNEL_GATHER, 0, 0});
@@ -473,9 +492,9 @@ int tune_level(hexmg_grid* g, int level, T* u, T* f, T* y, const T* wd, std::arr
     // keep the timer's noise below the differences between candidates
     const int reps = L.ne < 100000 ? 12 : 3;
     for (const auto& c : cand) {
-      launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
+      run(c, mode);
       HIP_TRY(hipEventRecord(e0, s));
-      for (int rep = 0; rep < reps; ++rep) launch_choice<T>(g, c, mode, level, u, f, wd, y, 1, s);
+      for (int rep = 0; rep < reps; ++rep) run(c, mode);
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -503,7 +522,7 @@ int tune_kernels(hexmg_grid* g, hipStream_t s) {
       if (int e = tune_level<double>(g, l, g->vu64[l], g->vf64[l], g->vt64[l], g->wd64[l], &g->choice64[l], s))
         return e;
     } else if (l == 0) {
-      if (int e = tune_level<double>(g, 0, g->p, nullptr, g->q, nullptr, &g->choice64[0], s, 1)) return e;
+      if (int e = tune_level<double>(g, 0, g->r, nullptr, g->q, nullptr, &g->choice64[0], s, 1)) return e;
     }
     if (g->vu32[l])
       if (int e = tune_level<float>(g, l, g->vu32[l], g->vf32[l], g->vt32[l], g->wd32[l], &g->choice32[l], s))
@@ -525,9 +544,61 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
   }
   LaunchTimer t;
   if (a && b) t = LaunchTimer{a, b};
-  launch_choice<T>(g, (f32 ? g->choice32[level] : g->choice64[level])[mode], mode, level, u, f, wd, y, nrhs, s, maskin,
+  const int cm = mode == kSmoothFirst ? kSmooth : mode;  // the sweep's kernel choice
+  launch_choice<T>(g, (f32 ? g->choice32[level] : g->choice64[level])[cm], mode, level, u, f, wd, y, nrhs, s, maskin,
                    act, t, dotp);
   if (a && b) g->recs.push_back({family_of(mode, f32), a, b, g->prof_tag});
+}
+
+// y = A p32 at level 0 in binary64 on the binary32 search direction of the
+// mixed form (the level's binary64 K u choice; recorded as a batchable task
+// while the grid is batched).
+void apply_p32(hexmg_grid* g, double* y, int nrhs, hipStream_t s, const int* act, double* dotp) {
+  const hexmg_grid::Choice ch = g->choice64[0][kApply];
+  const Level L = g->lv[0];
+  const float* u = g->p32;
+  const double* E = g->E64[0];
+  const double* Ke = g->Ke64;
+  const HaarCoef<double> q = *reinterpret_cast<const HaarCoef<double>*>(&g->hq64);
+  if (g->rec) {
+    if (ch.kernel == HEXMG_KERNEL_STREAM) {
+      StreamTask<double> task{};
+      task.L = L;
+      task.E = E;
+      task.u32 = u;
+      task.y = y;
+      task.act = act;
+      task.dotp = dotp;
+      task.zchunk = ch.zchunk;
+      stream_grid(L, false, ch.shape, ch.zchunk, &task.gx, &task.gy, &task.nchunks);
+      const int shape = ch.shape, zc = ch.zchunk;
+      const bool pre = zc == 1, dot = dotp != nullptr;
+      emit_task<StreamTask<double>>(
+          g, g->stage, s,
+          batch_sig(kBkStreamU32, sizeof(double), kApply, shape, pre, dot) | ((unsigned long long)g->rec_class << 48),
+          task, task.gx * task.gy * task.nchunks * nrhs,
+          [=](hipStream_t st) { launch_apply_u32(shape, L, q, E, u, y, zc, nrhs, act, st, LaunchTimer{}, dotp); },
+          [=](const Batch<StreamTask<double>>& b, hipStream_t st) {
+            launch_stream_batch<double>(kApply, shape, pre, dot, b, q, st, true);
+          });
+    } else {
+      emit_launch(g, g->stage, s,
+                  [=](hipStream_t st) { launch_gather_apply_u32(L, Ke, E, u, y, nrhs, act, st, LaunchTimer{}); });
+    }
+    return;
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  if (g->profile) {
+    a = take_event(g);
+    b = take_event(g);
+  }
+  LaunchTimer t;
+  if (a && b) t = LaunchTimer{a, b};
+  if (ch.kernel == HEXMG_KERNEL_STREAM)
+    launch_apply_u32(ch.shape, L, q, E, u, y, ch.zchunk, nrhs, act, s, t, dotp);
+  else
+    launch_gather_apply_u32(L, Ke, E, u, y, nrhs, act, s, t);
+  if (a && b) g->recs.push_back({family_of(kApply, false), a, b, g->prof_tag});
 }
 
 // drops the records of launches tagged with a CG iteration beyond last_its
@@ -617,6 +688,17 @@ void wait_coarse(hexmg_grid* g, hipStream_t s) {
   g->coarse_waited_valid = true;
 }
 
+// Whether the level-0 pre-smoothing forms the first sweep from zero on load
+// (kSmoothFirst: the second sweep reads f and omega/D instead of the first's
+// output), so that the CG residual update writes no first sweep: two or more
+// sweeps, and a streaming sweep kernel with such a form.
+template <typename T>
+bool first_fused(const hexmg_grid* g) {
+  if (!g->desc.fuse_first || g->L < 2 || g->desc.smooth_sweeps < 2) return false;
+  const hexmg_grid::Choice& ch = (sizeof(T) == 4 ? g->choice32 : g->choice64)[0][kSmooth];
+  return ch.kernel == HEXMG_KERNEL_STREAM && first_shape_ok(sizeof(T) == 4, ch.shape);
+}
+
 // out = V_l(f) from a zero initial guess.  The first sweep writes the level's
 // scratch vector and the 2*nu-1 further sweeps alternate, so the result lands
 // in `out` without a copy.  f and out must not overlap.  With first_done the
@@ -643,7 +725,10 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   const int nu = g->desc.smooth_sweeps;
   T* buf[2] = {v.t[l], out};
   int cur = 0;
-  if (!first_done) {
+  // level 0: the second sweep may form the first from f (first_fused); the
+  // first sweep's output is then neither written nor read
+  const bool first = l == 0 && !maskin && first_fused<T>(g);
+  if (!first_done && !first) {
     const T* wdl = v.wd[l];
     T* t0 = buf[0];
     emit_launch(g, st_down(l, 0), s,
@@ -651,7 +736,8 @@ void vcycle_level(hexmg_grid* g, VView<T>& v, int l, const T* f, T* out, int nrh
   }
   for (int it = 1; it < nu; ++it) {
     g->stage = st_down(l, it);
-    gather<T>(g, kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin, act);
+    gather<T>(g, it == 1 && first ? kSmoothFirst : kSmooth, l, buf[cur], f, v.wd[l], buf[1 - cur], nrhs, s, maskin,
+              act);
     cur = 1 - cur;
   }
   g->stage = st_down(l, 90);
@@ -874,6 +960,7 @@ int hexmg_default_desc(int nx, int ny, int nz, int levels, hexmg_grid_desc* d) {
   d->fixed_mask = nullptr;
   d->vcycle_both = 0;
   d->rr_every = 8;
+  d->fuse_first = 1;
   return 0;
 }
 
@@ -1228,6 +1315,8 @@ struct PcgRun {
     double* pq_target = npq ? parts_target(g, npq, g->partials) : nullptr;
     if (f32)
       gather<float>(g, kApply, 0, g->p32, nullptr, nullptr, g->q32, nb, s, false, g->active, pq_target);
+    else if (!g->p)  // mixed form: binary64 product on the binary32 direction
+      apply_p32(g, g->q, nb, s, g->active, pq_target);
     else
       gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active, pq_target);
     if (npq) npq = sum_big(g, npq, g->partials, nb, g->active, kStEnd + 205, s);
@@ -1235,10 +1324,12 @@ struct PcgRun {
       const long long n = N();
       const int b = nb;
       double *p = g->p, *q = g->q, *parts = g->partials;
-      float* q32 = g->q32;
+      float *q32 = g->q32, *p32 = g->p32;
       const int* act = g->active;
       if (f32)
         emit_launch(g, kStEnd + 210, s, [=](hipStream_t st) { launch_dot_mixed(n, q32, p, parts, b, act, st); });
+      else if (!p)
+        emit_launch(g, kStEnd + 210, s, [=](hipStream_t st) { launch_dot_mixed(n, p32, q, parts, b, act, st); });
       else
         emit_launch(g, kStEnd + 210, s, [=](hipStream_t st) { launch_dot_partial(n, p, q, parts, b, act, st); });
       npq = kReduceBlocks;
@@ -1246,11 +1337,11 @@ struct PcgRun {
     // r -= alpha q with the next preconditioner's first sweep (x += alpha p follows in the p update)
     const bool sweep = g->L > 1;
     if (g->desc.precision == HEXMG_FP64) {
-      emit_update_r<double, double>(npq, (k - 1) & 1, g->q, g->wd64[0], nullptr, sweep ? g->vt64[0] : nullptr,
-                                    nullptr);
+      emit_update_r<double, double>(npq, (k - 1) & 1, g->q, g->wd64[0], nullptr,
+                                    sweep && !first_fused<double>(g) ? g->vt64[0] : nullptr, nullptr);
     } else if (!f32) {
-      emit_update_r<float, double>(npq, (k - 1) & 1, g->q, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr,
-                                   nullptr);
+      emit_update_r<float, double>(npq, (k - 1) & 1, g->q, g->wd32[0], g->vf32[0],
+                                   sweep && !first_fused<float>(g) ? g->vt32[0] : nullptr, nullptr);
     } else {
       // binary32 A p; every rr_every-th iteration of a right-hand side its
       // residual is replaced by the binary64 M f - A x (x brought up to date
@@ -1267,8 +1358,8 @@ struct PcgRun {
       if (replace)
         emit_launch(g, kStEnd + 220, s,
                     [=](hipStream_t st) { launch_replace_flags(sc, act, repl, b, every, st); });
-      emit_update_r<float, float>(npq, (k - 1) & 1, g->q32, g->wd32[0], g->vf32[0], sweep ? g->vt32[0] : nullptr,
-                                  replace ? g->repl : nullptr);
+      emit_update_r<float, float>(npq, (k - 1) & 1, g->q32, g->wd32[0], g->vf32[0],
+                                  sweep && !first_fused<float>(g) ? g->vt32[0] : nullptr, replace ? g->repl : nullptr);
       if (replace) {
         double* p = g->p;
         double* x = u;
@@ -1333,7 +1424,7 @@ struct PcgRun {
       emit_update_px<double>(nrz, (k - 1) & 1, g->z, nullptr);
     } else {
       const int nrz = precondition(g, g->r, g->z, g->partials, nb, g->active, s, false, true, true);
-      emit_update_px<float>(nrz, (k - 1) & 1, g->vu32[0], m32() ? g->p32 : nullptr);
+      emit_update_px<float>(nrz, (k - 1) & 1, g->vu32[0], g->p32);  // mixed: the direction itself
     }
     return issue_iteration(k + 1);
   }
@@ -1360,7 +1451,15 @@ struct PcgRun {
     emit_launch(g, kStInit, s, [=](hipStream_t st) { launch_pcg_init(rt2, parts, sc, act, b, st); });
     if (maxit == 0) return enqueue_finish(0);
     g->prof_tag = 1;
-    precondition(g, g->r, g->p, g->partials, nb, g->active, s);  // p0 = z0 = M^{-1} r0
+    if (p) {
+      precondition(g, g->r, p, g->partials, nb, g->active, s);  // p0 = z0 = M^{-1} r0
+    } else {  // mixed form: z0 stays in the binary32 V-cycle output, which p0 copies
+      precondition(g, g->r, nullptr, g->partials, nb, g->active, s, false);
+      const float* z32 = g->vu32[0];
+      const size_t bytes = (size_t)n * b * sizeof(float);
+      HIP_TRY(emit_api(g, kStEnd + 20, s,
+                       [=](hipStream_t st) { return hipMemcpyAsync(p32, z32, bytes, hipMemcpyDeviceToDevice, st); }));
+    }
     emit_launch(g, kStEnd + 10, s, [=](hipStream_t st) { launch_reduce_final(parts, sc + kRz0, kScalars, b, st); });
     if (m32()) emit_launch(g, kStEnd + 20, s, [=](hipStream_t st) { launch_f64_to_f32(n, p, p32, b, act, st); });
     if (int e = issue_iteration(1)) return e;
@@ -1426,9 +1525,10 @@ struct PcgRun {
     const int b = nb;
     const long long n = N();
     double *p = g->p, *x = u, *q = g->q, *pa = g->partials, *pb = g->partials2;
+    const float* p32 = g->p32;
     const double* ff = f;
     emit_launch(g, kStEnd + 600, s, [=](hipStream_t st) {
-      launch_flush_x(n, sc, p, x, b, st);  // the last iteration's x += alpha p
+      launch_flush_x(n, sc, p, x, b, st, nullptr, p32);  // the last iteration's x += alpha p
     });
     {
       hipEvent_t e1 = t1;
@@ -1692,8 +1792,8 @@ int hexmg_compliance_sensitivity(hexmg_grid_t g, const double* f, const double* 
   for (int k = 0; k < nrhs; ++k) {
     if (dc) {
       const double w = weights ? weights[k] : 1.0;
-      launch_sensitivity(L0, g->Ke64, g->rho[0], u + k * N, -d.penal * (d.E0 - d.Emin) * w, d.penal - 1.0,
-                         k > 0, dc, s);
+      launch_sensitivity_haar(L0, g->hq64, g->rho[0], u + k * N, -d.penal * (d.E0 - d.Emin) * w, d.penal - 1.0,
+                              k > 0, dc, s);
     }
     if (c_host) {
       dot(g, N, f + k * N, u + k * N, g->scalars + kTmp, 1, s);

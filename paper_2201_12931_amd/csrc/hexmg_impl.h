@@ -69,6 +69,19 @@ template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
                    const LaunchTimer& t = {}, double* dotp = nullptr);
+// binary64 K u (mode apply, input not masked) of the binary32 u: the
+// product on the mixed solver's binary32 search direction; shape is a
+// binary64 shape, dotp as for launch_stream
+void launch_apply_u32(int shape, const Level& L, const HaarCoef<double>& q, const double* E, const float* u,
+                      double* y, int zchunk, int nrhs, const int* act, hipStream_t s, const LaunchTimer& t = {},
+                      double* dotp = nullptr);
+// adjoint sensitivity dc_e = coef rho_e^pm1 u_e^T K0 u_e (accumulate: added
+// to dc) with the element energy in the Haar basis of q
+void launch_sensitivity_haar(const Level& L, const HaarCoef<double>& q, const double* rho, const double* u,
+                             double coef, double pm1, int accumulate, double* dc, hipStream_t s);
+// whether streaming shape `shape` has a kSmoothFirst form (launch_stream and
+// launch_stream_batch take that mode only for such shapes, input unmasked, no dotp)
+bool first_shape_ok(bool f32, int shape);
 // workgroups of one right-hand side's launch of the streaming kernel
 int stream_blocks(const Level& L, bool f32, int shape, int zchunk);
 
@@ -102,6 +115,7 @@ struct StreamTask {
   Level L;
   const T* E;
   const T* u;
+  const float* u32;  // binary64 K u of a binary32 input (u unused; batches launched with u32in)
   const T* f;
   const T* wd;
   T* y;
@@ -113,7 +127,7 @@ struct StreamTask {
 // mode's dot product) are common to the batch.
 template <typename T>
 void launch_stream_batch(int mode, int shape, bool pre, bool dot, const Batch<StreamTask<T>>& b,
-                         const HaarCoef<T>& q, hipStream_t s);
+                         const HaarCoef<T>& q, hipStream_t s, bool u32in = false);
 // the launch grid of one grid's streaming-kernel launch: (gx, gy, nchunks)
 void stream_grid(const Level& L, bool f32, int shape, int zchunk, int* gx, int* gy, int* nchunks);
 
@@ -216,8 +230,13 @@ template <typename T>
 void launch_gather(int mode, const Level& L, const T* Ke, const T* E, const T* u, const T* f,
                    const T* wdinv, T* y, int nrhs, const int* act, hipStream_t s,
                    const LaunchTimer& t = {});
+// binary64 y = A u of the binary32 u (node-gather form of launch_apply_u32)
+void launch_gather_apply_u32(const Level& L, const double* Ke, const double* E, const float* u, double* y, int nrhs,
+                             const int* act, hipStream_t s, const LaunchTimer& t = {});
 // mode: 0 y = A u; 1 y = u + wdinv (f - A u); 2 y = f - A u
-enum { kApply = 0, kSmooth = 1, kResidual = 2 };
+// element-product modes; kSmoothFirst (streaming kernel only): a Jacobi sweep
+// whose input is the first sweep from zero, (omega/D) f, formed on load
+enum { kApply = 0, kSmooth = 1, kResidual = 2, kSmoothFirst = 3 };
 
 template <typename T>
 void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, const int* act, hipStream_t s);
@@ -296,13 +315,16 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
 // rz_new = sum of the nrz rz partials of a right-hand side (nrz apart);
 // beta = rz_new / rz[parity]; x += alpha p (the previous iteration's);
 // p = z + beta p; rz[1-parity] = rz_new
-// (x += alpha p only while s[kXPend]; p32, may be null: binary32 copy of the new p)
+// (x += alpha p only while s[kXPend]; p32, may be null: binary32 copy of the
+// new p; with p null the direction lives in p32 alone, read widened and
+// written rounded to binary32)
 template <typename TZ>
 void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
                       double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32 = nullptr);
-// x += alpha p for the right-hand sides where it is still due (s[kXPend])
+// x += alpha p for the right-hand sides where it is still due (s[kXPend]);
+// with p null, the binary32 direction p32
 void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s,
-                    const int* act = nullptr);
+                    const int* act = nullptr, const float* p32 = nullptr);
 // partials of r . (double) u32 (the binary32 V-cycle output, not widened in memory)
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s);
@@ -311,8 +333,6 @@ void launch_to64_dot(long long n, const float* u32, const double* r, double* z, 
                      const int* act, hipStream_t s);
 void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s);
 
-void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
-                        double coef, double pm1, int accumulate, double* dc, hipStream_t s);
 void launch_symmetrize(int n, const double* A, double* B, hipStream_t s);
 // Blocked Gauss-Jordan inverse of the n x n SPD matrix in A (B is the
 // ping-pong buffer, D 2 kGJBlock^2 scratch for the pivot-block inverses);
@@ -462,7 +482,10 @@ struct hexmg_grid {
   bool tuned;
   // PCG
   double *r, *z, *p, *q;
-  float *p32, *q32;  // binary32 p and A p of HEXMG_MIXED32 (else null)
+  // p: binary64 direction (null with HEXMG_MIXED, whose direction is p32 alone);
+  // p32: binary32 direction (HEXMG_MIXED) or binary32 copy of p (HEXMG_MIXED32);
+  // q32: binary32 A p of HEXMG_MIXED32
+  float *p32, *q32;
   double* partials;
   double* partials2;
   double* big_parts = nullptr;  // per-workgroup partials of level-0 launches beyond kMaxDotParts workgroups

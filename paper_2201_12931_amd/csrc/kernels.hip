@@ -59,19 +59,27 @@ __device__ inline double sum_partials(const double* __restrict__ partials) {
 
 inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
+// rho^p of the SIMP law (Eq. 2): the paper's p = 3 (and p = 1) by products,
+// other exponents by pow
+__device__ inline double simp_pow(double r, double p) {
+  if (p == 3.0) return r * r * r;
+  if (p == 1.0) return r;
+  return pow(r, p);
+}
+
 // ---------------------------------------------------------------------------
 // Matrix-free K u (Sec. 4.2.1), node-gather form: one thread per node (see
 // gather_node).
-template <typename T, int MODE>
+template <typename T, int MODE, typename TU = T>
 __global__ __launch_bounds__(kBlock) void k_gather(Level L, const T* __restrict__ Ke,
-                                                   const T* __restrict__ E, const T* __restrict__ u,
+                                                   const T* __restrict__ E, const TU* __restrict__ u,
                                                    const T* __restrict__ f,
                                                    const T* __restrict__ wdinv, T* __restrict__ y,
                                                    const int* __restrict__ act) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= L.nn || (act && !act[blockIdx.y])) return;
   const long long off = 3ll * L.nn * blockIdx.y;  // right-hand side blockIdx.y: vectors are [nrhs][3 nn]
-  gather_node<T, MODE>(L, Ke, E, u + off, MODE != kApply ? f + off : f, wdinv, y + off, n);
+  gather_node<T, MODE, TU>(L, Ke, E, u + off, MODE != kApply ? f + off : f, wdinv, y + off, n);
 }
 
 // First sweep from a zero guess: u = omega D^{-1} f.
@@ -214,7 +222,7 @@ __global__ void k_simp(int ne, const double* __restrict__ rho, double E0, double
     const double r = rho[e];
     if (!(r >= 0.0 && r <= 1.0)) bad = 1;  // also catches NaN
     rho_copy[e] = r;
-    const double E = scale * (Emin + pow(r, p) * (E0 - Emin));
+    const double E = scale * (Emin + simp_pow(r, p) * (E0 - Emin));
     E64[e] = E;
     E32[e] = (float)E;
   }
@@ -245,7 +253,7 @@ __global__ void k_modulus_from_density(int ne, const double* __restrict__ rho, d
                                        float* __restrict__ E32) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= ne) return;
-  const double E = scale * (Emin + pow(rho[e], p) * (E0 - Emin));
+  const double E = scale * (Emin + simp_pow(rho[e], p) * (E0 - Emin));
   E64[e] = E;
   E32[e] = (float)E;
 }
@@ -270,7 +278,7 @@ __global__ void k_coarsest_moduli(Level F, Level C, int blk, const double* __res
   s = block_sum(s);
   if (threadIdx.x == 0) {
     const double m = s / nb;
-    Ec[e] = density ? scale * (Emin + pow(m, p) * (E0 - Emin)) : scale * m;
+    Ec[e] = density ? scale * (Emin + simp_pow(m, p) * (E0 - Emin)) : scale * m;
   }
 }
 
@@ -1003,9 +1011,21 @@ __device__ __forceinline__ void update_px_block(long long n, const double* __res
   }
   const long long off = n * rhs;
   z += off;
-  p += off;
   x += off;
   if (p32) p32 += off;
+  if (!p) {  // the direction is held in binary32 only: x += alpha p, p = z + beta p rounded to binary32
+    for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
+      const long long e = min(b0 + kVecChunk, n);
+#pragma unroll 4
+      for (long long i = b0 + threadIdx.x; i < e; i += kBlock) {
+        const double pi = (double)p32[i];
+        x[i] += alpha * pi;
+        p32[i] = (float)((double)z[i] + beta * pi);
+      }
+    }
+    return;
+  }
+  p += off;
   for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
     const long long e = min(b0 + kVecChunk, n);
     if (p32) {
@@ -1109,7 +1129,8 @@ __global__ void k_pcg_restart(double* __restrict__ sc, int* __restrict__ active,
 
 // grid (kReduceBlocks, nrhs): the x += alpha p still due when the solve stops
 // (act, may be null: only the right-hand sides whose flag is set)
-__global__ void k_flush_x(long long n, const double* __restrict__ sc, const double* __restrict__ p,
+template <typename TP>
+__global__ void k_flush_x(long long n, const double* __restrict__ sc, const TP* __restrict__ p,
                           double* __restrict__ x, const int* __restrict__ act) {
   const int rhs = blockIdx.y;
   const double* s = sc + kScalars * rhs;
@@ -1120,7 +1141,7 @@ __global__ void k_flush_x(long long n, const double* __restrict__ sc, const doub
   x += off;
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
-    x[i] += alpha * p[i];
+    x[i] += alpha * (double)p[i];
 }
 
 // partials of r . (double) u32 (grid (kReduceBlocks, nrhs)); the widened z is not stored
@@ -1170,34 +1191,6 @@ __global__ void k_f64_to_f32(long long n, const double* __restrict__ a, float* _
   if (i < n) b[off + i] = (float)a[off + i];
 }
 
-// Adjoint sensitivity (Eq. 7 with u* = u): dc_e = coef rho_e^(p-1) u_e^T K0 u_e,
-// coef = -p (E0 - Emin) times the load-case weight.
-__global__ void k_sensitivity(Level L, const double* __restrict__ Ke, const double* __restrict__ rho,
-                              const double* __restrict__ u, double coef, double pm1, int accumulate,
-                              double* __restrict__ dc) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= L.ne) return;
-  const int i = e % L.nx, t = e / L.nx, j = t % L.ny, k = t / L.ny;
-  double ue[24];
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const int m = (i + (b & 1)) + L.nxn * ((j + ((b >> 1) & 1)) + L.nyn * (k + (b >> 2)));
-    ue[3 * b] = u[3ll * m];
-    ue[3 * b + 1] = u[3ll * m + 1];
-    ue[3 * b + 2] = u[3ll * m + 2];
-  }
-  double q = 0.0;
-#pragma unroll
-  for (int r = 0; r < 24; ++r) {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 24; ++c) s += Ke[r * 24 + c] * ue[c];
-    q += ue[r] * s;
-  }
-  const double v = coef * pow(rho[e], pm1) * q;
-  dc[e] = accumulate ? dc[e] + v : v;
-}
-
 }  // namespace
 
 // ---- launchers ------------------------------------------------------------
@@ -1218,6 +1211,12 @@ template void launch_gather<double>(int, const Level&, const double*, const doub
 template void launch_gather<float>(int, const Level&, const float*, const float*, const float*,
                                    const float*, const float*, float*, int, const int*, hipStream_t,
                                    const LaunchTimer&);
+void launch_gather_apply_u32(const Level& L, const double* Ke, const double* E, const float* u, double* y, int nrhs,
+                             const int* act, hipStream_t s, const LaunchTimer& t) {
+  const dim3 g(blocks_for(L.nn), nrhs);
+  launch_timed(k_gather<double, kApply, float>, g, dim3(kBlock), s, t, L, Ke, E, u, (const double*)nullptr,
+               (const double*)nullptr, y, act);
+}
 
 template <typename T>
 void launch_jacobi_first(long long n, const T* wdinv, const T* f, T* u, int nrhs, const int* act, hipStream_t s) {
@@ -1379,8 +1378,11 @@ template void launch_update_px<double>(long long, const double*, int, double*, c
 template void launch_update_px<float>(long long, const double*, int, double*, const int*, const float*, double*,
                                       double*, int, int, hipStream_t, float*);
 void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s,
-                    const int* act) {
-  k_flush_x<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x, act);
+                    const int* act, const float* p32) {
+  if (p)
+    k_flush_x<double><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x, act);
+  else
+    k_flush_x<float><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p32, x, act);
 }
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s) {
@@ -1392,10 +1394,6 @@ void launch_to64_dot(long long n, const float* u32, const double* r, double* z, 
 }
 void launch_f64_to_f32(long long n, const double* a, float* b, int nrhs, const int* act, hipStream_t s) {
   k_f64_to_f32<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(n, a, b, act);
-}
-void launch_sensitivity(const Level& L, const double* Ke, const double* rho, const double* u,
-                        double coef, double pm1, int accumulate, double* dc, hipStream_t s) {
-  k_sensitivity<<<blocks_for(L.ne), kBlock, 0, s>>>(L, Ke, rho, u, coef, pm1, accumulate, dc);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,9 +18,10 @@ __device__ inline void node_coords(const Level& L, int n, int& i, int& j, int& k
 // matrix and no scatter conflicts.  Supports: u is read as M u; fixed DOFs
 // return u.  MODE 0: y = A u;  1: y = u + wdinv (f - A u) (damped Jacobi,
 // Eq. 21);  2: y = f - A u (residual, Eq. 19).  Vectors of one right-hand side.
-template <typename T, int MODE>
+// TU: the type u is stored in (T, or binary32 read into binary64 arithmetic).
+template <typename T, int MODE, typename TU = T>
 __device__ inline void gather_node(const Level& L, const T* __restrict__ Ke, const T* __restrict__ E,
-                                   const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ wdinv,
+                                   const TU* __restrict__ u, const T* __restrict__ f, const T* __restrict__ wdinv,
                                    T* __restrict__ y, int n) {
   int i, j, k;
   node_coords(L, n, i, j, k);
@@ -37,10 +38,10 @@ __device__ inline void gather_node(const Level& L, const T* __restrict__ Ke, con
         if (ii >= 0 && ii < L.nxn && jj >= 0 && jj < L.nyn && kk >= 0 && kk < L.nzn) {
           const int m = n + dx + L.nxn * (dy + L.nyn * dz);
           const int mk = L.mask[m];
-          const T* um = u + 3ll * m;
-          v0 = (mk & 1) ? T(0) : um[0];
-          v1 = (mk & 2) ? T(0) : um[1];
-          v2 = (mk & 4) ? T(0) : um[2];
+          const TU* um = u + 3ll * m;
+          v0 = (mk & 1) ? T(0) : T(um[0]);
+          v1 = (mk & 2) ? T(0) : T(um[1]);
+          v2 = (mk & 4) ? T(0) : T(um[2]);
         }
         un[o][0] = v0;
         un[o][1] = v1;

@@ -100,6 +100,51 @@ __device__ inline void block_product(const HaarCoef<T>& q, T E, const T (&v)[8][
   for (int c = 0; c < 3; ++c) t[0][c] = T(0);
 }
 
+// Adjoint sensitivity (Eq. 7 with the self-adjoint u* = u), one thread per
+// element: dc_e = coef rho_e^(p-1) u_e^T K0 u_e, with the element energy
+// formed in the Haar basis, u_e^T K0 u_e = v^T (Q / 64) v, v = H u_e (about 150
+// operations instead of 576 multiply-adds on a dense K0).  coef = -p (E0 -
+// Emin) times the load-case weight; with accumulate the result is added to dc.
+__global__ __launch_bounds__(256) void k_sensitivity_haar(Level L, HaarCoef<double> q,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ u, double coef, double pm1,
+                                                           int accumulate, double* __restrict__ dc) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= L.ne) return;
+  const int i = e % L.nx, t = e / L.nx, j = t % L.ny, k = t / L.ny;
+  double v[8][3];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const long long m = (i + (b & 1)) + (long long)L.nxn * ((j + ((b >> 1) & 1)) + (long long)L.nyn * (k + (b >> 2)));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[b][c] = u[3 * m + c];
+  }
+  // per axis a: the pair (lo, hi) across bit a becomes (hi + lo, hi - lo)
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      if (!(b & (1 << a))) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double lo = v[b][c], hi = v[b | (1 << a)][c];
+          v[b][c] = hi + lo;
+          v[b | (1 << a)][c] = hi - lo;
+        }
+      }
+  double tq[8][3];
+  block_product<double>(q, 1.0, v, tq);
+  double en = 0.0;
+#pragma unroll
+  for (int m = 1; m < 8; ++m)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) en += v[m][c] * tq[m][c];
+  const double r = rho[e];
+  const double w = pm1 == 2.0 ? r * r : pow(r, pm1);
+  const double val = coef * w * en;
+  dc[e] = accumulate ? dc[e] + val : val;
+}
+
 // Buffer-resource access.  Every load and store of the kernel goes through a
 // raw buffer resource that spans one z-plane of one array; the per-lane byte
 // offset inside the plane is fixed for the whole z-march and only the plane
@@ -163,16 +208,21 @@ __device__ inline double select_bit(int m, int c, double a, double b) { return (
 // DOT (K u and the sweep, without MASKIN): also one partial per workgroup
 // into dotp, of u . (A u) for K u and of f . y (the right-hand side times the
 // new iterate) for the sweep.
+// TU: the type u is stored in (T, or binary32 widened on load for the
+// binary64 product on a binary32 search direction).
 // One workgroup's tile: (bx, by, bz) is its place in the grid's launch of
 // gx * gy * (nchunks * nrhs) workgroups (the launch grid itself, or its slot
 // in a batched launch over several grids).
-template <typename T, int MODE, int R, int W, bool MASKIN, int PRE, bool DOT>
+template <typename T, int MODE, int R, int W, bool MASKIN, int PRE, bool DOT, typename TU = T>
 __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q, const T* __restrict__ Eg,
-                                            const T* __restrict__ ug, const T* __restrict__ fg,
+                                            const TU* __restrict__ ug, const T* __restrict__ fg,
                                             const T* __restrict__ wg, T* __restrict__ yg, int zchunk, int nchunks,
                                             const int* __restrict__ act, double* __restrict__ dotp, int bx, int by,
                                             int bz, int gx, int gy) {
   if (act && !act[bz / nchunks]) return;  // right-hand side already converged (uniform per block)
+  // kSmoothFirst: a sweep whose input is the first sweep from zero, u = (omega/D) f,
+  // formed on load from f and omega/D instead of read (ug unused)
+  constexpr bool FIRST = MODE == kSmoothFirst;
   {  // bz = z-chunk + nchunks * right-hand side; vectors are [nrhs][3 nn]
     const long long off = 3ll * L.nn * (bz / nchunks);
     ug += off;
@@ -193,6 +243,7 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
   const long long plane = (long long)L.nxn * L.nyn;
   const long long eplane = (long long)L.nx * L.ny;
   const int vbytes = (int)(3 * plane * (long long)sizeof(T));   // one plane of a nodal vector
+  const int ubytes = (int)(3 * plane * (long long)sizeof(TU));  // one plane of u
   const int ebytes = (int)(eplane * (long long)sizeof(T));      // one layer of moduli
   const int mbytes = (int)plane;                                 // one plane of support bits
 
@@ -205,13 +256,13 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
     const int jr = j0 + r;
     const int n = i + L.nxn * jr;
     const bool in = col_in && jr >= 0 && jr < L.nyn;
-    offu[r] = in ? n * (3 * (int)sizeof(T)) : kOutside;
+    offu[r] = in ? n * (3 * (int)sizeof(TU)) : kOutside;
     offm[r] = in ? n : kOutside;
     if (r < R) {
       offe[r] = (col_elem && jr >= 0 && jr < L.ny) ? (i + L.nx * jr) * (int)sizeof(T) : kOutside;
       const int rt = w * R + r;
       const bool out = lane_out && rt >= 1 && rt <= kOutRows && jr < L.nyn;
-      offo[r] = out ? offu[r] : kOutside;
+      offo[r] = out ? n * (3 * (int)sizeof(T)) : kOutside;
       offmo[r] = out ? n : kOutside;
     }
   }
@@ -221,17 +272,29 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
   // being processed.
   // Plane buffers alternate by parity (A holds the planes kc0-1, kc0+1, ...,
   // B the others), so the pipeline never copies a plane between registers.
-  T uA[R + 1][3], uB[R + 1][3], uo[R][3];
+  TU uA[R + 1][3], uB[R + 1][3];
+  T wA[FIRST ? R + 1 : 1][3], wB[FIRST ? R + 1 : 1][3];  // omega/D of the input planes (FIRST)
+  T uo[R][3];
   int mA[R + 1], mB[R + 1];
   T EA[R], EB[R];
   __shared__ T xch[2][W][3][64];  // [parity][wave][xyz][lane]: node values for the next wave
   // Only planes kc0-1..kc1 and element layers kc0-1..kc1-1 are needed; the
   // pipeline's requests outside them are given empty resources (no traffic).
-  auto load_plane = [&](int kk, T (&u)[R + 1][3], int (&m)[R + 1]) {
+  auto load_plane = [&](int kk, TU (&u)[R + 1][3], T (&wv)[FIRST ? R + 1 : 1][3], int (&m)[R + 1]) {
     const bool pin = kk >= 0 && kk < L.nzn && kk <= kc1;
-    const Rsrc ru = plane_rsrc(ug + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
+    if constexpr (FIRST) {
+      const Rsrc ru = plane_rsrc(fg + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
+      const Rsrc rw = plane_rsrc(wg + 3 * plane * (pin ? kk : 0), pin ? vbytes : 0);
 #pragma unroll
-    for (int r = 0; r <= R; ++r) load3(ru, offu[r], u[r]);
+      for (int r = 0; r <= R; ++r) {
+        load3(ru, offu[r], u[r]);
+        load3(rw, offu[r], wv[r]);
+      }
+    } else {
+      const Rsrc ru = plane_rsrc(ug + 3 * plane * (pin ? kk : 0), pin ? ubytes : 0);
+#pragma unroll
+      for (int r = 0; r <= R; ++r) load3(ru, offu[r], u[r]);
+    }
     if (MASKIN) {
       const Rsrc rm = plane_rsrc(L.mask + plane * (pin ? kk : 0), pin ? mbytes : 0);
 #pragma unroll
@@ -283,7 +346,7 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
 #pragma unroll
       for (int r = 0; r < R; ++r) load3(rf, offo[r], fo[r]);
     }
-    if (MODE == kSmooth) {
+    if (MODE == kSmooth || FIRST) {
       const Rsrc rw = plane_rsrc(wg + 3 * po, out_plane ? vbytes : 0);
 #pragma unroll
       for (int r = 0; r < R; ++r) load3(rw, offo[r], wo[r]);
@@ -294,7 +357,8 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
   // kk-1 and the output of plane kk-1.
   // Fin/Tin: the previous plane's face modes and the previous layer's top-face
   // modes; Fout/Tout receive this plane's and this layer's.
-  auto body = [&](int kk, const T (&uc)[R + 1][3], const int (&mc)[R + 1], const T (&Ec)[R], const int (&mo)[R],
+  auto body = [&](int kk, const TU (&uc)[R + 1][3], const T (&wc)[FIRST ? R + 1 : 1][3], const int (&mc)[R + 1],
+                  const T (&Ec)[R], const int (&mo)[R],
                   const T (&fo)[R][3], const T (&wo)[R][3], const T (&Fin)[R][4][3], T (&Fout)[R][4][3],
                   const T (&Tin)[R][4][3], T (&Tout)[R][4][3]) {
     const bool out_plane = kk - 1 >= kc0 && kk - 1 < kc1;
@@ -305,10 +369,17 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
 #pragma unroll
     for (int r = 0; r <= R; ++r) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ue[r][c] = uc[r][c];
+      for (int c = 0; c < 3; ++c) ue[r][c] = T(uc[r][c]);
+      if constexpr (FIRST) {
+        // rounded on its own, as where the first sweep is stored: the product
+        // is not contracted into the additions that consume it
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ue[r][c] = wc[r][c] * ue[r][c];
+      }
       if (MASKIN && __any(mc[r] != 0)) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ue[r][c] = select_bit(mc[r], c, T(0), uc[r][c]);
+        for (int c = 0; c < 3; ++c) ue[r][c] = select_bit(mc[r], c, T(0), ue[r][c]);
       }
     }
     // x-edge modes of row r: s = u(i+1) + u(i), d = u(i+1) - u(i).  The
@@ -336,7 +407,7 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
         if (MODE == kApply) {
           v[c] = Au;
           if (DOT && out_plane && offo[r] != kOutside) dot += (double)uo[r][c] * (double)Au;
-        } else if (MODE == kSmooth) {
+        } else if (MODE == kSmooth || FIRST) {
           v[c] = uo[r][c] + wo[r][c] * (fo[r][c] - Au);
           if (DOT && out_plane && offo[r] != kOutside) dot += (double)fo[r][c] * (double)v[c];
         } else
@@ -444,7 +515,7 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) uo[r][c] = uc[r][c];
+      for (int c = 0; c < 3; ++c) uo[r][c] = FIRST ? ue[r][c] : T(uc[r][c]);
   };
 
   if constexpr (PRE > 0) {
@@ -452,11 +523,13 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
     // for a z-chunk of one plane): every input is requested before any
     // arithmetic, so the workgroup waits on memory once.
     constexpr int Z = PRE;
-    T up[Z + 2][R + 1][3], Ep[Z + 2][R];
+    TU up[Z + 2][R + 1][3];
+    T wp[Z + 2][FIRST ? R + 1 : 1][3];
+    T Ep[Z + 2][R];
     int mp[Z + 2][R + 1], mo[Z][R];
     T fo[Z][R][3], wo[Z][R][3];
 #pragma unroll
-    for (int t = 0; t < Z + 2; ++t) load_plane(kc0 - 1 + t, up[t], mp[t]);
+    for (int t = 0; t < Z + 2; ++t) load_plane(kc0 - 1 + t, up[t], wp[t], mp[t]);
 #pragma unroll
     for (int r = 0; r < R; ++r) Ep[0][r] = T(0);
 #pragma unroll
@@ -468,33 +541,33 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
       const int kk = kc0 - 1 + t, o = t >= 2 ? t - 2 : 0;
       if (kk <= kc1) {
         if (t & 1)
-          body(kk, up[t], mp[t], Ep[t], mo[o], fo[o], wo[o], FpB, FpA, TpB, TpA);
+          body(kk, up[t], wp[t], mp[t], Ep[t], mo[o], fo[o], wo[o], FpB, FpA, TpB, TpA);
         else
-          body(kk, up[t], mp[t], Ep[t], mo[o], fo[o], wo[o], FpA, FpB, TpA, TpB);
+          body(kk, up[t], wp[t], mp[t], Ep[t], mo[o], fo[o], wo[o], FpA, FpB, TpA, TpB);
       }
     }
   } else {
     // two planes per trip: A is processed while B's plane is requested, then
     // the other way round
-    load_plane(kc0 - 1, uA, mA);
+    load_plane(kc0 - 1, uA, wA, mA);
     load_layer(kc0 - 2, EA);
     for (int kk = kc0 - 1; kk <= kc1; kk += 2) {
       {
-        load_plane(kk + 1, uB, mB);
+        load_plane(kk + 1, uB, wB, mB);
         load_layer(kk, EB);
         int mo[R];
         T fo[R][3], wo[R][3];
         load_out(kk, mo, fo, wo);
-        body(kk, uA, mA, EA, mo, fo, wo, FpA, FpB, TpA, TpB);
+        body(kk, uA, wA, mA, EA, mo, fo, wo, FpA, FpB, TpA, TpB);
       }
       if (kk + 1 > kc1) break;
       {
-        load_plane(kk + 2, uA, mA);
+        load_plane(kk + 2, uA, wA, mA);
         load_layer(kk + 1, EA);
         int mo[R];
         T fo[R][3], wo[R][3];
         load_out(kk + 1, mo, fo, wo);
-        body(kk + 1, uB, mB, EB, mo, fo, wo, FpB, FpA, TpB, TpA);
+        body(kk + 1, uB, wB, mB, EB, mo, fo, wo, FpB, FpA, TpB, TpA);
       }
     }
   }
@@ -515,27 +588,33 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
   }
 }
 
-template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT>
+template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT, typename TU = T>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
-                                                      const T* __restrict__ ug, const T* __restrict__ fg,
+                                                      const TU* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
                                                       int nchunks, const int* __restrict__ act,
                                                       double* __restrict__ dotp) {
-  stream_tile<T, MODE, R, W, MASKIN, PRE, DOT>(L, q, Eg, ug, fg, wg, yg, zchunk, nchunks, act, dotp, blockIdx.x,
-                                               blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
+  stream_tile<T, MODE, R, W, MASKIN, PRE, DOT, TU>(L, q, Eg, ug, fg, wg, yg, zchunk, nchunks, act, dotp, blockIdx.x,
+                                                   blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
 // Several grids in one launch: workgroup b belongs to the task t with
 // begin[t] <= b < begin[t + 1] and takes that task's tile b - begin[t] in the
 // order of its own launch grid (x fastest).
-template <typename T, int MODE, int R, int W, int MINW, int PRE, bool DOT>
+// TU = float (binary64 K p only): u is the task's binary32 u32.
+template <typename T, int MODE, int R, int W, int MINW, int PRE, bool DOT, typename TU = T>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream_batch(Batch<StreamTask<T>> tb, HaarCoef<T> q) {
   const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
   const StreamTask<T>& a = tb.a[t];
   const int local = (int)blockIdx.x - tb.begin[t];
   const int bx = local % a.gx, by = (local / a.gx) % a.gy, bz = local / (a.gx * a.gy);
-  stream_tile<T, MODE, R, W, false, PRE, DOT>(a.L, q, a.E, a.u, a.f, a.wd, a.y, a.zchunk, a.nchunks, a.act, a.dotp,
-                                              bx, by, bz, a.gx, a.gy);
+  const TU* u;
+  if constexpr (sizeof(TU) == sizeof(T))
+    u = a.u;
+  else
+    u = a.u32;
+  stream_tile<T, MODE, R, W, false, PRE, DOT, TU>(a.L, q, a.E, u, a.f, a.wd, a.y, a.zchunk, a.nchunks, a.act,
+                                                  a.dotp, bx, by, bz, a.gx, a.gy);
 }
 
 template <typename T, int R, int W, int MINW, bool MASKIN, int PRE>
@@ -582,6 +661,53 @@ void launch_stream_impl(int mode, bool maskin, const Level& L, const HaarCoef<T>
                                                 s, t);
 }
 
+
+// binary64 K u on binary32 input (the search direction of the mixed solver)
+template <int R, int W, int MINW>
+void launch_apply_u32_impl(const Level& L, const HaarCoef<double>& q, const double* E, const float* u, double* y,
+                           int zchunk, int nrhs, const int* act, double* dotp, hipStream_t s, const LaunchTimer& t) {
+  constexpr int kOutRows = W * R - 1;
+  const int nchunks = (L.nzn + zchunk - 1) / zchunk;
+  dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
+  dim3 block(64 * W);
+  const double* none = nullptr;
+  if (zchunk == 1 && dotp)
+    launch_timed(k_stream<double, kApply, R, W, MINW, false, 1, true, float>, grid, block, s, t, L, q, E, u, none,
+                 none, y, zchunk, nchunks, act, dotp);
+  else if (zchunk == 1)
+    launch_timed(k_stream<double, kApply, R, W, MINW, false, 1, false, float>, grid, block, s, t, L, q, E, u, none,
+                 none, y, zchunk, nchunks, act, (double*)nullptr);
+  else if (dotp)
+    launch_timed(k_stream<double, kApply, R, W, MINW, false, 0, true, float>, grid, block, s, t, L, q, E, u, none,
+                 none, y, zchunk, nchunks, act, dotp);
+  else
+    launch_timed(k_stream<double, kApply, R, W, MINW, false, 0, false, float>, grid, block, s, t, L, q, E, u, none,
+                 none, y, zchunk, nchunks, act, (double*)nullptr);
+}
+
+// The sweep on the first sweep from zero (kSmoothFirst), one launch or a batch.
+template <typename T, int R, int W, int MINW>
+void launch_first_impl(const Level& L, const HaarCoef<T>& q, const T* E, const T* f, const T* wd, T* y, int zchunk,
+                       int nrhs, const int* act, hipStream_t s, const LaunchTimer& t) {
+  constexpr int kOutRows = W * R - 1;
+  const int nchunks = (L.nzn + zchunk - 1) / zchunk;
+  dim3 grid((L.nxn + 61) / 62, (L.nyn + kOutRows - 1) / kOutRows, nchunks * nrhs);
+  dim3 block(64 * W);
+  const T* none = nullptr;
+  if (zchunk == 1)
+    launch_timed(k_stream<T, kSmoothFirst, R, W, MINW, false, 1, false>, grid, block, s, t, L, q, E, none, f, wd, y,
+                 zchunk, nchunks, act, (double*)nullptr);
+  else
+    launch_timed(k_stream<T, kSmoothFirst, R, W, MINW, false, 0, false>, grid, block, s, t, L, q, E, none, f, wd, y,
+                 zchunk, nchunks, act, (double*)nullptr);
+}
+template <typename T, int R, int W, int MINW>
+void launch_first_batch_impl(bool pre, const Batch<StreamTask<T>>& b, const HaarCoef<T>& q, hipStream_t s) {
+  const dim3 grid(b.begin[b.n]), block(64 * W);
+  if (pre) k_stream_batch<T, kSmoothFirst, R, W, MINW, 1, false><<<grid, block, 0, s>>>(b, q);
+  else k_stream_batch<T, kSmoothFirst, R, W, MINW, 0, false><<<grid, block, 0, s>>>(b, q);
+}
+
 }  // namespace
 
 // Shapes (rows per thread R, waves per workgroup W, minimum waves per SIMD the
@@ -598,10 +724,26 @@ int stream_out_rows(bool f32, int shape) {
   return f32 ? r32[shape] : r64[shape];
 }
 
+// Shapes with a kSmoothFirst form: the one-row tiles and binary32's 2x4 (which
+// holds omega/D of its input planes in three waves per SIMD's registers); the
+// taller tiles would spill.
+bool first_shape_ok(bool f32, int shape) { return f32 ? (shape == 0 || shape == 5 || shape == 6) : shape != 1; }
+
 template <typename T>
 void launch_stream(int mode, bool maskin, int shape, const Level& L, const HaarCoef<T>& q, const T* E, const T* u,
                    const T* f, const T* wd, T* y, int zchunk, int nrhs, const int* act, hipStream_t s,
                    const LaunchTimer& t, double* dotp) {
+  if (mode == kSmoothFirst) {  // the caller checked first_shape_ok; no input masking, no partials
+    if constexpr (sizeof(T) == 4) {
+      if (shape == 0) launch_first_impl<T, 2, 4, 3>(L, q, E, f, wd, y, zchunk, nrhs, act, s, t);
+      else if (shape == 5) launch_first_impl<T, 1, 8, 2>(L, q, E, f, wd, y, zchunk, nrhs, act, s, t);
+      else launch_first_impl<T, 1, 4, 2>(L, q, E, f, wd, y, zchunk, nrhs, act, s, t);
+    } else {
+      if (shape == 0) launch_first_impl<T, 1, 8, 2>(L, q, E, f, wd, y, zchunk, nrhs, act, s, t);
+      else launch_first_impl<T, 1, 4, 2>(L, q, E, f, wd, y, zchunk, nrhs, act, s, t);
+    }
+    return;
+  }
   if constexpr (sizeof(T) == 4) {
     if (shape == 0)
       launch_stream_impl<T, 2, 4, 2>(mode, maskin, L, q, E, u, f, wd, y, zchunk, nrhs, act, dotp, s, t);
@@ -633,7 +775,36 @@ template void launch_stream<double>(int, bool, int, const Level&, const HaarCoef
                                     const double*, const double*, const double*, double*, int, int, const int*,
                                     hipStream_t, const LaunchTimer&, double*);
 
+void launch_sensitivity_haar(const Level& L, const HaarCoef<double>& q, const double* rho, const double* u,
+                             double coef, double pm1, int accumulate, double* dc, hipStream_t s) {
+  k_sensitivity_haar<<<(L.ne + 255) / 256, 256, 0, s>>>(L, q, rho, u, coef, pm1, accumulate, dc);
+}
+
+void launch_apply_u32(int shape, const Level& L, const HaarCoef<double>& q, const double* E, const float* u,
+                      double* y, int zchunk, int nrhs, const int* act, hipStream_t s, const LaunchTimer& t,
+                      double* dotp) {
+  // the binary32 input leaves the one-row, four-wave tile room for three
+  // waves per SIMD without spilling
+  if (shape == 0)
+    launch_apply_u32_impl<1, 8, 2>(L, q, E, u, y, zchunk, nrhs, act, dotp, s, t);
+  else if (shape == 1)
+    launch_apply_u32_impl<2, 4, 1>(L, q, E, u, y, zchunk, nrhs, act, dotp, s, t);
+  else
+    launch_apply_u32_impl<1, 4, 3>(L, q, E, u, y, zchunk, nrhs, act, dotp, s, t);
+}
+
 namespace {
+// binary64 K u of the tasks' binary32 u32
+template <int R, int W, int MINW>
+void launch_stream_batch_u32(bool pre, bool dot, const Batch<StreamTask<double>>& b, const HaarCoef<double>& q,
+                             hipStream_t s) {
+  const dim3 grid(b.begin[b.n]), block(64 * W);
+  if (pre && dot) k_stream_batch<double, kApply, R, W, MINW, 1, true, float><<<grid, block, 0, s>>>(b, q);
+  else if (pre) k_stream_batch<double, kApply, R, W, MINW, 1, false, float><<<grid, block, 0, s>>>(b, q);
+  else if (dot) k_stream_batch<double, kApply, R, W, MINW, 0, true, float><<<grid, block, 0, s>>>(b, q);
+  else k_stream_batch<double, kApply, R, W, MINW, 0, false, float><<<grid, block, 0, s>>>(b, q);
+}
+
 template <typename T, int R, int W, int MINW>
 void launch_stream_batch_impl(int mode, bool pre, bool dot, const Batch<StreamTask<T>>& b, const HaarCoef<T>& q,
                               hipStream_t s) {
@@ -657,7 +828,18 @@ void launch_stream_batch_impl(int mode, bool pre, bool dot, const Batch<StreamTa
 
 template <typename T>
 void launch_stream_batch(int mode, int shape, bool pre, bool dot, const Batch<StreamTask<T>>& b,
-                         const HaarCoef<T>& q, hipStream_t s) {
+                         const HaarCoef<T>& q, hipStream_t s, bool u32in) {
+  if (mode == kSmoothFirst) {  // shapes of launch_stream's kSmoothFirst
+    if constexpr (sizeof(T) == 4) {
+      if (shape == 0) launch_first_batch_impl<T, 2, 4, 3>(pre, b, q, s);
+      else if (shape == 5) launch_first_batch_impl<T, 1, 8, 2>(pre, b, q, s);
+      else launch_first_batch_impl<T, 1, 4, 2>(pre, b, q, s);
+    } else {
+      if (shape == 0) launch_first_batch_impl<T, 1, 8, 2>(pre, b, q, s);
+      else launch_first_batch_impl<T, 1, 4, 2>(pre, b, q, s);
+    }
+    return;
+  }
   if constexpr (sizeof(T) == 4) {
     if (shape == 0) launch_stream_batch_impl<T, 2, 4, 2>(mode, pre, dot, b, q, s);
     else if (shape == 1) launch_stream_batch_impl<T, 3, 4, 2>(mode, pre, dot, b, q, s);
@@ -666,6 +848,10 @@ void launch_stream_batch(int mode, int shape, bool pre, bool dot, const Batch<St
     else if (shape == 4) launch_stream_batch_impl<T, 2, 8, 1>(mode, pre, dot, b, q, s);
     else if (shape == 5) launch_stream_batch_impl<T, 1, 8, 2>(mode, pre, dot, b, q, s);
     else launch_stream_batch_impl<T, 1, 4, 2>(mode, pre, dot, b, q, s);
+  } else if (u32in) {  // the shapes of launch_apply_u32
+    if (shape == 0) launch_stream_batch_u32<1, 8, 2>(pre, dot, b, q, s);
+    else if (shape == 1) launch_stream_batch_u32<2, 4, 1>(pre, dot, b, q, s);
+    else launch_stream_batch_u32<1, 4, 3>(pre, dot, b, q, s);
   } else {
     if (shape == 0) launch_stream_batch_impl<T, 1, 8, 2>(mode, pre, dot, b, q, s);
     else if (shape == 1) launch_stream_batch_impl<T, 2, 4, 1>(mode, pre, dot, b, q, s);
@@ -673,9 +859,9 @@ void launch_stream_batch(int mode, int shape, bool pre, bool dot, const Batch<St
   }
 }
 template void launch_stream_batch<float>(int, int, bool, bool, const Batch<StreamTask<float>>&,
-                                         const HaarCoef<float>&, hipStream_t);
+                                         const HaarCoef<float>&, hipStream_t, bool);
 template void launch_stream_batch<double>(int, int, bool, bool, const Batch<StreamTask<double>>&,
-                                          const HaarCoef<double>&, hipStream_t);
+                                          const HaarCoef<double>&, hipStream_t, bool);
 
 void stream_grid(const Level& L, bool f32, int shape, int zchunk, int* gx, int* gy, int* nchunks) {
   const int rows = stream_out_rows(f32, shape);

@@ -45,6 +45,7 @@ class GridDesc(ctypes.Structure):
         ("omega", ctypes.c_double), ("coarse_avg", ctypes.c_int), ("max_nrhs", ctypes.c_int),
         ("kernel", ctypes.c_int), ("fixed_mask", ctypes.c_void_p), ("coarse_op", ctypes.c_int),
         ("vcycle_both", ctypes.c_int), ("rr_every", ctypes.c_int), ("stencil_storage", ctypes.c_int),
+        ("fuse_first", ctypes.c_int),
     ]
 
 

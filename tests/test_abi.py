@@ -29,6 +29,7 @@ def test_element_matrix_matches_oracle(nu):
 def test_descriptor_validation():
     d = hexmg.default_desc(32, 16, 16, 3)
     assert d.E0 == 1.0 and d.Emin == 1e-9 and d.nu == 0.3 and d.penal == 3.0
+    assert d.fuse_first == 1 and d.rr_every == 8 and d.smooth_sweeps == 2
     assert hexmg.workspace_size(d) > 0
     bad = [
         dict(nx=33),          # not divisible by 2^(levels-1)
@@ -39,6 +40,7 @@ def test_descriptor_validation():
         dict(smooth_sweeps=0),
         dict(precision=7),
         dict(coarse_avg=3),
+        dict(fuse_first=2),
     ]
     for kw in bad:
         d = hexmg.default_desc(32, 16, 16, 3)

@@ -480,3 +480,42 @@ def test_every_stream_shape(dtype_name, shape, zchunk):
     z = torch.empty_like(y)
     grid.vcycle(gpu(r.astype(npdt)), z)
     assert rel(z.cpu().numpy(), h.vcycle(r)) < (1e-4 if dt == hexmg.F32 else 1e-10)
+
+
+@pytest.mark.parametrize("precision,dtype_name,shape,zchunk", [
+    ("mixed", "f32", 0, 4), ("mixed", "f32", 5, 3), ("mixed", "f32", 6, 1), ("fp64", "f64", 0, 4),
+    ("fp64", "f64", 2, 1), ("mixed32", "f32", 0, 8)])
+def test_first_sweep_formed_on_load_bitwise(precision, dtype_name, shape, zchunk):
+    """The level-0 pre-smoothing whose second sweep forms the first sweep from
+    zero, (omega/D) r, as it loads its input (fuse_first = 1) gives the same
+    iterates, bit for bit, as the residual update writing that first sweep
+    (fuse_first = 0), for each tile shape that has the form, with ragged tiles
+    and z-chunks (including the preloaded one-plane form)."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case first sweep {precision} shape {shape} zchunk={zchunk}", flush=True)
+    _require_gpu()
+    dims, levels = (124, 24, 20), 3
+    g = W.Grid(*dims)
+    rho = W.random_field_density(g, seed=5, length_scale=4.0, lo=0.01)
+    f = gpu(W.cantilever_line_load(g))
+    prec = {"mixed": hexmg.MIXED, "fp64": hexmg.FP64, "mixed32": hexmg.MIXED32}[precision]
+    dt = hexmg.F32 if dtype_name == "f32" else hexmg.F64
+    out = []
+    for fuse in (1, 0):
+        grid = hexmg.Grid(*dims, levels, precision=prec, fuse_first=fuse)
+        grid.set_density(gpu(rho))
+        for l in range(levels):  # the same kernels on both grids (timed choices can differ)
+            for d in (hexmg.F32, hexmg.F64):
+                if l == 0 and d == dt:
+                    grid.set_kernel_choice(l, d, hexmg.KERNEL_STREAM, zchunk, shape)
+                else:
+                    grid.set_kernel_choice(l, d, hexmg.KERNEL_STREAM, 4, 0)
+        for d in (hexmg.F32, hexmg.F64):
+            grid.set_coarse_cycle(d, 0)
+        u = torch.zeros_like(f)
+        code, info = grid.solve(f, u, rtol=1e-7, maxit=60)
+        out.append((u.cpu().numpy(), info[0]["iterations"], info[0]["compliance"], code))
+    assert out[0][1] == out[1][1] and out[0][3] == out[1][3]
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][2] == out[1][2]
