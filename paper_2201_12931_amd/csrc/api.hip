@@ -909,8 +909,11 @@ int precondition(hexmg_grid* g, const double* r, double* z, double* rz_partials,
     if (!first_done) {
       const float* wd = g->wd32[0];
       float* t32 = g->vt32[0];
-      emit_launch(g, st_down(0, 0), s,
-                  [=](hipStream_t st) { launch_jacobi_first_from64(N, wd, r, f32, t32, nrhs, act, st); });
+      if (first_fused<float>(g))  // the second sweep forms the first: only the binary32 copy of r
+        emit_launch(g, st_down(0, 0), s, [=](hipStream_t st) { launch_f64_to_f32(N, r, f32, nrhs, act, st); });
+      else
+        emit_launch(g, st_down(0, 0), s,
+                    [=](hipStream_t st) { launch_jacobi_first_from64(N, wd, r, f32, t32, nrhs, act, st); });
     }
     vcycle_level<float>(g, v, 0, f32, u32, nrhs, act, s, true, false,
                         nd ? parts_target(g, nd, rz_partials) : nullptr);
