@@ -318,7 +318,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 V-cycle and K p, f64 CG" if args.precision == "mixed32" else "f32 V-cycle, f64 K p and CG",
+        "dtype": ("f32 V-cycle and K p, f64 CG" if args.precision == "mixed32"
+                  else "f32 V-cycle and search direction, f64 K p arithmetic and CG"),
         "data": "synthetic",
         "config": {
             "workload": args.workload,
