@@ -519,3 +519,37 @@ def test_first_sweep_formed_on_load_bitwise(precision, dtype_name, shape, zchunk
     assert out[0][1] == out[1][1] and out[0][3] == out[1][3]
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][2] == out[1][2]
+
+
+@pytest.mark.parametrize("shape,zchunk", [(0, 4), (1, 3), (2, 8), (2, 1)])
+def test_binary64_product_on_binary32_direction_every_shape(shape, zchunk):
+    """The mixed form's binary64 K p reads the binary32 search direction with
+    its own kernels (one per tile shape): with the level-0 binary64 choice
+    forced to each streaming shape and z-chunk, a fixed number of CG
+    iterations gives the iterate of the node-gather kernel, which reads the
+    same binary32 direction (binary64 sums in another order; the tolerance
+    leaves room for a residual entry that then rounds to the other binary32
+    neighbour on its way into the V-cycle)."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case binary64 K p on binary32 direction shape {shape} zchunk={zchunk}", flush=True)
+    _require_gpu()
+    dims, levels = (124, 24, 20), 3
+    g = W.Grid(*dims)
+    rho = W.random_field_density(g, seed=6, length_scale=4.0, lo=0.01)
+    f = gpu(W.cantilever_line_load(g))
+    out = []
+    for kern in (hexmg.KERNEL_STREAM, hexmg.KERNEL_GATHER):
+        grid = hexmg.Grid(*dims, levels, precision=hexmg.MIXED)
+        grid.set_density(gpu(rho))
+        for l in range(levels):
+            grid.set_kernel_choice(l, hexmg.F32, hexmg.KERNEL_STREAM, 4, 0)
+        if kern == hexmg.KERNEL_STREAM:
+            grid.set_kernel_choice(0, hexmg.F64, kern, zchunk, shape)
+        else:
+            grid.set_kernel_choice(0, hexmg.F64, kern)
+        grid.set_coarse_cycle(hexmg.F32, 0)
+        u = torch.zeros_like(f)
+        grid.solve(f, u, rtol=0.0, maxit=8)
+        out.append(u.cpu().numpy())
+    assert rel(out[0], out[1]) < 1e-9
