@@ -588,26 +588,55 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
   }
 }
 
+// Tile (bx, by) of the workgroup with index l in its z-slab of gx * gy tiles,
+// whose first workgroup has linear id `first` in the launch.  The eight XCDs,
+// each with its own L2, take workgroups round-robin by linear id; the slab's
+// tiles (row-major) are cut into eight contiguous bands and XCD c takes band
+// c, so the tiles whose halo rows and columns overlap run on one L2, while the
+// chip as a whole still moves through the grid one z-slab after the other.
+// A bijection on the slab's tiles: every tile is computed once, by the same
+// arithmetic, and keeps its partial's slot.
+__device__ inline void xcd_band_tile(int gx, int gy, int l, long long first, int& bx, int& by) {
+  const int T = gx * gy;
+  const int r0 = (int)(first & 7);  // XCD of the slab's first workgroup
+  const int c = (r0 + l) & 7;       // XCD of this workgroup
+  const int q = T >> 3, rem = T & 7;
+  // XCD k takes the slab's indices l = ((k - r0) & 7) + 8 j: q + 1 of them
+  // where (k - r0) & 7 < rem, else q; band c starts after the bands of XCDs
+  // 0..c-1
+  int start = c * q;
+  for (int k = 0; k < c; ++k) start += ((k - r0) & 7) < rem;
+  const int t = start + (l >> 3);
+  bx = t % gx;
+  by = t / gx;
+}
+
 template <typename T, int MODE, int R, int W, int MINW, bool MASKIN, int PRE, bool DOT, typename TU = T>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream(Level L, HaarCoef<T> q, const T* __restrict__ Eg,
                                                       const TU* __restrict__ ug, const T* __restrict__ fg,
                                                       const T* __restrict__ wg, T* __restrict__ yg, int zchunk,
                                                       int nchunks, const int* __restrict__ act,
                                                       double* __restrict__ dotp) {
-  stream_tile<T, MODE, R, W, MASKIN, PRE, DOT, TU>(L, q, Eg, ug, fg, wg, yg, zchunk, nchunks, act, dotp, blockIdx.x,
-                                                   blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
+  int bx, by;
+  xcd_band_tile(gridDim.x, gridDim.y, (int)blockIdx.x + (int)gridDim.x * (int)blockIdx.y,
+                (long long)gridDim.x * gridDim.y * blockIdx.z, bx, by);
+  stream_tile<T, MODE, R, W, MASKIN, PRE, DOT, TU>(L, q, Eg, ug, fg, wg, yg, zchunk, nchunks, act, dotp, bx, by,
+                                                   blockIdx.z, gridDim.x, gridDim.y);
 }
 
 // Several grids in one launch: workgroup b belongs to the task t with
-// begin[t] <= b < begin[t + 1] and takes that task's tile b - begin[t] in the
-// order of its own launch grid (x fastest).
+// begin[t] <= b < begin[t + 1]; b - begin[t] counts the task's workgroups z-slab
+// by z-slab, and inside a slab the tiles go to the XCDs in bands as in
+// k_stream.
 // TU = float (binary64 K p only): u is the task's binary32 u32.
 template <typename T, int MODE, int R, int W, int MINW, int PRE, bool DOT, typename TU = T>
 __global__ __launch_bounds__(64 * W, MINW) void k_stream_batch(Batch<StreamTask<T>> tb, HaarCoef<T> q) {
   const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
   const StreamTask<T>& a = tb.a[t];
   const int local = (int)blockIdx.x - tb.begin[t];
-  const int bx = local % a.gx, by = (local / a.gx) % a.gy, bz = local / (a.gx * a.gy);
+  const int bz = local / (a.gx * a.gy), l = local - bz * (a.gx * a.gy);
+  int bx, by;
+  xcd_band_tile(a.gx, a.gy, l, (long long)blockIdx.x - l, bx, by);
   const TU* u;
   if constexpr (sizeof(TU) == sizeof(T))
     u = a.u;
