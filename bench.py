@@ -60,9 +60,10 @@ def apply_bytes(g, word) -> float:
 # known size), keyed by workload, kernel family, kernel choice and a digest of
 # the kernel source they were taken on: any change to the kernel voids them.
 TRAFFIC = {
-    # level-0 binary32 Jacobi sweep, 768x384x384, 2 rows x 4 waves, z-chunk 4
-    # (profiles/stream_smooth_f32_L0_cantilever_768x384x384_rf_traffic.md)
-    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "8353785f36e9b8a0"): 9094580928.0,
+    # level-0 binary32 Jacobi sweep, 768x384x384, 2 rows x 4 waves, z-chunks 8
+    # and 4 (profiles/stream_smooth_f32_L0_cantilever_768x384x384_rf_traffic.md)
+    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 8, 0, "97d12e9dcf2505f5"): 6409816576.0,
+    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "97d12e9dcf2505f5"): 6496456294.4,
 }
 
 
