@@ -4,6 +4,8 @@
 // bits per node.  Every reduction is a fixed-shape two-stage tree (kReduceBlocks
 // partial sums, then one block in a fixed order) so results are reproducible
 // run to run; no floating-point atomics are used anywhere.
+#include <algorithm>
+
 #include "hexmg_impl.h"
 #include "node_ops.h"
 
@@ -104,6 +106,29 @@ __global__ void k_jacobi_first_from64(long long n, const float* __restrict__ wdi
   }
 }
 
+// Block order for the eight XCDs, each with its own L2, which take a launch's
+// workgroups round-robin by linear id.  The launch's n blocks (x dimension)
+// are cut into slabs of `slab` consecutive blocks, and inside a slab XCD c takes
+// the c-th contiguous band; with a slab of about one plane of the grid, the
+// blocks that read the same rows of the other level run on one L2, and the
+// next slab's band (the next plane) re-reads rows the same L2 has just held.
+// A bijection on each slab's blocks: only the order changes.
+__device__ inline int xcd_band_block(int slab) {
+  const int n = (int)gridDim.x, b = (int)blockIdx.x;
+  const int s0 = b - b % slab;
+  const int T = min(slab, n - s0), l = b - s0;
+  const int r0 = (int)(((long long)n * blockIdx.y + s0) & 7);  // XCD of the slab's first block
+  const int c = (r0 + l) & 7;                                  // XCD of this block
+  const int q = T >> 3, rem = T & 7;
+  // XCD k takes the slab's blocks l = ((k - r0) & 7) + 8 j: q + 1 of them where
+  // (k - r0) & 7 < rem, else q; band c starts after the bands of XCDs 0..c-1
+  int start = c * q;
+  for (int k = 0; k < c; ++k) start += ((k - r0) & 7) < rem;
+  return s0 + start + (l >> 3);
+}
+// A slab of about one plane of `per_plane` blocks, a multiple of 8.
+inline int band_slab(long long per_plane) { return (int)std::max<long long>(8, (per_plane + 7) / 8 * 8); }
+
 // Coarse right-hand side f_c = M_c P^T r (see restrict_node); with wdc set,
 // also the coarse level's first Jacobi sweep from zero, tc = wdc * f_c.
 // (bx, rhs): the workgroup's place in a launch of (ceil(C.nn / kBlock), nrhs).
@@ -117,8 +142,8 @@ __device__ __forceinline__ void restrict_block(const Level& F, const Level& C, c
 }
 template <typename T>
 __global__ void k_restrict(Level F, Level C, const T* __restrict__ r, T* __restrict__ fc,
-                           const int* __restrict__ act, const T* __restrict__ wdc, T* __restrict__ tc) {
-  restrict_block<T>(F, C, r, fc, act, wdc, tc, blockIdx.x, blockIdx.y);
+                           const int* __restrict__ act, const T* __restrict__ wdc, T* __restrict__ tc, int slab) {
+  restrict_block<T>(F, C, r, fc, act, wdc, tc, xcd_band_block(slab), blockIdx.y);
 }
 template <typename T>
 __global__ void k_restrict_batch(Batch<RestrictTask<T>> tb) {
@@ -200,8 +225,8 @@ __device__ __forceinline__ void prolong_block(const Level& F, const Level& C, co
 }
 template <typename T>
 __global__ void k_prolong_add(Level F, Level C, const T* __restrict__ ec, T* __restrict__ u,
-                              const int* __restrict__ act) {
-  prolong_block<T>(F, C, ec, u, act, blockIdx.x, blockIdx.y);
+                              const int* __restrict__ act, int slab) {
+  prolong_block<T>(F, C, ec, u, act, xcd_band_block(slab), blockIdx.y);
 }
 template <typename T>
 __global__ void k_prolong_add_batch(Batch<ProlongTask<T>> tb) {
@@ -1234,7 +1259,9 @@ void launch_jacobi_first_from64(long long n, const float* wdinv, const double* r
 template <typename T>
 void launch_restrict(const Level& F, const Level& C, const T* r, T* fc, int nrhs, const int* act, hipStream_t s,
                      const T* wdc, T* tc) {
-  k_restrict<T><<<dim3(blocks_for(C.nn), nrhs), kBlock, 0, s>>>(F, C, r, fc, act, wdc, tc);
+  // a slab: the blocks of one coarse plane
+  const int slab = band_slab(((long long)C.nxn * C.nyn + kBlock - 1) / kBlock);
+  k_restrict<T><<<dim3(blocks_for(C.nn), nrhs), kBlock, 0, s>>>(F, C, r, fc, act, wdc, tc, slab);
 }
 template void launch_restrict<double>(const Level&, const Level&, const double*, double*, int, const int*,
                                       hipStream_t, const double*, double*);
@@ -1244,7 +1271,9 @@ template void launch_restrict<float>(const Level&, const Level&, const float*, f
 template <typename T>
 void launch_prolong_add(const Level& F, const Level& C, const T* ec, T* u, int nrhs, const int* act,
                         hipStream_t s) {
-  k_prolong_add<T><<<dim3(prolong_blocks(F), nrhs), kBlock, 0, s>>>(F, C, ec, u, act);
+  // a slab: the blocks of the row quads of one pair of fine planes
+  const int slab = band_slab((long long)((F.nxn + 63) / 64) * ((((F.nyn + 1) / 2) + 3) / 4));
+  k_prolong_add<T><<<dim3(prolong_blocks(F), nrhs), kBlock, 0, s>>>(F, C, ec, u, act, slab);
 }
 template void launch_prolong_add<double>(const Level&, const Level&, const double*, double*, int, const int*,
                                          hipStream_t);
