@@ -62,8 +62,8 @@ def apply_bytes(g, word) -> float:
 TRAFFIC = {
     # level-0 binary32 Jacobi sweep, 768x384x384, 2 rows x 4 waves, z-chunks 8
     # and 4 (profiles/stream_smooth_f32_L0_cantilever_768x384x384_rf_traffic.md)
-    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 8, 0, "97d12e9dcf2505f5"): 6409816576.0,
-    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "97d12e9dcf2505f5"): 6496456294.4,
+    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 8, 0, "dfc1f4b9e31fd384"): 6410424012.8,
+    ("cantilever_768x384x384_rf", "smooth_f32", "stream", 4, 0, "dfc1f4b9e31fd384"): 6496693145.6,
 }
 
 

@@ -110,6 +110,24 @@ __device__ inline int batch_task(const int* begin, int n, int b) {
   }
   return lo;
 }
+
+// Work order for the eight XCDs, each with its own L2, which take a launch's
+// workgroups round-robin by linear id.  For the workgroup with index l in a
+// range of T consecutive workgroups whose first has linear id `first`, the
+// item of the range it takes: the range is cut into eight contiguous bands and
+// XCD c takes band c, so items that read overlapping data run on one L2.  A
+// bijection on [0, T): only the order of the items changes.
+__device__ inline int xcd_band_index(int l, int T, long long first) {
+  const int r0 = (int)(first & 7);  // XCD of the range's first workgroup
+  const int c = (r0 + l) & 7;       // XCD of this workgroup
+  const int q = T >> 3, rem = T & 7;
+  // XCD k takes the range's workgroups l = ((k - r0) & 7) + 8 j: q + 1 of them
+  // where (k - r0) & 7 < rem, else q; band c starts after the bands of XCDs
+  // 0..c-1
+  int start = c * q;
+  for (int k = 0; k < c; ++k) start += ((k - r0) & 7) < rem;
+  return start + (l >> 3);
+}
 template <typename T>
 struct StreamTask {
   Level L;

@@ -106,25 +106,15 @@ __global__ void k_jacobi_first_from64(long long n, const float* __restrict__ wdi
   }
 }
 
-// Block order for the eight XCDs, each with its own L2, which take a launch's
-// workgroups round-robin by linear id.  The launch's n blocks (x dimension)
-// are cut into slabs of `slab` consecutive blocks, and inside a slab XCD c takes
-// the c-th contiguous band; with a slab of about one plane of the grid, the
-// blocks that read the same rows of the other level run on one L2, and the
-// next slab's band (the next plane) re-reads rows the same L2 has just held.
-// A bijection on each slab's blocks: only the order changes.
+// The launch's blocks (x dimension) in slabs of `slab` consecutive blocks,
+// each slab in XCD bands (xcd_band_index): with a slab of about one plane of
+// the grid, the blocks that read the same rows of the other level run on one
+// L2, and the next slab's band (the next plane) re-reads rows the same L2 has
+// just held.
 __device__ inline int xcd_band_block(int slab) {
   const int n = (int)gridDim.x, b = (int)blockIdx.x;
   const int s0 = b - b % slab;
-  const int T = min(slab, n - s0), l = b - s0;
-  const int r0 = (int)(((long long)n * blockIdx.y + s0) & 7);  // XCD of the slab's first block
-  const int c = (r0 + l) & 7;                                  // XCD of this block
-  const int q = T >> 3, rem = T & 7;
-  // XCD k takes the slab's blocks l = ((k - r0) & 7) + 8 j: q + 1 of them where
-  // (k - r0) & 7 < rem, else q; band c starts after the bands of XCDs 0..c-1
-  int start = c * q;
-  for (int k = 0; k < c; ++k) start += ((k - r0) & 7) < rem;
-  return s0 + start + (l >> 3);
+  return s0 + xcd_band_index(b - s0, min(slab, n - s0), (long long)n * blockIdx.y + s0);
 }
 // A slab of about one plane of `per_plane` blocks, a multiple of 8.
 inline int band_slab(long long per_plane) { return (int)std::max<long long>(8, (per_plane + 7) / 8 * 8); }

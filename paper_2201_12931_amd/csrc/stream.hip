@@ -589,24 +589,13 @@ __device__ __forceinline__ void stream_tile(const Level& L, const HaarCoef<T>& q
 }
 
 // Tile (bx, by) of the workgroup with index l in its z-slab of gx * gy tiles,
-// whose first workgroup has linear id `first` in the launch.  The eight XCDs,
-// each with its own L2, take workgroups round-robin by linear id; the slab's
-// tiles (row-major) are cut into eight contiguous bands and XCD c takes band
-// c, so the tiles whose halo rows and columns overlap run on one L2, while the
-// chip as a whole still moves through the grid one z-slab after the other.
-// A bijection on the slab's tiles: every tile is computed once, by the same
-// arithmetic, and keeps its partial's slot.
+// whose first workgroup has linear id `first` in the launch: XCD c takes the
+// c-th contiguous band (row-major) of every slab's tiles, so the tiles whose
+// halo rows and columns overlap run on one L2, while the chip as a whole still
+// moves through the grid one z-slab after the other.  Every tile is computed
+// once, by the same arithmetic, and keeps its partial's slot.
 __device__ inline void xcd_band_tile(int gx, int gy, int l, long long first, int& bx, int& by) {
-  const int T = gx * gy;
-  const int r0 = (int)(first & 7);  // XCD of the slab's first workgroup
-  const int c = (r0 + l) & 7;       // XCD of this workgroup
-  const int q = T >> 3, rem = T & 7;
-  // XCD k takes the slab's indices l = ((k - r0) & 7) + 8 j: q + 1 of them
-  // where (k - r0) & 7 < rem, else q; band c starts after the bands of XCDs
-  // 0..c-1
-  int start = c * q;
-  for (int k = 0; k < c; ++k) start += ((k - r0) & 7) < rem;
-  const int t = start + (l >> 3);
+  const int t = xcd_band_index(l, gx * gy, first);
   bx = t % gx;
   by = t / gx;
 }
