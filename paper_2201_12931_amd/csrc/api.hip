@@ -309,6 +309,8 @@ size_t carve(hexmg_grid* g, char* base) {
   g->p = g->desc.precision != HEXMG_MIXED ? c.take<double>(N0 * R) : nullptr;
   g->q = c.take<double>(N0 * R);
   g->p32 = g->desc.precision != HEXMG_FP64 ? c.take<float>(N0 * R) : nullptr;
+  // the mixed form alternates its binary32 direction between two buffers
+  g->p32b = g->desc.precision == HEXMG_MIXED ? c.take<float>(N0 * R) : nullptr;
   g->q32 = g->desc.precision == HEXMG_MIXED32 ? c.take<float>(N0 * R) : nullptr;
   g->partials = c.take<double>((size_t)kMaxDotParts * R);  // >= kReduceBlocks
   {  // the most workgroups a level-0 streaming launch can have (z-chunk 1)
@@ -550,13 +552,12 @@ void gather(hexmg_grid* g, int mode, int level, const T* u, const T* f, const T*
   if (a && b) g->recs.push_back({family_of(mode, f32), a, b, g->prof_tag});
 }
 
-// y = A p32 at level 0 in binary64 on the binary32 search direction of the
+// y = A u at level 0 in binary64 on u, a binary32 search direction of the
 // mixed form (the level's binary64 K u choice; recorded as a batchable task
 // while the grid is batched).
-void apply_p32(hexmg_grid* g, double* y, int nrhs, hipStream_t s, const int* act, double* dotp) {
+void apply_p32(hexmg_grid* g, const float* u, double* y, int nrhs, hipStream_t s, const int* act, double* dotp) {
   const hexmg_grid::Choice ch = g->choice64[0][kApply];
   const Level L = g->lv[0];
-  const float* u = g->p32;
   const double* E = g->E64[0];
   const double* Ke = g->Ke64;
   const HaarCoef<double> q = *reinterpret_cast<const HaarCoef<double>*>(&g->hq64);
@@ -1302,6 +1303,8 @@ struct PcgRun {
   // iteration k (1-based): q = A p, alpha, the r update (its x update follows
   // in the next p update, or at the end), ||r||^2 and the test
   bool m32() const { return g->desc.precision == HEXMG_MIXED32; }
+  // the mixed form's binary32 direction of iteration k (odd: p32, even: p32b)
+  float* dir32(int k) const { return (k & 1) ? g->p32 : g->p32b; }
   int issue_iteration(int k) {
     double* sc = g->scalars;
     g->prof_tag = k - tag_off;
@@ -1319,7 +1322,7 @@ struct PcgRun {
     if (f32)
       gather<float>(g, kApply, 0, g->p32, nullptr, nullptr, g->q32, nb, s, false, g->active, pq_target);
     else if (!g->p)  // mixed form: binary64 product on the binary32 direction
-      apply_p32(g, g->q, nb, s, g->active, pq_target);
+      apply_p32(g, dir32(k), g->q, nb, s, g->active, pq_target);
     else
       gather<double>(g, kApply, 0, g->p, nullptr, nullptr, g->q, nb, s, false, g->active, pq_target);
     if (npq) npq = sum_big(g, npq, g->partials, nb, g->active, kStEnd + 205, s);
@@ -1327,7 +1330,8 @@ struct PcgRun {
       const long long n = N();
       const int b = nb;
       double *p = g->p, *q = g->q, *parts = g->partials;
-      float *q32 = g->q32, *p32 = g->p32;
+      float* q32 = g->q32;
+      const float* p32 = f32 ? g->p32 : dir32(k);
       const int* act = g->active;
       if (f32)
         emit_launch(g, kStEnd + 210, s, [=](hipStream_t st) { launch_dot_mixed(n, q32, p, parts, b, act, st); });
@@ -1407,13 +1411,13 @@ struct PcgRun {
   }
   template <typename TZ>
   void emit_update_px(int nrz, int parity, const TZ* z, float* p32) {
-    UpdatePxTask<TZ> task{N(), g->partials, nrz, parity, g->scalars, g->active, z, g->p, u, p32};
+    UpdatePxTask<TZ> task{N(), g->partials, nrz, parity, g->scalars, g->active, z, g->p, u, p32, g->p32b};
     const int b = nb;
     emit_task<UpdatePxTask<TZ>>(
         g, kStEnd + 100, s, batch_sig(kBkUpdatePx, sizeof(TZ)), task, kReduceBlocks * nb,
         [=](hipStream_t st) {
           launch_update_px<TZ>(task.n, task.rz_partials, task.nrz, task.sc, task.active, task.z, task.p, task.x,
-                               task.parity, b, st, task.p32);
+                               task.parity, b, st, task.p32, task.p32b);
         },
         [](const Batch<UpdatePxTask<TZ>>& bt, hipStream_t st) { launch_update_px_batch<TZ>(bt, st); });
   }
@@ -1528,10 +1532,10 @@ struct PcgRun {
     const int b = nb;
     const long long n = N();
     double *p = g->p, *x = u, *q = g->q, *pa = g->partials, *pb = g->partials2;
-    const float* p32 = g->p32;
+    const float *p32 = g->p32, *p32b = g->p32b;
     const double* ff = f;
     emit_launch(g, kStEnd + 600, s, [=](hipStream_t st) {
-      launch_flush_x(n, sc, p, x, b, st, nullptr, p32);  // the last iteration's x += alpha p
+      launch_flush_x(n, sc, p, x, b, st, nullptr, p32, p32b);  // the x updates still pending
     });
     {
       hipEvent_t e1 = t1;

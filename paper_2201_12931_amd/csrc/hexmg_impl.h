@@ -211,6 +211,7 @@ struct UpdatePxTask {
   double* p;
   double* x;
   float* p32;
+  float* p32b;
 };
 template <typename T>
 void launch_restrict_batch(const Batch<RestrictTask<T>>& b, hipStream_t s);
@@ -334,15 +335,21 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
 // beta = rz_new / rz[parity]; x += alpha p (the previous iteration's);
 // p = z + beta p; rz[1-parity] = rz_new
 // (x += alpha p only while s[kXPend]; p32, may be null: binary32 copy of the
-// new p; with p null the direction lives in p32 alone, read widened and
-// written rounded to binary32)
+// new p).  With p null the direction is binary32 alone, read widened and
+// written rounded: the direction of iteration k lives in p32 when k is odd
+// and in p32b when k is even, and x is brought up to date only after the even
+// iterations, by the two directions then pending (x += alpha_(k-1) p_(k-1),
+// then x += alpha_k p_k, the order and rounding of one update per iteration).
 template <typename TZ>
 void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
-                      double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32 = nullptr);
+                      double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32 = nullptr,
+                      float* p32b = nullptr);
 // x += alpha p for the right-hand sides where it is still due (s[kXPend]);
-// with p null, the binary32 direction p32
+// with p null, the binary32 directions still pending after the right-hand
+// side's last iteration k = s[kIts]: p_k (in p32 for odd k), and for even k
+// also p_(k-1), in the order of launch_update_px
 void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s,
-                    const int* act = nullptr, const float* p32 = nullptr);
+                    const int* act = nullptr, const float* p32 = nullptr, const float* p32b = nullptr);
 // partials of r . (double) u32 (the binary32 V-cycle output, not widened in memory)
 void launch_dot_mixed(long long n, const float* u32, const double* r, double* partials, int nrhs, const int* act,
                       hipStream_t s);
@@ -447,6 +454,7 @@ enum ScalarSlot {
   kTmp = 11,
   kTmp2 = 12,
   kXPend = 13,   // 1 while the last iteration's x += alpha p has not been applied
+  kAlphaP = 14,  // alpha of the last odd iteration (14) and even one (15); 0 after a breakdown
   kScalars = 16
 };
 
@@ -501,9 +509,10 @@ struct hexmg_grid {
   // PCG
   double *r, *z, *p, *q;
   // p: binary64 direction (null with HEXMG_MIXED, whose direction is p32 alone);
-  // p32: binary32 direction (HEXMG_MIXED) or binary32 copy of p (HEXMG_MIXED32);
-  // q32: binary32 A p of HEXMG_MIXED32
-  float *p32, *q32;
+  // p32: binary32 direction (HEXMG_MIXED: that of the odd iterations) or
+  // binary32 copy of p (HEXMG_MIXED32); p32b: the even iterations' direction
+  // (HEXMG_MIXED); q32: binary32 A p of HEXMG_MIXED32
+  float *p32, *p32b, *q32;
   double* partials;
   double* partials2;
   double* big_parts = nullptr;  // per-workgroup partials of level-0 launches beyond kMaxDotParts workgroups

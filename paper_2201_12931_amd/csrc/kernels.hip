@@ -835,6 +835,8 @@ __global__ void k_pcg_init(double rtol2, const double* __restrict__ ff_partials,
   s[kRr] = ff;
   s[kPq] = 0.0;
   s[kXPend] = 0.0;
+  s[kAlphaP] = 0.0;
+  s[kAlphaP + 1] = 0.0;
 }
 
 // grid (kReduceBlocks, nrhs), after q = A x: the partials of ||M f - q||^2
@@ -907,6 +909,7 @@ __device__ __forceinline__ void update_r_first_block(long long n, const double* 
     s[kPq] = pq;
     s[kAlpha] = alpha;
     s[kXPend] = ok ? 1.0 : 0.0;
+    s[kAlphaP + parity] = ok ? alpha : 0.0;
   }
   if (!ok || (repl && repl[rhs])) {  // breakdown: keep the previous iterate; the check flags it
     if (threadIdx.x == 0) rr_partials[bx] = 0.0;
@@ -1010,8 +1013,8 @@ template <typename TZ>
 __device__ __forceinline__ void update_px_block(long long n, const double* __restrict__ rz_partials, int nrz,
                                                 double* __restrict__ sc, const int* __restrict__ active,
                                                 const TZ* __restrict__ z, double* __restrict__ p,
-                                                double* __restrict__ x, int parity, float* __restrict__ p32, int bx,
-                                                int rhs) {
+                                                double* __restrict__ x, int parity, float* __restrict__ p32,
+                                                float* __restrict__ p32b, int bx, int rhs) {
   constexpr int gx = kReduceBlocks;
   if (!active[rhs]) return;
   double rzs = 0.0;
@@ -1028,14 +1031,32 @@ __device__ __forceinline__ void update_px_block(long long n, const double* __res
   z += off;
   x += off;
   if (p32) p32 += off;
-  if (!p) {  // the direction is held in binary32 only: x += alpha p, p = z + beta p rounded to binary32
-    for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
-      const long long e = min(b0 + kVecChunk, n);
+  if (!p) {
+    // The direction is held in binary32 only, p_k of iteration k in p32 (k odd)
+    // or p32b (k even); parity = (k - 1) & 1.  After an odd k: p_(k+1) = z +
+    // beta p_k into p32b.  After an even k: x += alpha_(k-1) p_(k-1) (p32), x +=
+    // alpha_k p_k (p32b), and p_(k+1) = z + beta p_k into p32, over p_(k-1).
+    p32b += off;
+    if (parity) {
+      const double a_odd = s[kAlphaP], a_even = s[kAlphaP + 1];
+      for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
+        const long long e = min(b0 + kVecChunk, n);
 #pragma unroll 4
-      for (long long i = b0 + threadIdx.x; i < e; i += kBlock) {
-        const double pi = (double)p32[i];
-        x[i] += alpha * pi;
-        p32[i] = (float)((double)z[i] + beta * pi);
+        for (long long i = b0 + threadIdx.x; i < e; i += kBlock) {
+          const double po = (double)p32[i], pe = (double)p32b[i];
+          double xi = x[i];
+          xi += a_odd * po;
+          xi += a_even * pe;
+          x[i] = xi;
+          p32[i] = (float)((double)z[i] + beta * pe);
+        }
+      }
+    } else {
+      for (long long b0 = (long long)bx * kVecChunk; b0 < n; b0 += (long long)gx * kVecChunk) {
+        const long long e = min(b0 + kVecChunk, n);
+#pragma unroll 4
+        for (long long i = b0 + threadIdx.x; i < e; i += kBlock)
+          p32b[i] = (float)((double)z[i] + beta * (double)p32[i]);
       }
     }
     return;
@@ -1065,15 +1086,15 @@ __device__ __forceinline__ void update_px_block(long long n, const double* __res
 template <typename TZ>
 __global__ void k_update_px(long long n, const double* __restrict__ rz_partials, int nrz, double* __restrict__ sc,
                             const int* __restrict__ active, const TZ* __restrict__ z, double* __restrict__ p,
-                            double* __restrict__ x, int parity, float* __restrict__ p32) {
-  update_px_block<TZ>(n, rz_partials, nrz, sc, active, z, p, x, parity, p32, blockIdx.x, blockIdx.y);
+                            double* __restrict__ x, int parity, float* __restrict__ p32, float* __restrict__ p32b) {
+  update_px_block<TZ>(n, rz_partials, nrz, sc, active, z, p, x, parity, p32, p32b, blockIdx.x, blockIdx.y);
 }
 template <typename TZ>
 __global__ void k_update_px_batch(Batch<UpdatePxTask<TZ>> tb) {
   const int t = batch_task(tb.begin, tb.n, (int)blockIdx.x);
   const UpdatePxTask<TZ>& a = tb.a[t];
   const int local = (int)blockIdx.x - tb.begin[t];
-  update_px_block<TZ>(a.n, a.rz_partials, a.nrz, a.sc, a.active, a.z, a.p, a.x, a.parity, a.p32,
+  update_px_block<TZ>(a.n, a.rz_partials, a.nrz, a.sc, a.active, a.z, a.p, a.x, a.parity, a.p32, a.p32b,
                       local % kReduceBlocks, local / kReduceBlocks);
 }
 
@@ -1157,6 +1178,40 @@ __global__ void k_flush_x(long long n, const double* __restrict__ sc, const TP* 
 #pragma unroll 4
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
     x[i] += alpha * (double)p[i];
+}
+// The same for the binary32 directions of the mixed form (launch_update_px):
+// after the last iteration k, p_k (p32 for odd k) is pending, and for even k
+// p_(k-1) (p32) before it; a breakdown left its alpha 0.
+__global__ void k_flush_x_pair(long long n, const double* __restrict__ sc, const float* __restrict__ p32,
+                               const float* __restrict__ p32b, double* __restrict__ x, const int* __restrict__ act) {
+  const int rhs = blockIdx.y;
+  const double* s = sc + kScalars * rhs;
+  const long long k = (long long)s[kIts];
+  if (k == 0 || (act && !act[rhs])) return;
+  const bool even = (k & 1) == 0;
+  const double a_odd = s[kAlphaP], a_even = s[kAlphaP + 1];
+  const long long off = n * rhs;
+  p32 += off;
+  p32b += off;
+  x += off;
+  if (even && a_even == 0.0) {  // breakdown in the last iteration: only p_(k-1) is due
+    if (a_odd == 0.0) return;
+#pragma unroll 4
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+      x[i] += a_odd * (double)p32[i];
+  } else if (even) {
+#pragma unroll 4
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+      double xi = x[i];
+      xi += a_odd * (double)p32[i];
+      xi += a_even * (double)p32b[i];
+      x[i] = xi;
+    }
+  } else if (a_odd != 0.0) {
+#pragma unroll 4
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+      x[i] += a_odd * (double)p32[i];
+  }
 }
 
 // partials of r . (double) u32 (grid (kReduceBlocks, nrhs)); the widened z is not stored
@@ -1388,18 +1443,20 @@ void launch_rr_check(const double* rr_partials, double* sc, int* active, double*
 }
 template <typename TZ>
 void launch_update_px(long long n, const double* rz_partials, int nrz, double* sc, const int* active, const TZ* z,
-                      double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32) {
+                      double* p, double* x, int parity, int nrhs, hipStream_t s, float* p32, float* p32b) {
   k_update_px<TZ><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, rz_partials, nrz, sc, active, z, p, x, parity,
-                                                                p32);
+                                                                p32, p32b);
 }
 template void launch_update_px<double>(long long, const double*, int, double*, const int*, const double*, double*,
-                                       double*, int, int, hipStream_t, float*);
+                                       double*, int, int, hipStream_t, float*, float*);
 template void launch_update_px<float>(long long, const double*, int, double*, const int*, const float*, double*,
-                                      double*, int, int, hipStream_t, float*);
+                                      double*, int, int, hipStream_t, float*, float*);
 void launch_flush_x(long long n, const double* sc, const double* p, double* x, int nrhs, hipStream_t s,
-                    const int* act, const float* p32) {
+                    const int* act, const float* p32, const float* p32b) {
   if (p)
     k_flush_x<double><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p, x, act);
+  else if (p32b)
+    k_flush_x_pair<<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p32, p32b, x, act);
   else
     k_flush_x<float><<<dim3(kReduceBlocks, nrhs), kBlock, 0, s>>>(n, sc, p32, x, act);
 }

@@ -553,3 +553,64 @@ def test_binary64_product_on_binary32_direction_every_shape(shape, zchunk):
         grid.solve(f, u, rtol=0.0, maxit=8)
         out.append(u.cpu().numpy())
     assert rel(out[0], out[1]) < 1e-9
+
+
+@pytest.mark.parametrize("iters", [1, 2, 3, 4, 7])
+def test_mixed_deferred_x_updates(iters):
+    """The mixed form brings x up to date after every even iteration only (two
+    binary32 directions, alternating buffers) and applies what is pending
+    when the solve stops: after any number of iterations, odd or even, the
+    binary64 residual of the returned x equals the recursive residual that
+    the iteration tracked (a direction applied twice or not at all would
+    leave them apart by the size of that step), on two right-hand sides in
+    lockstep."""
+    from paper_2201_12931_amd import hexmg
+
+    print(f"case mixed deferred x iters={iters}", flush=True)
+    _require_gpu()
+    dims, levels = (64, 16, 16), 3
+    g = W.Grid(*dims)
+    rho = W.random_field_density(g, seed=7, lo=0.01)
+    f1 = W.cantilever_line_load(g)
+    f2 = W.random_vector(g.n_dof, seed=8) * fem.free_dof_mask(W.fixed_mask_face_x0(g))
+    grid = hexmg.Grid(*dims, levels, precision=hexmg.MIXED, max_nrhs=2)
+    grid.set_density(gpu(rho))
+    f = torch.stack([gpu(f1), gpu(f2)])
+    u = torch.zeros_like(f)
+    code, info = grid.solve(f, u, rtol=0.0, maxit=iters)
+    for k in range(2):
+        assert info[k]["iterations"] == iters
+        rec, true = info[k]["rel_res_recursive"], info[k]["rel_res_true"]
+        assert abs(true - rec) <= 1e-8 * rec, (k, rec, true)
+
+
+def test_mixed_multi_rhs_equals_single():
+    """Lockstep right-hand sides of the mixed form, which stop at their own
+    iterations (odd or even, with one or two directions then pending), equal
+    single solves bit for bit."""
+    from paper_2201_12931_amd import hexmg
+
+    print("case mixed multi-rhs", flush=True)
+    dims, levels = (32, 16, 16), 3
+    _require_gpu()
+    g = W.Grid(*dims)
+    rho = gpu(W.random_field_density(g, seed=3, lo=0.01))
+    F = gpu(W.point_loads(g, 4, seed=31))
+    multi = hexmg.Grid(*dims, levels, precision=hexmg.MIXED, max_nrhs=4)
+    single = hexmg.Grid(*dims, levels, precision=hexmg.MIXED, max_nrhs=1)
+    for grid in (multi, single):
+        grid.set_density(rho)
+        for l in range(levels):
+            for dt in (hexmg.F32, hexmg.F64):
+                grid.set_kernel_choice(l, dt, hexmg.KERNEL_STREAM, 4, 0)
+        grid.set_coarse_cycle(hexmg.F32, 0)
+    U = torch.empty_like(F)
+    code, info = multi.solve(F, U, rtol=1e-9, maxit=200)
+    assert code == 0
+    for r in range(4):
+        u1 = torch.empty_like(F[r])
+        c1, i1 = single.solve(F[r].contiguous(), u1, rtol=1e-9, maxit=200)
+        assert i1[0]["iterations"] == info[r]["iterations"], r
+        assert torch.equal(u1, U[r]), r
+        assert info[r]["rel_res_true"] <= 1e-9
+    print("iterations", [info[r]["iterations"] for r in range(4)], flush=True)
